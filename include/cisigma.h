@@ -1,0 +1,224 @@
+/*
+ * cisigma.h -- C ABI of the MI355X determinant-CI sigma builder and Davidson
+ * eigensolver.
+ *
+ * The library computes the direct-CI sigma vector sigma = H C of Vogiatzis et
+ * al., arXiv:1707.04346 (Sec. 2.1, Eqs. 4-8), over alpha/beta occupation
+ * strings (Eq. 2) of a CAS or GAS space (Sec. 3.1), and the lowest
+ * eigenpairs of H by the Davidson method the sigma vector serves (Sec. 2.1 and
+ * Sec. 3.3).  All numerical work runs in HIP kernels on one GPU; host memory
+ * is touched only to take in the integrals and to hand back energies.
+ *
+ * Hamiltonian (Eq. 6, with the spin-summed excitation operators of Eq. 7):
+ *     H = sum_kl h_kl E_kl + 1/2 sum_ijkl (ij|kl) (E_ij E_kl - delta_jk E_il)
+ * real orbitals, chemists' notation (ij|kl).
+ *
+ * Determinant space and order (a contract of this library; the paper fixes no
+ * order):
+ *   - norb spatial orbitals numbered 0..norb-1; GAS space g holds the next
+ *     gas->norb[g] orbitals after space g-1.
+ *   - a string is a bitmask of occupied orbitals (bit p = orbital p); its
+ *     occupation type is the tuple of electron counts per GAS space (Sec. 3.1,
+ *     Eq. 9: the T of a TS string).
+ *   - the space holds every (alpha string, beta string) with nalpha and nbeta
+ *     electrons such that, for every g, the total (alpha + beta) count in
+ *     spaces 0..g lies in [gas->min_cum[g], gas->max_cum[g]].
+ *   - occupation types of one spin are ordered lexicographically by their
+ *     tuples; only types that pair with at least one type of the other spin
+ *     are kept.  Strings of a type are ordered by ascending bitmask.  The
+ *     string index of a spin runs over types in that order.
+ *   - the vector is a sequence of blocks (alpha type, beta type) -- the TTSS
+ *     blocks of Sec. 3.1 without the spatial-symmetry label -- in
+ *     alpha-type-major order, each block row-major [I_alpha][I_beta].  A CAS
+ *     is one block of N_alpha x N_beta elements.
+ *   - determinant |alpha(I_a) beta(I_b)> = a^+_{p1 a} ... a^+_{pk a} a^+_{q1 b}
+ *     ... |vac> with p1 < p2 < ..., alpha operators to the left (Eq. 2).
+ *
+ * Memory and streams: every vector argument named "device" is a pointer to
+ * GPU memory owned by the caller (for example a torch tensor's data_ptr()).
+ * Streams are hipStream_t passed as void*; NULL means the default (null)
+ * stream.  Host arrays are read during the call and may be freed afterwards.
+ *
+ * Errors: every call returns CISIGMA_OK (0) or a negative status; no C++
+ * exception crosses this boundary.  cisigma_last_error() returns a message
+ * for the most recent failure on a context.  A context is not thread-safe;
+ * use one per host thread.
+ */
+#ifndef CISIGMA_H
+#define CISIGMA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define CISIGMA_OK 0
+#define CISIGMA_EINVAL (-1)   /* bad argument: sizes, NULL, NaN, asymmetric integrals, aliasing, empty space */
+#define CISIGMA_ENOMEM (-2)   /* device (or host) allocation failed */
+#define CISIGMA_EDEVICE (-3)  /* a HIP call failed; the message is kept */
+#define CISIGMA_ENOCONV (-4)  /* Davidson reached max_iter; energies are still written */
+#define CISIGMA_EUNSUPPORTED (-5) /* valid request outside what this build implements */
+
+/* element types of CI vectors */
+#define CISIGMA_FP64 0
+#define CISIGMA_FP32 1
+
+/* option keys for cisigma_set_option */
+#define CISIGMA_OPT_PRECISION 1    /* Davidson vectors and sigma: CISIGMA_FP64 (plain) or CISIGMA_FP32 (mixed) */
+#define CISIGMA_OPT_MAX_SPACE 2    /* Davidson subspace size before collapse (>= 2*nroots); default 8*nroots, min 16 */
+#define CISIGMA_OPT_MAX_ITER 3     /* Davidson iteration limit; default 100 */
+#define CISIGMA_OPT_REFINE_EVERY 4 /* mixed mode: rebuild the FP64 sigma of the basis every R iterations; default 8 */
+#define CISIGMA_OPT_RESID_TOL 5    /* residual-norm threshold; default sqrt(tol) (mixed: max(sqrt(tol), 1e-5)) */
+#define CISIGMA_OPT_VERBOSE 6      /* print one line per Davidson iteration to stderr when nonzero */
+#define CISIGMA_OPT_PROFILE 7      /* nonzero: time every pass of cisigma_apply with HIP events (resets the totals) */
+
+/* passes of one cisigma_apply, in order, as reported by cisigma_pass_times */
+#define CISIGMA_PASS_LAYOUT_IN 0   /* C -> padded alpha-major and beta-major copies */
+#define CISIGMA_PASS_CLEAR 1       /* clear the two accumulators */
+#define CISIGMA_PASS_SIGMA_AB 2    /* sigma_3: alpha-beta part (Eq. 8) */
+#define CISIGMA_PASS_SIGMA_AA 3    /* sigma_2: alpha-alpha part */
+#define CISIGMA_PASS_SIGMA_BB 4    /* sigma_1: beta-beta part */
+#define CISIGMA_PASS_LAYOUT_OUT 5  /* accumulators -> sigma */
+#define CISIGMA_NPASS 6
+
+/* GAS definition (Sec. 3.1).  Cumulative bounds are on total (alpha+beta)
+ * electrons.  Pass NULL to cisigma_init for a CAS. */
+typedef struct cisigma_gas {
+    int ngas;             /* 1..16 */
+    const int *norb;      /* [ngas] orbitals per space, summing to norb */
+    const int *min_cum;   /* [ngas] */
+    const int *max_cum;   /* [ngas] */
+} cisigma_gas;
+
+typedef struct cisigma_stats {
+    int iterations;       /* Davidson iterations performed */
+    int sigma_fp32;       /* sigma builds in FP32 */
+    int sigma_fp64;       /* sigma builds in FP64 */
+    int refinements;      /* FP64 refinement points (mixed mode) */
+    double residual;      /* final max residual norm (from an FP64 sigma) */
+    double seconds;       /* wall time of the call */
+} cisigma_stats;
+
+typedef struct cisigma_ctx cisigma_ctx;
+
+/*
+ * cisigma_init -- build a context for (norb, nalpha, nbeta, GAS) and integrals.
+ *   ctx    out: new context (NULL on failure).
+ *   norb   1..32 orbitals; 0 <= nalpha, nbeta <= norb.
+ *   gas    NULL for a CAS (one space holding all electrons), else Sec. 3.1 GAS.
+ *   h1e    host FP64 [norb*norb], row-major, symmetric (|h_pq - h_qp| <= 1e-12 max|h|).
+ *   eri    host FP64 [norb^4], eri[((i*n+j)*n+k)*n+l] = (ij|kl), 8-fold symmetric.
+ * Both integral arrays are copied; the caller keeps ownership.  Builds the
+ * string, excitation-list and integral tables on the current HIP device
+ * (synchronous).  Returns EINVAL for bad sizes, NaN or asymmetric integrals
+ * or an empty space; ENOMEM when device memory runs out; EDEVICE on a HIP
+ * failure.
+ */
+int cisigma_init(cisigma_ctx **ctx, int norb, int nalpha, int nbeta, const cisigma_gas *gas,
+                 const double *h1e, const double *eri);
+
+/* release all device memory of the context; NULL is ignored */
+void cisigma_free(cisigma_ctx *ctx);
+
+/* number of determinants (vector length), or -1 for a NULL context */
+int64_t cisigma_ndet(const cisigma_ctx *ctx);
+
+/*
+ * cisigma_layout -- the block table of the vector order above.
+ *   nblocks    out: number of (alpha type, beta type) blocks.
+ *   The array arguments may be NULL (then only nblocks is written); otherwise
+ *   they need room for *nblocks (block_offset: *nblocks + 1) entries:
+ *   block_offset[b] first element of block b (block_offset[nblocks] = ndet),
+ *   alpha_type/beta_type type indices, nalpha_str/nbeta_str strings per type
+ *   of the block's alpha and beta type.
+ */
+int cisigma_layout(const cisigma_ctx *ctx, int *nblocks, int64_t *block_offset, int *alpha_type,
+                   int *beta_type, int *nalpha_str, int *nbeta_str);
+
+/*
+ * cisigma_address -- position of determinant (alpha bits, beta bits) in the
+ * vector; *index = -1 when it is not in the space.  Host-side, no device work.
+ */
+int cisigma_address(const cisigma_ctx *ctx, uint32_t alpha_bits, uint32_t beta_bits, int64_t *index);
+
+/*
+ * cisigma_strings -- copy the device string table of one spin (0 alpha,
+ * 1 beta) to the host: out[nstr] bitmasks in string-index order.  *nstr is
+ * written; out may be NULL to query the size only.
+ */
+int cisigma_strings(const cisigma_ctx *ctx, int spin, uint32_t *out, int *nstr);
+
+/*
+ * cisigma_excitations -- copy the device single-excitation list of one spin
+ * to the host (the E_kl connection lists of Sec. 3.1 / Sec. 3.3).  For string
+ * I and each occupied k (ascending) and empty l (ascending), the entry at
+ * [I][ko*nvirt + lv] describes J = I - k + l:
+ *     bits 31..11  index of J (all ones = J is not a string of the space)
+ *     bits 10..6   k,  bits 5..1  l,  bit 0  1 when <J|a^+_l a_k|I> = -1
+ * (the whole word is 0xFFFFFFFF when J is not in the space).
+ * out may be NULL; *per_string = nelec*(norb-nelec) and *nstr are written.
+ */
+int cisigma_excitations(const cisigma_ctx *ctx, int spin, uint32_t *out, int *per_string, int *nstr);
+
+/* option setter; EINVAL for an unknown key or out-of-range value */
+int cisigma_set_option(cisigma_ctx *ctx, int key, double value);
+
+/*
+ * cisigma_apply -- sigma = H C (Eq. 5) for one vector.
+ *   C, sigma   device arrays of ndet elements of dtype (CISIGMA_FP64 or
+ *              CISIGMA_FP32), caller-owned, contiguous, in the vector order
+ *              above.  They must not overlap (EINVAL).  sigma is overwritten.
+ *   stream     hipStream_t or NULL.  The call only enqueues work: it returns
+ *              before the result is ready; synchronise the stream to read it.
+ * FP32 computes in FP32 (MFMA with FP32 accumulation); FP64 in FP64.
+ * The first call for a dtype allocates that dtype's workspace (synchronous).
+ */
+int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream);
+
+/*
+ * cisigma_hdiag -- diagonal H_II into the device array hdiag[ndet] (FP64),
+ * asynchronously on stream.
+ */
+int cisigma_hdiag(cisigma_ctx *ctx, double *hdiag, void *stream);
+
+/*
+ * cisigma_davidson -- lowest nroots eigenpairs of H (Sec. 3.3).
+ *   nroots     1..64 (and <= ndet).
+ *   tol        energy convergence threshold |delta E| between iterations.
+ *   energies   host double[nroots], ascending.
+ *   vecs       NULL, or caller-owned device array [nroots][ndet] of FP64
+ *              (plain mode) or FP32 (mixed mode) receiving the eigenvectors.
+ *   stats      NULL or statistics out.
+ * Synchronous; runs on the context's own stream.  Returns ENOCONV when
+ * max_iter is reached (energies and vectors are the last Ritz values).
+ * In mixed mode (CISIGMA_OPT_PRECISION = CISIGMA_FP32) basis vectors and
+ * sigma builds are FP32 while the projected matrix, orthogonalisation and
+ * residual norms accumulate in FP64, the basis sigma is rebuilt in FP64 every
+ * REFINE_EVERY iterations, and the returned energies are FP64 Rayleigh
+ * quotients <x|H x>/<x|x> with an FP64 sigma.
+ */
+int cisigma_davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs,
+                     cisigma_stats *stats);
+
+/*
+ * cisigma_pass_times -- with CISIGMA_OPT_PROFILE set, every cisigma_apply
+ * records a HIP event pair around each pass on the stream it runs on.  This
+ * call synchronises those events and writes the summed milliseconds of each
+ * pass since profiling was (re)enabled into ms[CISIGMA_NPASS] and the number
+ * of profiled apply calls into *ncalls.  EINVAL when profiling is off.
+ */
+int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls);
+
+/* message of the most recent failure on ctx (never NULL) */
+const char *cisigma_last_error(const cisigma_ctx *ctx);
+
+/* static description of a status code (never NULL) */
+const char *cisigma_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CISIGMA_H */

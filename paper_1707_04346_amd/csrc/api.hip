@@ -1,0 +1,630 @@
+// api.hip -- the extern "C" boundary declared in include/cisigma.h.
+//
+// cisigma_init builds, in order: the GAS occupation types of each spin and the
+// allowed (alpha type, beta type) blocks (Sec. 3.1), the padded alpha-major and
+// beta-major work layouts, the device string / excitation / pair tables
+// (tables.hip), and the integral tables the sigma kernels read: (ij|kl) with
+// the kl index packed to pairs k >= l (alpha-beta part), and for each spin the
+// pair matrix V of the same-spin part (sigma_ss.hip).
+// cisigma_apply enqueues: C -> padded copies, sigma_3, sigma_2, sigma_1,
+// padded accumulators -> sigma (Eq. 8: sigma = sigma_1 + sigma_2 + sigma_3).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+#define CIS_API extern "C" __attribute__((visibility("default")))
+
+int cis_set_error(cisigma_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+namespace {
+
+const char *status_text(int s) {
+    switch (s) {
+        case CISIGMA_OK: return "ok";
+        case CISIGMA_EINVAL: return "invalid argument";
+        case CISIGMA_ENOMEM: return "out of memory";
+        case CISIGMA_EDEVICE: return "HIP device error";
+        case CISIGMA_ENOCONV: return "Davidson did not converge within max_iter";
+        case CISIGMA_EUNSUPPORTED: return "request outside what this build implements";
+        default: return "unknown status";
+    }
+}
+
+int hip_fail(cisigma_ctx *ctx, hipError_t e, const char *where) {
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return cis_set_error(ctx, CISIGMA_ENOMEM, std::string(where) + ": device out of memory");
+    return cis_set_error(ctx, CISIGMA_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_OR_FAIL(ctx, x, where)                     \
+    do {                                               \
+        hipError_t e_ = (x);                           \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+    } while (0)
+
+uint64_t binom(int m, int k) {
+    if (k < 0 || k > m) return 0;
+    uint64_t c = 1;
+    for (int i = 0; i < k; ++i) c = c * uint64_t(m - i) / uint64_t(i + 1);
+    return c;
+}
+
+// all occupation tuples of `nel` electrons over the GAS spaces
+void enum_tuples(const std::vector<int> &gn, int nel, int g, std::vector<int> &cur, std::vector<std::vector<int>> &out) {
+    if (g == int(gn.size())) {
+        if (nel == 0) out.push_back(cur);
+        return;
+    }
+    for (int k = 0; k <= std::min(nel, gn[g]); ++k) {
+        cur[g] = k;
+        enum_tuples(gn, nel - k, g + 1, cur, out);
+    }
+}
+
+bool pair_allowed(const cisigma_ctx *c, const int *ta, const int *tb) {
+    int cum = 0;
+    for (size_t g = 0; g < c->gas_norb.size(); ++g) {
+        cum += ta[g] + tb[g];
+        if (cum < c->gas_min[g] || cum > c->gas_max[g]) return false;
+    }
+    return true;
+}
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+    size_t n = src.size() > 0 ? src.size() : 1;
+    hipError_t e = hipMalloc(dst, n * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+void free_ctx(cisigma_ctx *c) {
+    if (!c) return;
+    for (int s = 0; s < 2; ++s) {
+        auto &T = c->sp[s];
+        hipFree(T.d_str); hipFree(T.d_stype); hipFree(T.d_exc); hipFree(T.d_pairs);
+        hipFree(T.d_tkey); hipFree(T.d_tstart); hipFree(T.d_radix); hipFree(T.d_adiag);
+        auto &L = c->pl[s];
+        hipFree(L.d_seg); hipFree(L.d_ld); hipFree(L.d_tile_u); hipFree(L.d_tile_c0);
+        hipFree(c->d_tstart[s]);
+        hipFree(c->d_v64[s]); hipFree(c->d_v32[s]);
+        auto &W = c->ws[s];
+        hipFree(W.cp); hipFree(W.sp); hipFree(W.ct); hipFree(W.st);
+    }
+    hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
+    hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
+    for (auto e : c->prof_events) hipEventDestroy(e);
+    if (c->stream) hipStreamDestroy(c->stream);
+    delete c;
+}
+
+// host-side string index (same contract as the device tables)
+int64_t host_string_index(const cisigma_ctx *c, int spin, uint32_t x) {
+    const auto &T = c->sp[spin];
+    const int G = c->gas.ngas;
+    if (__builtin_popcount(x) != T.nel) return -1;
+    if (c->n < 32 && (x >> c->n)) return -1;
+    uint64_t key = 0;
+    for (int g = 0; g < G; ++g) key += uint64_t(__builtin_popcount(x & c->gas.mask[g])) * c->gas.keymul[g];
+    auto it = std::lower_bound(T.tkey.begin(), T.tkey.end(), key);
+    if (it == T.tkey.end() || *it != key) return -1;
+    int t = int(it - T.tkey.begin());
+    uint64_t rank = 0, radix = 1;
+    for (int g = 0; g < G; ++g) {
+        uint32_t sub = (x & c->gas.mask[g]) >> c->gas.first[g];
+        uint64_t r = 0;
+        int i = 1;
+        while (sub) {
+            int p = __builtin_ctz(sub);
+            r += binom(p, i);
+            ++i;
+            sub &= sub - 1;
+        }
+        rank += r * radix;
+        radix *= binom(__builtin_popcount(c->gas.mask[g]), T.tocc[size_t(t) * G + g]);
+    }
+    return T.tstart[t] + int64_t(rank);
+}
+
+int build_integrals(cisigma_ctx *c) {
+    const int n = c->n;
+    const size_t n2 = size_t(n) * n;
+    c->npair = n * (n + 1) / 2;
+    c->nps = n * (n - 1) / 2;
+    c->kp = cis::sigma_ab_kp(c->npair);
+    const double *g = c->g.data();
+    auto G = [&](int p, int q, int r, int s) { return g[((size_t(p) * n + q) * n + r) * n + s]; };
+    // (ij|kl), kl packed k >= l, zero padded to kp
+    std::vector<double> gp(n2 * c->kp, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k)
+                for (int l = 0; l <= k; ++l) gp[(size_t(i) * n + j) * c->kp + cis::pair_ge(k, l)] = G(i, j, k, l);
+    std::vector<float> gp32(gp.begin(), gp.end());
+    HIP_OR_FAIL(c, upload(&c->d_gp64, gp), "init: integral upload");
+    HIP_OR_FAIL(c, upload(&c->d_gp32, gp32), "init: integral upload");
+    std::vector<float> h32(c->h.begin(), c->h.end());
+    HIP_OR_FAIL(c, upload(&c->d_h64, c->h), "init: integral upload");
+    HIP_OR_FAIL(c, upload(&c->d_h32, h32), "init: integral upload");
+    std::vector<double> jpq(n2);
+    for (int p = 0; p < n; ++p)
+        for (int q = 0; q < n; ++q) jpq[size_t(p) * n + q] = G(p, p, q, q);
+    HIP_OR_FAIL(c, upload(&c->d_jpq, jpq), "init: integral upload");
+    // same-spin pair matrices (absorbing h / (N-1))
+    for (int s = 0; s < 2; ++s) {
+        int N = c->sp[s].nel;
+        if (N < 2 || c->nps == 0) continue;
+        const double f = 1.0 / double(N - 1);
+        auto Tm = [&](int p, int q, int r, int t) {
+            double v = G(p, q, r, t);
+            if (r == t) v += f * c->h[size_t(p) * n + q];
+            if (p == q) v += f * c->h[size_t(r) * n + t];
+            return v;
+        };
+        std::vector<double> V(size_t(c->nps) * c->nps);
+        for (int r = 1; r < n; ++r)
+            for (int p = 0; p < r; ++p) {          // creator pair (p < r)
+                int P = cis::pair_gt(r, p);
+                for (int t = 1; t < n; ++t)
+                    for (int q = 0; q < t; ++q) {  // annihilator pair (q < t)
+                        int Q = cis::pair_gt(t, q);
+                        V[size_t(P) * c->nps + Q] = Tm(p, q, r, t) - Tm(p, t, r, q);
+                    }
+            }
+        std::vector<float> V32(V.begin(), V.end());
+        HIP_OR_FAIL(c, upload(&c->d_v64[s], V), "init: pair matrix upload");
+        HIP_OR_FAIL(c, upload(&c->d_v32[s], V32), "init: pair matrix upload");
+    }
+    return CISIGMA_OK;
+}
+
+int build_layouts(cisigma_ctx *c) {
+    auto &A = c->sp[0], &B = c->sp[1];
+    for (int rs = 0; rs < 2; ++rs) {
+        auto &L = c->pl[rs];
+        const auto &R = c->sp[rs], &O = c->sp[1 - rs];
+        L.rs = rs;
+        L.ld.assign(O.ntype, 0);
+        for (int u = 0; u < O.ntype; ++u) L.ld[u] = (O.tcount[u] + cis::kTileCols - 1) / cis::kTileCols * cis::kTileCols;
+        L.seg.assign(size_t(R.ntype) * O.ntype, -1);
+        int64_t off = 0;
+        for (int t = 0; t < R.ntype; ++t)
+            for (int u = 0; u < O.ntype; ++u) {
+                int64_t b = rs == 0 ? c->lay.boff[size_t(t) * B.ntype + u] : c->lay.boff[size_t(u) * B.ntype + t];
+                if (b < 0) continue;
+                L.seg[size_t(t) * O.ntype + u] = off;
+                off += int64_t(R.tcount[t]) * L.ld[u];
+            }
+        L.size = off;
+        L.tile_u.clear();
+        L.tile_c0.clear();
+        for (int u = 0; u < O.ntype; ++u)
+            for (int c0 = 0; c0 < L.ld[u]; c0 += cis::kTileCols) {
+                L.tile_u.push_back(u);
+                L.tile_c0.push_back(c0);
+            }
+        L.ntiles = int(L.tile_u.size());
+        HIP_OR_FAIL(c, upload(&L.d_seg, L.seg), "init: layout upload");
+        HIP_OR_FAIL(c, upload(&L.d_ld, L.ld), "init: layout upload");
+        HIP_OR_FAIL(c, upload(&L.d_tile_u, L.tile_u), "init: layout upload");
+        HIP_OR_FAIL(c, upload(&L.d_tile_c0, L.tile_c0), "init: layout upload");
+        HIP_OR_FAIL(c, upload(&c->d_tstart[rs], c->sp[rs].tstart), "init: layout upload");
+    }
+    // conversion tiles over the caller-layout blocks
+    std::vector<cis::BlockDev> blk(c->lay.nblk);
+    std::vector<int> tb, tr, tc;
+    for (int b = 0; b < c->lay.nblk; ++b) {
+        int ta = c->lay.blk_a[b], tbb = c->lay.blk_b[b];
+        cis::BlockDev d{};
+        d.ta = ta; d.tb = tbb; d.na = A.tcount[ta]; d.nb = B.tcount[tbb];
+        d.off = c->lay.blk_off[b];
+        d.sega = c->pl[0].seg[size_t(ta) * B.ntype + tbb];
+        d.segb = c->pl[1].seg[size_t(tbb) * A.ntype + ta];
+        d.lda = c->pl[0].ld[tbb];
+        d.ldb = c->pl[1].ld[ta];
+        blk[b] = d;
+        for (int r0 = 0; r0 < d.na; r0 += 64)
+            for (int c0 = 0; c0 < d.nb; c0 += 64) {
+                tb.push_back(b); tr.push_back(r0); tc.push_back(c0);
+            }
+    }
+    c->bt.ntiles = int(tb.size());
+    HIP_OR_FAIL(c, upload(&c->bt.blk, blk), "init: block upload");
+    HIP_OR_FAIL(c, upload(&c->bt.tb, tb), "init: block upload");
+    HIP_OR_FAIL(c, upload(&c->bt.tr, tr), "init: block upload");
+    HIP_OR_FAIL(c, upload(&c->bt.tc, tc), "init: block upload");
+    return CISIGMA_OK;
+}
+
+int ensure_workspace(cisigma_ctx *c, int dtype) {
+    auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
+    if (W.ready) return CISIGMA_OK;
+    size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
+    size_t na = size_t(std::max<int64_t>(c->pl[0].size, 1)) * es;
+    size_t nb = size_t(std::max<int64_t>(c->pl[1].size, 1)) * es;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2 * (na + nb) + (64u << 20) > fr)
+        return cis_set_error(c, CISIGMA_ENOMEM, "apply: not enough device memory for the sigma workspace");
+    HIP_OR_FAIL(c, hipMalloc(&W.cp, na), "apply: workspace");
+    HIP_OR_FAIL(c, hipMalloc(&W.sp, na), "apply: workspace");
+    HIP_OR_FAIL(c, hipMalloc(&W.ct, nb), "apply: workspace");
+    HIP_OR_FAIL(c, hipMalloc(&W.st, nb), "apply: workspace");
+    // padding columns of the C copies stay zero for good
+    HIP_OR_FAIL(c, hipMemset(W.cp, 0, na), "apply: workspace");
+    HIP_OR_FAIL(c, hipMemset(W.ct, 0, nb), "apply: workspace");
+    HIP_OR_FAIL(c, hipDeviceSynchronize(), "apply: workspace");
+    W.ready = true;
+    return CISIGMA_OK;
+}
+
+}  // namespace
+
+namespace cis {
+
+int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s) {
+    int rc = ensure_workspace(c, dtype);
+    if (rc) return rc;
+    auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
+    hipEvent_t ev[CISIGMA_NPASS + 1];
+    const bool prof = c->profile;
+    if (prof) {
+        for (auto &e : ev) HIP_OR_FAIL(c, hipEventCreate(&e), "apply: profiling events");
+        HIP_OR_FAIL(c, hipEventRecord(ev[0], s), "apply: profiling events");
+    }
+    auto mark = [&](int pass) -> hipError_t { return prof ? hipEventRecord(ev[pass + 1], s) : hipSuccess; };
+    HIP_OR_FAIL(c, launch_scatter_in(c, C, W.cp, W.ct, dtype, s), "apply: layout conversion");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_LAYOUT_IN), "apply: profiling events");
+    HIP_OR_FAIL(c, launch_fill(W.sp, c->pl[0].size, dtype, s), "apply: fill");
+    HIP_OR_FAIL(c, launch_fill(W.st, c->pl[1].size, dtype, s), "apply: fill");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_CLEAR), "apply: profiling events");
+    HIP_OR_FAIL(c, launch_sigma_ab(c, W.cp, W.sp, dtype, s), "apply: sigma_3 (alpha-beta)");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AB), "apply: profiling events");
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, W.sp, dtype, s), "apply: sigma_2 (alpha-alpha)");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AA), "apply: profiling events");
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s), "apply: sigma_1 (beta-beta)");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_BB), "apply: profiling events");
+    HIP_OR_FAIL(c, launch_gather_out(c, W.sp, W.st, sigma, dtype, s), "apply: layout conversion");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_LAYOUT_OUT), "apply: profiling events");
+    if (prof) {
+        for (auto e : ev) c->prof_events.push_back(e);
+        c->prof_pending.push_back(1);
+    }
+    return CISIGMA_OK;
+}
+
+}  // namespace cis
+
+static void prof_reset(cisigma_ctx *c) {
+    for (auto e : c->prof_events) hipEventDestroy(e);
+    c->prof_events.clear();
+    c->prof_pending.clear();
+    for (double &v : c->prof_ms) v = 0;
+    c->prof_calls = 0;
+}
+
+CIS_API int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls) {
+    if (!ctx || !ms || !ncalls) return CISIGMA_EINVAL;
+    if (!ctx->profile) return cis_set_error(ctx, CISIGMA_EINVAL, "pass_times: profiling is off");
+    const size_t per = CISIGMA_NPASS + 1;
+    for (size_t k = 0; k < ctx->prof_pending.size(); ++k) {
+        hipEvent_t *ev = &ctx->prof_events[k * per];
+        HIP_OR_FAIL(ctx, hipEventSynchronize(ev[per - 1]), "pass_times");
+        for (int p = 0; p < CISIGMA_NPASS; ++p) {
+            float t = 0;
+            HIP_OR_FAIL(ctx, hipEventElapsedTime(&t, ev[p], ev[p + 1]), "pass_times");
+            ctx->prof_ms[p] += t;
+        }
+        ctx->prof_calls += 1;
+    }
+    for (auto e : ctx->prof_events) hipEventDestroy(e);
+    ctx->prof_events.clear();
+    ctx->prof_pending.clear();
+    for (int p = 0; p < CISIGMA_NPASS; ++p) ms[p] = ctx->prof_ms[p];
+    *ncalls = ctx->prof_calls;
+    return CISIGMA_OK;
+}
+
+CIS_API const char *cisigma_strerror(int status) { return status_text(status); }
+
+CIS_API const char *cisigma_last_error(const cisigma_ctx *ctx) {
+    if (!ctx) return "NULL context";
+    return ctx->err.c_str();
+}
+
+CIS_API void cisigma_free(cisigma_ctx *ctx) { free_ctx(ctx); }
+
+CIS_API int64_t cisigma_ndet(const cisigma_ctx *ctx) { return ctx ? ctx->lay.ndet : -1; }
+
+CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, const cisigma_gas *gas,
+                         const double *h1e, const double *eri) {
+    if (!out) return CISIGMA_EINVAL;
+    *out = nullptr;
+    if (norb < 1 || norb > 32 || nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb || !h1e || !eri)
+        return CISIGMA_EINVAL;
+    cisigma_ctx *c = new (std::nothrow) cisigma_ctx();
+    if (!c) return CISIGMA_ENOMEM;
+    c->n = norb; c->na = nalpha; c->nb = nbeta;
+    // GAS
+    if (gas) {
+        if (gas->ngas < 1 || gas->ngas > cis::kMaxGas || !gas->norb || !gas->min_cum || !gas->max_cum) {
+            free_ctx(c);
+            return CISIGMA_EINVAL;
+        }
+        int tot = 0;
+        for (int g = 0; g < gas->ngas; ++g) {
+            if (gas->norb[g] < 0) { free_ctx(c); return CISIGMA_EINVAL; }
+            tot += gas->norb[g];
+            c->gas_norb.push_back(gas->norb[g]);
+            c->gas_min.push_back(gas->min_cum[g]);
+            c->gas_max.push_back(gas->max_cum[g]);
+        }
+        if (tot != norb) { free_ctx(c); return CISIGMA_EINVAL; }
+    } else {
+        c->gas_norb = {norb};
+        c->gas_min = {nalpha + nbeta};
+        c->gas_max = {nalpha + nbeta};
+    }
+    const int G = int(c->gas_norb.size());
+    c->gas.n = norb;
+    c->gas.ngas = G;
+    {
+        int first = 0;
+        for (int g = 0; g < G; ++g) {
+            c->gas.first[g] = first;
+            uint32_t m = 0;
+            for (int k = 0; k < c->gas_norb[g]; ++k) m |= 1u << (first + k);
+            c->gas.mask[g] = m;
+            first += c->gas_norb[g];
+        }
+        uint64_t mul = 1;
+        for (int g = G - 1; g >= 0; --g) {
+            c->gas.keymul[g] = mul;
+            mul *= uint64_t(c->gas_norb[g] + 1);
+        }
+    }
+    // integrals: finite and symmetric
+    const size_t n2 = size_t(norb) * norb;
+    c->h.assign(h1e, h1e + n2);
+    c->g.assign(eri, eri + n2 * n2);
+    double hmax = 0, gmax = 0;
+    for (double v : c->h) { if (!std::isfinite(v)) { free_ctx(c); return CISIGMA_EINVAL; } hmax = std::max(hmax, std::fabs(v)); }
+    for (double v : c->g) { if (!std::isfinite(v)) { free_ctx(c); return CISIGMA_EINVAL; } gmax = std::max(gmax, std::fabs(v)); }
+    const double th = 1e-12 * std::max(hmax, 1.0), tg = 1e-12 * std::max(gmax, 1.0);
+    for (int p = 0; p < norb; ++p)
+        for (int q = 0; q < norb; ++q)
+            if (std::fabs(c->h[size_t(p) * norb + q] - c->h[size_t(q) * norb + p]) > th) {
+                cis_set_error(c, CISIGMA_EINVAL, "init: h1e is not symmetric");
+                free_ctx(c);
+                return CISIGMA_EINVAL;
+            }
+    auto G4 = [&](int p, int q, int r, int s) { return c->g[((size_t(p) * norb + q) * norb + r) * norb + s]; };
+    for (int p = 0; p < norb; ++p)
+        for (int q = 0; q < norb; ++q)
+            for (int r = 0; r < norb; ++r)
+                for (int s = 0; s < norb; ++s) {
+                    double v = G4(p, q, r, s);
+                    if (std::fabs(v - G4(q, p, r, s)) > tg || std::fabs(v - G4(p, q, s, r)) > tg ||
+                        std::fabs(v - G4(r, s, p, q)) > tg) {
+                        free_ctx(c);
+                        return CISIGMA_EINVAL;
+                    }
+                }
+    // occupation types per spin, kept when they pair with a type of the other spin
+    std::vector<std::vector<int>> tup[2];
+    for (int s = 0; s < 2; ++s) {
+        std::vector<int> cur(G, 0);
+        enum_tuples(c->gas_norb, s == 0 ? nalpha : nbeta, 0, cur, tup[s]);
+        std::sort(tup[s].begin(), tup[s].end());
+    }
+    std::vector<char> keep[2] = {std::vector<char>(tup[0].size(), 0), std::vector<char>(tup[1].size(), 0)};
+    for (size_t a = 0; a < tup[0].size(); ++a)
+        for (size_t b = 0; b < tup[1].size(); ++b)
+            if (pair_allowed(c, tup[0][a].data(), tup[1][b].data())) keep[0][a] = keep[1][b] = 1;
+    for (int s = 0; s < 2; ++s) {
+        auto &T = c->sp[s];
+        T.nel = s == 0 ? nalpha : nbeta;
+        T.tstart.assign(1, 0);
+        for (size_t i = 0; i < tup[s].size(); ++i) {
+            if (!keep[s][i]) continue;
+            uint64_t cnt = 1, key = 0;
+            for (int g = 0; g < G; ++g) {
+                cnt *= binom(c->gas_norb[g], tup[s][i][g]);
+                key += uint64_t(tup[s][i][g]) * c->gas.keymul[g];
+            }
+            for (int g = 0; g < G; ++g) T.tocc.push_back(tup[s][i][g]);
+            T.tcount.push_back(int(cnt));
+            T.tkey.push_back(key);
+            if (T.tstart.back() + cnt > (1u << 21) - 1) {
+                cis_set_error(c, CISIGMA_EUNSUPPORTED, "init: more than 2^21-1 strings of one spin");
+                free_ctx(c);
+                return CISIGMA_EUNSUPPORTED;
+            }
+            T.tstart.push_back(T.tstart.back() + int(cnt));
+        }
+        T.ntype = int(T.tcount.size());
+        T.nstr = T.tstart.back();
+    }
+    // blocks in alpha-type-major order
+    {
+        auto &L = c->lay;
+        const auto &A = c->sp[0], &B = c->sp[1];
+        L.boff.assign(size_t(A.ntype) * B.ntype, -1);
+        int64_t off = 0;
+        for (int a = 0; a < A.ntype; ++a)
+            for (int b = 0; b < B.ntype; ++b)
+                if (pair_allowed(c, &A.tocc[size_t(a) * G], &B.tocc[size_t(b) * G])) {
+                    L.boff[size_t(a) * B.ntype + b] = off;
+                    L.blk_a.push_back(a);
+                    L.blk_b.push_back(b);
+                    L.blk_off.push_back(off);
+                    off += int64_t(A.tcount[a]) * B.tcount[b];
+                }
+        L.blk_off.push_back(off);
+        L.nblk = int(L.blk_a.size());
+        L.ndet = off;
+        if (off == 0) {
+            free_ctx(c);
+            return CISIGMA_EINVAL;
+        }
+    }
+    c->cas = (c->sp[0].ntype == 1 && c->sp[1].ntype == 1);
+    // the same-spin kernel is built for up to 14 empty orbitals + 2 per K
+    for (int s = 0; s < 2; ++s) {
+        int N = c->sp[s].nel;
+        if (N >= 2 && norb - N + 2 > 14) {
+            cis_set_error(c, CISIGMA_EUNSUPPORTED, "init: more than 12 empty orbitals of one spin");
+            free_ctx(c);
+            return CISIGMA_EUNSUPPORTED;
+        }
+    }
+    int dev = 0;
+    hipError_t he = hipGetDevice(&dev);
+    if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (he != hipSuccess) {
+        int rc = hip_fail(c, he, "init: device");
+        free_ctx(c);
+        return rc;
+    }
+    int rc = build_layouts(c);
+    if (!rc) rc = build_integrals(c);
+    if (!rc) {
+        for (int s = 0; s < 2 && !rc; ++s) {
+            hipError_t e = cis::build_string_tables(c, s);
+            if (e != hipSuccess) rc = hip_fail(c, e, "init: string tables");
+        }
+    }
+    if (!rc) {
+        hipError_t e = cis::build_diag_tables(c);
+        if (e != hipSuccess) rc = hip_fail(c, e, "init: diagonal tables");
+    }
+    if (rc) {
+        std::fprintf(stderr, "cisigma_init: %s\n", c->err.c_str());
+        free_ctx(c);
+        return rc;
+    }
+    *out = c;
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_layout(const cisigma_ctx *ctx, int *nblocks, int64_t *block_offset, int *alpha_type,
+                           int *beta_type, int *nalpha_str, int *nbeta_str) {
+    if (!ctx || !nblocks) return CISIGMA_EINVAL;
+    const auto &L = ctx->lay;
+    *nblocks = L.nblk;
+    for (int b = 0; b < L.nblk; ++b) {
+        if (block_offset) block_offset[b] = L.blk_off[b];
+        if (alpha_type) alpha_type[b] = L.blk_a[b];
+        if (beta_type) beta_type[b] = L.blk_b[b];
+        if (nalpha_str) nalpha_str[b] = ctx->sp[0].tcount[L.blk_a[b]];
+        if (nbeta_str) nbeta_str[b] = ctx->sp[1].tcount[L.blk_b[b]];
+    }
+    if (block_offset) block_offset[L.nblk] = L.ndet;
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_address(const cisigma_ctx *ctx, uint32_t alpha_bits, uint32_t beta_bits, int64_t *index) {
+    if (!ctx || !index) return CISIGMA_EINVAL;
+    *index = -1;
+    int64_t a = host_string_index(ctx, 0, alpha_bits), b = host_string_index(ctx, 1, beta_bits);
+    if (a < 0 || b < 0) return CISIGMA_OK;
+    const auto &A = ctx->sp[0], &B = ctx->sp[1];
+    int ta = int(std::upper_bound(A.tstart.begin(), A.tstart.end(), int(a)) - A.tstart.begin()) - 1;
+    int tb = int(std::upper_bound(B.tstart.begin(), B.tstart.end(), int(b)) - B.tstart.begin()) - 1;
+    int64_t off = ctx->lay.boff[size_t(ta) * B.ntype + tb];
+    if (off < 0) return CISIGMA_OK;
+    *index = off + (a - A.tstart[ta]) * B.tcount[tb] + (b - B.tstart[tb]);
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_strings(const cisigma_ctx *ctx, int spin, uint32_t *out, int *nstr) {
+    if (!ctx || !nstr || spin < 0 || spin > 1) return CISIGMA_EINVAL;
+    const auto &T = ctx->sp[spin];
+    *nstr = T.nstr;
+    if (out && T.nstr > 0) {
+        hipError_t e = hipMemcpy(out, T.d_str, size_t(T.nstr) * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(const_cast<cisigma_ctx *>(ctx), e, "strings");
+    }
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_excitations(const cisigma_ctx *ctx, int spin, uint32_t *out, int *per_string, int *nstr) {
+    if (!ctx || !per_string || !nstr || spin < 0 || spin > 1) return CISIGMA_EINVAL;
+    const auto &T = ctx->sp[spin];
+    *nstr = T.nstr;
+    *per_string = T.nexc;
+    if (out && T.nstr > 0 && T.nexc > 0) {
+        hipError_t e = hipMemcpy(out, T.d_exc, size_t(T.nstr) * T.nexc * sizeof(uint32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(const_cast<cisigma_ctx *>(ctx), e, "excitations");
+    }
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if (!std::isfinite(value)) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: value is not finite");
+    switch (key) {
+        case CISIGMA_OPT_PRECISION:
+            if (value != CISIGMA_FP64 && value != CISIGMA_FP32)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: precision must be FP64 or FP32");
+            ctx->precision = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_MAX_SPACE:
+            if (value < 2 || value > 512) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: max_space out of range");
+            ctx->max_space = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_MAX_ITER:
+            if (value < 1 || value > 100000) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: max_iter out of range");
+            ctx->max_iter = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_REFINE_EVERY:
+            if (value < 1 || value > 100000) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: refine_every out of range");
+            ctx->refine_every = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_RESID_TOL:
+            if (value <= 0) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: resid_tol must be positive");
+            ctx->resid_tol = value;
+            return CISIGMA_OK;
+        case CISIGMA_OPT_VERBOSE:
+            ctx->verbose = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_PROFILE:
+            prof_reset(ctx);
+            ctx->profile = value != 0;
+            return CISIGMA_OK;
+        default:
+            return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unknown key");
+    }
+}
+
+CIS_API int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if (!C || !sigma) return cis_set_error(ctx, CISIGMA_EINVAL, "apply: NULL vector");
+    if (dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64) return cis_set_error(ctx, CISIGMA_EINVAL, "apply: bad dtype");
+    const size_t bytes = size_t(ctx->lay.ndet) * (dtype == CISIGMA_FP32 ? 4 : 8);
+    const char *a = static_cast<const char *>(C), *b = static_cast<const char *>(sigma);
+    if (a < b + bytes && b < a + bytes) return cis_set_error(ctx, CISIGMA_EINVAL, "apply: C and sigma overlap");
+    return cis::apply_sigma(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
+}
+
+CIS_API int cisigma_hdiag(cisigma_ctx *ctx, double *hdiag, void *stream) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if (!hdiag) return cis_set_error(ctx, CISIGMA_EINVAL, "hdiag: NULL output");
+    HIP_OR_FAIL(ctx, cis::launch_hdiag(ctx, hdiag, static_cast<hipStream_t>(stream)), "hdiag");
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs,
+                             cisigma_stats *stats) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if (nroots < 1 || nroots > 64 || nroots > ctx->lay.ndet || !energies || !(tol > 0) || !std::isfinite(tol))
+        return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: bad nroots, tol or energies");
+    return cis::davidson(ctx, nroots, tol, energies, vecs, stats);
+}

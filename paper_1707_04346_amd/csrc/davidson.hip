@@ -1,0 +1,518 @@
+// davidson.hip -- Davidson eigensolver around sigma = H C (Sec. 2.1; Sec. 3.3
+// steps 1-4):
+//   (1) initial subspace: unit vectors on the lowest diagonal elements, their
+//       sigma vectors, diagonalisation of the projected matrix G = B^T H B;
+//   (2) preconditioner: the diagonal H_II;
+//   (3) correction t = r / (theta - H_II) for each unconverged root, made
+//       orthogonal to all previous vectors (classical Gram-Schmidt, twice);
+//   (4) sigma of the new vectors, updated G, re-diagonalisation; repeat.
+// The basis collapses to the current Ritz vectors when it would exceed
+// max_space.  Vector arithmetic runs in HIP kernels with FP64 accumulation;
+// only the projected matrix (max_space^2 doubles) and a few norms cross to the
+// host each iteration.  The projected eigenproblem is solved on the host by
+// cyclic Jacobi rotations.
+//
+// Mixed precision (FP32 basis and sigma): every refine_every iterations, and
+// whenever the FP32 iteration meets the convergence test, the Ritz vectors
+// are formed in FP64, their sigma is rebuilt in FP64, and the basis collapses
+// onto them with the FP64 sigma (iterative refinement).  Convergence is only
+// declared there, on FP64 residual norms, and the returned energies are the
+// FP64 Rayleigh quotients.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <functional>
+#include <type_traits>
+#include <vector>
+
+#include "internal.h"
+
+namespace cis {
+namespace {
+
+constexpr int kRedBlocks = 1024;
+constexpr int kGroup = 8;
+
+template <typename T>
+__device__ __forceinline__ double ld(const T *p, int64_t i) { return double(p[i]); }
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double s = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < int(blockDim.x >> 6); ++i) s += sh[i];
+    return s;
+}
+
+// partial[b][i] = sum over block b's slice of X_i . y
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_dots(const TX *X, int64_t sx, int nx, const TY *y, int64_t N,
+                                              double *partial) {
+    __shared__ double sh[8];
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int i0 = 0; i0 < nx; i0 += kGroup) {
+        double acc[kGroup];
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) acc[j] = 0;
+        for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+            double yv = double(y[n]);
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j)
+                if (i0 + j < nx) acc[j] += double(X[(i0 + j) * sx + n]) * yv;
+        }
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+            if (i0 + j >= nx) break;
+            double s = block_sum(acc[j], sh);
+            if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nx + i0 + j] = s;
+        }
+    }
+}
+
+__global__ void k_reduce_partials(const double *partial, int nb, int nx, double *out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nx) return;
+    double s = 0;
+    for (int b = 0; b < nb; ++b) s += partial[int64_t(b) * nx + i];
+    out[i] = s;
+}
+
+// x = sum_i y_i B_i ; s = sum_i y_i S_i ; r = s - theta x ; t = r / (theta - hd)
+// writes x (FP64), optionally s (storage type) and t; partial sums of r.r
+template <typename T>
+__global__ __launch_bounds__(256) void k_ritz(const T *B, const T *S, int64_t sv, int m, const double *y,
+                                              double theta, const double *hd, double *xout, T *sout, T *tout,
+                                              int64_t N, double *partial) {
+    __shared__ double sh[8];
+    __shared__ double ys[512];
+    for (int i = threadIdx.x; i < m; i += blockDim.x) ys[i] = y[i];
+    __syncthreads();
+    double rr = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double x = 0, s = 0;
+        for (int i = 0; i < m; ++i) {
+            x += ys[i] * double(B[i * sv + n]);
+            s += ys[i] * double(S[i * sv + n]);
+        }
+        double r = s - theta * x;
+        rr += r * r;
+        if (xout) xout[n] = x;
+        if (sout) sout[n] = T(s);
+        if (tout) {
+            double d = theta - hd[n];
+            if (fabs(d) < 1e-8) d = d < 0 ? -1e-8 : 1e-8;
+            tout[n] = T(r / d);
+        }
+    }
+    double tot = block_sum(rr, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// partial sums of |y - e x|^2
+__global__ __launch_bounds__(256) void k_resid(const double *y, const double *x, double e, int64_t N, double *partial) {
+    __shared__ double sh[8];
+    double rr = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double r = y[n] - e * x[n];
+        rr += r * r;
+    }
+    double tot = block_sum(rr, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+// t -= sum_i c_i X_i
+template <typename T>
+__global__ __launch_bounds__(256) void k_subtract(const T *X, int64_t sx, int nx, const double *c, T *t, int64_t N) {
+    __shared__ double cs[512];
+    for (int i = threadIdx.x; i < nx; i += blockDim.x) cs[i] = c[i];
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double v = double(t[n]);
+        for (int i = 0; i < nx; ++i) v -= cs[i] * double(X[i * sx + n]);
+        t[n] = T(v);
+    }
+}
+
+template <typename TI, typename TO>
+__global__ void k_scale_copy(const TI *src, TO *dst, double f, int64_t N) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) dst[n] = TO(f * double(src[n]));
+}
+
+template <typename T>
+__global__ void k_unit(T *x, int64_t N, int64_t idx) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) x[n] = T(n == idx ? 1 : 0);
+}
+
+// lexicographic (value, index) minimum strictly above (pv, pi)
+__global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, double pv, int64_t pi, double *ov,
+                                                int64_t *oi) {
+    __shared__ double sv[256];
+    __shared__ int64_t si[256];
+    double bv = INFINITY;
+    int64_t bi = -1;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double v = hd[n];
+        bool above = (v > pv) || (v == pv && n > pi);
+        if (!above) continue;
+        if (v < bv || (v == bv && n < bi)) { bv = v; bi = n; }
+    }
+    sv[threadIdx.x] = bv;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (int(threadIdx.x) < off) {
+            double v2 = sv[threadIdx.x + off];
+            int64_t i2 = si[threadIdx.x + off];
+            if (i2 >= 0 && (si[threadIdx.x] < 0 || v2 < sv[threadIdx.x] || (v2 == sv[threadIdx.x] && i2 < si[threadIdx.x]))) {
+                sv[threadIdx.x] = v2;
+                si[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { ov[blockIdx.x] = sv[0]; oi[blockIdx.x] = si[0]; }
+}
+
+// symmetric eigenproblem by cyclic Jacobi; A (n x n, row-major) is destroyed;
+// eigenvalues ascending in w, eigenvectors as columns of V
+void jacobi_eig(std::vector<double> A, int n, std::vector<double> &w, std::vector<double> &V) {
+    V.assign(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i) V[size_t(i) * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0, tot = 0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                double a = A[size_t(i) * n + j];
+                tot += a * a;
+                if (i != j) off += a * a;
+            }
+        if (off <= 1e-30 * tot || off == 0) break;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                double apq = A[size_t(p) * n + q];
+                if (apq == 0) continue;
+                double app = A[size_t(p) * n + p], aqq = A[size_t(q) * n + q];
+                double th = (aqq - app) / (2 * apq);
+                double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
+                double c = 1 / std::sqrt(t * t + 1), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    double akp = A[size_t(k) * n + p], akq = A[size_t(k) * n + q];
+                    A[size_t(k) * n + p] = c * akp - s * akq;
+                    A[size_t(k) * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double apk = A[size_t(p) * n + k], aqk = A[size_t(q) * n + k];
+                    A[size_t(p) * n + k] = c * apk - s * aqk;
+                    A[size_t(q) * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    double vkp = V[size_t(k) * n + p], vkq = V[size_t(k) * n + q];
+                    V[size_t(k) * n + p] = c * vkp - s * vkq;
+                    V[size_t(k) * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    w.resize(n);
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) { w[i] = A[size_t(i) * n + i]; idx[i] = i; }
+    for (int i = 1; i < n; ++i)
+        for (int j = i; j > 0 && w[idx[j]] < w[idx[j - 1]]; --j) std::swap(idx[j], idx[j - 1]);
+    std::vector<double> w2(n), V2(size_t(n) * n);
+    for (int j = 0; j < n; ++j) {
+        w2[j] = w[idx[j]];
+        for (int k = 0; k < n; ++k) V2[size_t(k) * n + j] = V[size_t(k) * n + idx[j]];
+    }
+    w.swap(w2);
+    V.swap(V2);
+}
+
+struct Dev {
+    cisigma_ctx *ctx;
+    hipStream_t s;
+    double *partial = nullptr, *dvec = nullptr;
+    int64_t *pidx = nullptr;
+    int grid(int64_t N) const {
+        int64_t g = (N + 255) / 256;
+        return int(g < kRedBlocks ? (g > 0 ? g : 1) : kRedBlocks);
+    }
+};
+
+#define DV_TRY(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return cis_set_error(ctx, e_ == hipErrorOutOfMemory ? CISIGMA_ENOMEM : CISIGMA_EDEVICE, \
+                                 std::string("davidson: ") + hipGetErrorString(e_));        \
+    } while (0)
+
+template <typename TX, typename TY>
+hipError_t dots(Dev &d, const TX *X, int64_t sx, int nx, const TY *y, int64_t N, double *host_out) {
+    int g = d.grid(N);
+    hipLaunchKernelGGL((k_dots<TX, TY>), dim3(g), dim3(256), 0, d.s, X, sx, nx, y, N, d.partial);
+    hipLaunchKernelGGL(k_reduce_partials, dim3((nx + 63) / 64), dim3(64), 0, d.s, d.partial, g, nx, d.dvec);
+    hipError_t e = hipMemcpyAsync(host_out, d.dvec, size_t(nx) * sizeof(double), hipMemcpyDeviceToHost, d.s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(d.s);
+}
+
+template <typename T>
+int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats) {
+    auto t0 = std::chrono::steady_clock::now();
+    const bool mixed = std::is_same<T, float>::value;
+    const int dt = mixed ? CISIGMA_FP32 : CISIGMA_FP64;
+    const int64_t N = ctx->lay.ndet;
+    int max_space = ctx->max_space > 0 ? ctx->max_space : std::max(8 * nroots, 16);
+    max_space = std::max(max_space, 2 * nroots);
+    if (int64_t(max_space) > N) max_space = int(N);
+    if (max_space > 512) max_space = 512;
+    double rtol = ctx->resid_tol > 0 ? ctx->resid_tol : std::sqrt(tol);
+    if (mixed && ctx->resid_tol <= 0) rtol = std::max(rtol, 1e-5);
+    Dev d{ctx, ctx->stream};
+    const size_t es = sizeof(T);
+    T *B = nullptr, *S = nullptr, *SX = nullptr, *TB = nullptr;
+    double *X64 = nullptr, *hd = nullptr, *sig64 = nullptr;
+    // free-memory check before the big allocations
+    {
+        size_t need = size_t(2 * max_space + 2 * nroots) * N * es + size_t(nroots + 1) * N * 8 +
+                      (mixed ? size_t(N) * 8 : 0);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && need + (256u << 20) > fr)
+            return cis_set_error(ctx, CISIGMA_ENOMEM, "davidson: not enough device memory for the subspace");
+    }
+    auto cleanup = [&]() {
+        hipFree(B); hipFree(S); hipFree(SX); hipFree(TB); hipFree(X64); hipFree(hd); hipFree(sig64);
+        hipFree(d.partial); hipFree(d.dvec); hipFree(d.pidx);
+    };
+    struct Guard { std::function<void()> f; ~Guard() { f(); } } guard{cleanup};
+    DV_TRY(hipMalloc(&B, size_t(max_space) * N * es));
+    DV_TRY(hipMalloc(&S, size_t(max_space) * N * es));
+    DV_TRY(hipMalloc(&SX, size_t(nroots) * N * es));
+    DV_TRY(hipMalloc(&TB, size_t(nroots) * N * es));
+    DV_TRY(hipMalloc(&X64, size_t(nroots) * N * 8));
+    DV_TRY(hipMalloc(&hd, size_t(N) * 8));
+    if (mixed) DV_TRY(hipMalloc(&sig64, size_t(N) * 8));
+    DV_TRY(hipMalloc(&d.partial, size_t(kRedBlocks) * 512 * sizeof(double)));
+    // per-block (argmin) or per-vector (dots, <= 512) results
+    DV_TRY(hipMalloc(&d.dvec, size_t(std::max(kRedBlocks, 512)) * sizeof(double)));
+    DV_TRY(hipMalloc(&d.pidx, kRedBlocks * sizeof(int64_t)));
+    DV_TRY(launch_hdiag(ctx, hd, d.s));
+
+    const int g = d.grid(N);
+    // (1) guess: unit vectors on the lowest diagonal elements (ties: lowest index)
+    {
+        double pv = -INFINITY;
+        int64_t pi = -1;
+        std::vector<double> hv(g);
+        std::vector<int64_t> hi(g);
+        for (int r = 0; r < nroots; ++r) {
+            hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx);
+            DV_TRY(hipMemcpyAsync(hv.data(), d.dvec, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
+            DV_TRY(hipMemcpyAsync(hi.data(), d.pidx, g * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
+            DV_TRY(hipStreamSynchronize(d.s));
+            double bv = INFINITY;
+            int64_t bi = -1;
+            for (int b = 0; b < g; ++b)
+                if (hi[b] >= 0 && (bi < 0 || hv[b] < bv || (hv[b] == bv && hi[b] < bi))) { bv = hv[b]; bi = hi[b]; }
+            hipLaunchKernelGGL(k_unit<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, bi);
+            pv = bv;
+            pi = bi;
+        }
+    }
+    std::vector<double> G(size_t(max_space) * max_space, 0.0);
+    std::vector<double> theta(nroots, 0.0), theta_old(nroots, INFINITY), rnorm(nroots, 0.0);
+    std::vector<double> erq(nroots, 0.0), r64(nroots, INFINITY);
+    std::vector<double> w, Y, col(max_space + 8);
+    int m = 0, nnew = nroots, iter = 0, nsig32 = 0, nsig64 = 0, nref = 0;
+    bool converged = false, have_rq = false;
+    int since_ref = 0;
+    int rc = CISIGMA_OK;
+    auto sigma_of = [&](const void *x, void *y, int dtype) -> int {
+        int r = apply_sigma(ctx, x, y, dtype, d.s);
+        if (dtype == CISIGMA_FP32) ++nsig32; else ++nsig64;
+        return r;
+    };
+    while (true) {
+        // (4) sigma of the new vectors and the new columns of G
+        for (int k = m; k < m + nnew; ++k) {
+            rc = sigma_of(B + int64_t(k) * N, S + int64_t(k) * N, dt);
+            if (rc) return rc;
+            DV_TRY(dots(d, B, N, k + 1, S + int64_t(k) * N, N, col.data()));
+            for (int i = 0; i <= k; ++i) G[size_t(i) * max_space + k] = G[size_t(k) * max_space + i] = col[i];
+        }
+        m += nnew;
+        std::vector<double> Gm(size_t(m) * m);
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j)
+                Gm[size_t(i) * m + j] = 0.5 * (G[size_t(i) * max_space + j] + G[size_t(j) * max_space + i]);
+        jacobi_eig(Gm, m, w, Y);
+        ++iter;
+        ++since_ref;
+        // Ritz vectors and residual norms
+        std::vector<double> yk(m);
+        bool all_ok = true;
+        for (int r = 0; r < nroots; ++r) {
+            theta[r] = w[r];
+            for (int i = 0; i < m; ++i) yk[i] = Y[size_t(i) * m + r];
+            DV_TRY(hipMemcpyAsync(d.dvec, yk.data(), m * sizeof(double), hipMemcpyHostToDevice, d.s));
+            hipLaunchKernelGGL((k_ritz<T>), dim3(g), dim3(256), 0, d.s, B, S, N, m, d.dvec, theta[r], hd,
+                               X64 + int64_t(r) * N, SX + int64_t(r) * N, TB + int64_t(r) * N, N, d.partial);
+            std::vector<double> part(g);
+            DV_TRY(hipMemcpyAsync(part.data(), d.partial, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
+            DV_TRY(hipStreamSynchronize(d.s));
+            double ss = 0;
+            for (double v : part) ss += v;
+            rnorm[r] = std::sqrt(ss);
+            if (!(std::fabs(theta[r] - theta_old[r]) <= tol && rnorm[r] <= rtol)) all_ok = false;
+        }
+        if (ctx->verbose) {
+            std::fprintf(stderr, "davidson it %3d dim %3d", iter, m);
+            for (int r = 0; r < nroots; ++r) std::fprintf(stderr, "  E%d %.12f |r| %.3e", r, theta[r], rnorm[r]);
+            std::fprintf(stderr, "\n");
+        }
+        for (int r = 0; r < nroots; ++r) theta_old[r] = theta[r];
+        bool refined_now = false;
+        if (mixed && (all_ok || since_ref >= ctx->refine_every || iter >= ctx->max_iter)) {
+            // FP64 refinement: rebuild sigma of the Ritz vectors in FP64
+            refined_now = true;
+            ++nref;
+            since_ref = 0;
+            bool ok64 = true;
+            for (int r = 0; r < nroots; ++r) {
+                double *x = X64 + int64_t(r) * N;
+                rc = sigma_of(x, sig64, CISIGMA_FP64);
+                if (rc) return rc;
+                double xs, xx;
+                DV_TRY(dots(d, x, N, 1, sig64, N, &xs));
+                DV_TRY(dots(d, x, N, 1, x, N, &xx));
+                erq[r] = xs / xx;
+                // residual of the FP64 Ritz vector: |sigma - E x| / |x|
+                hipLaunchKernelGGL(k_resid, dim3(g), dim3(256), 0, d.s, sig64, x, erq[r], N, d.partial);
+                std::vector<double> part(g);
+                DV_TRY(hipMemcpyAsync(part.data(), d.partial, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
+                DV_TRY(hipStreamSynchronize(d.s));
+                double r2 = 0;
+                for (double v : part) r2 += v;
+                r64[r] = std::sqrt(r2 / xx);
+                if (r64[r] > rtol) ok64 = false;
+                // collapse slot r: basis = x (FP32), sigma = FP64 sigma rounded
+                hipLaunchKernelGGL((k_scale_copy<double, T>), dim3(g), dim3(256), 0, d.s, x, TB + int64_t(r) * N,
+                                   1.0, N);
+                hipLaunchKernelGGL((k_scale_copy<double, T>), dim3(g), dim3(256), 0, d.s, sig64, SX + int64_t(r) * N,
+                                   1.0, N);
+            }
+            have_rq = true;
+            if (ctx->verbose) {
+                std::fprintf(stderr, "  refine %d:", nref);
+                for (int r = 0; r < nroots; ++r) std::fprintf(stderr, "  E%d %.12f |r64| %.3e", r, erq[r], r64[r]);
+                std::fprintf(stderr, "\n");
+            }
+            if (ok64) { converged = true; break; }
+            // restart from the collapsed FP64-refined Ritz vectors
+            for (int r = 0; r < nroots; ++r) {
+                DV_TRY(hipMemcpyAsync(B + int64_t(r) * N, TB + int64_t(r) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+                DV_TRY(hipMemcpyAsync(S + int64_t(r) * N, SX + int64_t(r) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+            }
+            // exact projected matrix of the collapsed basis
+            for (int k = 0; k < nroots; ++k) {
+                DV_TRY(dots(d, B, N, nroots, S + int64_t(k) * N, N, col.data()));
+                for (int i = 0; i < nroots; ++i) G[size_t(i) * max_space + k] = col[i];
+            }
+            for (int i = 0; i < nroots; ++i)
+                for (int k = 0; k < i; ++k)
+                    G[size_t(i) * max_space + k] = G[size_t(k) * max_space + i] =
+                        0.5 * (G[size_t(i) * max_space + k] + G[size_t(k) * max_space + i]);
+            m = nroots;
+            if (iter >= ctx->max_iter) break;
+            // corrections from the refined residuals: recompute Ritz pieces in the collapsed basis
+            std::vector<double> Gm2(size_t(m) * m);
+            for (int i = 0; i < m; ++i)
+                for (int j = 0; j < m; ++j) Gm2[size_t(i) * m + j] = G[size_t(i) * max_space + j];
+            jacobi_eig(Gm2, m, w, Y);
+            for (int r = 0; r < nroots; ++r) {
+                theta[r] = w[r];
+                for (int i = 0; i < m; ++i) yk[i] = Y[size_t(i) * m + r];
+                DV_TRY(hipMemcpyAsync(d.dvec, yk.data(), m * sizeof(double), hipMemcpyHostToDevice, d.s));
+                hipLaunchKernelGGL((k_ritz<T>), dim3(g), dim3(256), 0, d.s, B, S, N, m, d.dvec, theta[r], hd,
+                                   X64 + int64_t(r) * N, SX + int64_t(r) * N, TB + int64_t(r) * N, N, d.partial);
+            }
+        } else if (!mixed) {
+            if (all_ok) { converged = true; break; }
+        }
+        if (iter >= ctx->max_iter) break;
+        if (!refined_now && m + nroots > max_space) {
+            // collapse onto the current Ritz vectors
+            for (int r = 0; r < nroots; ++r)
+                hipLaunchKernelGGL((k_scale_copy<double, T>), dim3(g), dim3(256), 0, d.s, X64 + int64_t(r) * N,
+                                   B + int64_t(r) * N, 1.0, N);
+            for (int r = 0; r < nroots; ++r)
+                DV_TRY(hipMemcpyAsync(S + int64_t(r) * N, SX + int64_t(r) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+            for (int i = 0; i < max_space * max_space; ++i) G[i] = 0;
+            for (int r = 0; r < nroots; ++r) G[size_t(r) * max_space + r] = theta[r];
+            m = nroots;
+        }
+        // (3) corrections, orthogonalised against the basis (CGS2) and each other
+        nnew = 0;
+        bool any_open = false;
+        for (int r = 0; r < nroots; ++r) any_open = any_open || refined_now || rnorm[r] > rtol;
+        for (int r = 0; r < nroots; ++r) {
+            // roots whose residual already meets the threshold get no new direction
+            if (any_open && !refined_now && rnorm[r] <= rtol) continue;
+            T *t = B + int64_t(m + nnew) * N;
+            DV_TRY(hipMemcpyAsync(t, TB + int64_t(r) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+            for (int pass = 0; pass < 2; ++pass) {
+                DV_TRY(dots(d, B, N, m + nnew, t, N, col.data()));
+                DV_TRY(hipMemcpyAsync(d.dvec, col.data(), (m + nnew) * sizeof(double), hipMemcpyHostToDevice, d.s));
+                hipLaunchKernelGGL((k_subtract<T>), dim3(g), dim3(256), 0, d.s, B, N, m + nnew, d.dvec, t, N);
+            }
+            double tt;
+            DV_TRY(dots(d, t, N, 1, t, N, &tt));
+            double nt = std::sqrt(tt);
+            if (!(nt > 1e-12)) continue;
+            hipLaunchKernelGGL((k_scale_copy<T, T>), dim3(g), dim3(256), 0, d.s, t, t, 1.0 / nt, N);
+            ++nnew;
+            if (m + nnew >= max_space) break;
+        }
+        if (nnew == 0) break;
+    }
+    DV_TRY(hipStreamSynchronize(d.s));
+    for (int r = 0; r < nroots; ++r) energies[r] = (mixed && have_rq) ? erq[r] : theta[r];
+    double rfinal = 0;
+    for (int r = 0; r < nroots; ++r) rfinal = std::max(rfinal, (mixed && have_rq) ? r64[r] : rnorm[r]);
+    if (vecs) {
+        for (int r = 0; r < nroots; ++r) {
+            T *dst = static_cast<T *>(vecs) + int64_t(r) * N;
+            hipLaunchKernelGGL((k_scale_copy<double, T>), dim3(g), dim3(256), 0, d.s, X64 + int64_t(r) * N, dst, 1.0, N);
+        }
+        DV_TRY(hipStreamSynchronize(d.s));
+    }
+    if (stats) {
+        stats->iterations = iter;
+        stats->sigma_fp32 = nsig32;
+        stats->sigma_fp64 = nsig64;
+        stats->refinements = nref;
+        stats->residual = rfinal;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (!converged) return cis_set_error(ctx, CISIGMA_ENOCONV, "davidson: not converged within max_iter");
+    return CISIGMA_OK;
+}
+
+}  // namespace
+
+int davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats) {
+    if (ctx->precision == CISIGMA_FP32) return run<float>(ctx, nroots, tol, energies, vecs, stats);
+    return run<double>(ctx, nroots, tol, energies, vecs, stats);
+}
+
+}  // namespace cis

@@ -1,0 +1,192 @@
+// internal.h -- shared declarations of the cisigma library (host + device).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/cisigma.h"
+
+namespace cis {
+
+constexpr int kMaxGas = 16;
+
+// GAS description passed by value to table kernels.
+struct GasDesc {
+    int n;                        // orbitals
+    int ngas;
+    uint32_t mask[kMaxGas];       // orbital mask of each space
+    int first[kMaxGas];           // first orbital of each space
+    uint64_t keymul[kMaxGas];     // type key = sum_g occ_g * keymul[g]
+};
+
+// Per-spin string tables.  Strings are grouped by occupation type (types in
+// lexicographic order of their per-space counts), ascending bitmask inside a
+// type.
+struct SpinTables {
+    int nel = 0;
+    int ntype = 0;
+    std::vector<int> tocc;        // ntype x ngas
+    std::vector<int> tcount;      // strings per type
+    std::vector<int> tstart;      // ntype + 1
+    std::vector<uint64_t> tkey;   // sorted type keys
+    int nstr = 0;
+    int nexc = 0;                 // single excitations per string: nel*(n-nel)
+    // pair (two-electron same-spin) lists over (nel-2)-electron strings K
+    int nK = 0;                   // number of K strings
+    int npv = 0;                  // pairs disjoint from K: C(n-nel+2, 2)
+    // device
+    uint32_t *d_str = nullptr;    // [nstr] bitmasks
+    int *d_stype = nullptr;       // [nstr] type of each string
+    uint32_t *d_exc = nullptr;    // [nstr][nexc] packed single excitations
+    uint32_t *d_pairs = nullptr;  // [nK][npv] packed pair entries
+    uint64_t *d_tkey = nullptr;   // [ntype]
+    int *d_tstart = nullptr;      // [ntype+1]
+    uint32_t *d_radix = nullptr;  // [ntype][ngas]
+    // per-string diagonal pieces (FP64): sum_{p in I} h_pp + 1/2 sum_{p,q in I} ((pp|qq) - (pq|qp))
+    double *d_adiag = nullptr;    // [nstr]
+};
+
+// packed single-excitation entry:  J << 11 | k << 6 | l << 1 | negative
+__host__ __device__ inline uint32_t exc_pack(uint32_t J, int k, int l, bool neg) {
+    return (J << 11) | (uint32_t(k) << 6) | (uint32_t(l) << 1) | (neg ? 1u : 0u);
+}
+constexpr uint32_t kExcNone = 0xFFFFFFFFu;
+// packed pair entry:  J << 11 | pairindex << 1 | negative
+constexpr uint32_t kPairNone = 0xFFFFFFFFu;
+
+// index of the unordered pair {p, q} with p >= q among pairs including the
+// diagonal: p(p+1)/2 + q
+__host__ __device__ inline int pair_ge(int p, int q) {
+    return p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p;
+}
+// index of the strict pair {p, q}, p > q: p(p-1)/2 + q
+__host__ __device__ inline int pair_gt(int p, int q) {
+    return p > q ? p * (p - 1) / 2 + q : q * (q - 1) / 2 + p;
+}
+
+// Blocks of the vector: (alpha type, beta type) in alpha-type-major order.
+struct Layout {
+    int nblk = 0;
+    std::vector<int> blk_a, blk_b;
+    std::vector<int64_t> blk_off;   // nblk + 1
+    std::vector<int64_t> boff;      // [ntype_a][ntype_b], -1 = absent
+    int64_t ndet = 0;
+};
+
+// Padded block layout of the CI vector with rows = strings of spin `rs` and
+// columns = strings of the other spin.  Block (row type t, column type u)
+// starts at seg[t][u] (-1 when the block is not in the space) and has row
+// stride ld[u] = width of column type u rounded up to a multiple of 64, so
+// every row segment is 256-byte aligned and 64-column tiles never straddle a
+// row end.  The padding columns hold zeros.
+constexpr int kTileCols = 64;
+struct PadLayout {
+    int rs = 0;
+    std::vector<int> ld;          // [ntype_other]
+    std::vector<int64_t> seg;     // [ntype_rs][ntype_other]
+    int64_t size = 0;             // elements
+    int ntiles = 0;               // 64-column tiles over all column types
+    std::vector<int> tile_u, tile_c0;
+    // device copies
+    int64_t *d_seg = nullptr;
+    int *d_ld = nullptr;
+    int *d_tile_u = nullptr;
+    int *d_tile_c0 = nullptr;
+};
+
+// One (alpha type, beta type) block as the conversion kernels see it.
+struct BlockDev {
+    int ta, tb, na, nb;         // types and string counts of the block
+    int64_t off;                // offset in the caller's vector
+    int64_t sega, segb;         // offsets in the alpha-major / beta-major padded layouts
+    int lda, ldb;               // padded row strides there
+};
+
+struct BlockTilesDev {
+    BlockDev *blk;
+    int *tb, *tr, *tc;          // 64x64 tiles: block, first row, first column
+    int ntiles;
+};
+
+struct Workspace {
+    void *cp = nullptr;    // C in the alpha-major padded layout
+    void *sp = nullptr;    // sigma accumulator, alpha-major padded layout
+    void *ct = nullptr;    // C in the beta-major padded layout
+    void *st = nullptr;    // beta same-spin sigma, beta-major padded layout
+    bool ready = false;
+};
+
+}  // namespace cis
+
+struct cisigma_ctx {
+    int n = 0, na = 0, nb = 0;
+    cis::GasDesc gas{};
+    std::vector<int> gas_norb, gas_min, gas_max;
+    cis::SpinTables sp[2];
+    cis::Layout lay;
+    cis::PadLayout pl[2];          // [0] alpha-major, [1] beta-major
+    int *d_tstart[2] = {nullptr, nullptr};   // device copies of SpinTables::tstart
+    bool cas = true;               // one type per spin (single block)
+    std::vector<double> h, g;      // host copies of the integrals
+    // device integral tables
+    int npair = 0;                 // n(n+1)/2 (pairs with diagonal)
+    int kp = 0;                    // npair rounded up to a multiple of 4
+    int nps = 0;                   // n(n-1)/2 strict pairs
+    double *d_gp64 = nullptr;      // [n*n][kp]: (ij|kl) with kl = pair_ge(k, l)
+    float *d_gp32 = nullptr;
+    double *d_v64[2] = {nullptr, nullptr};  // [nps][nps] same-spin pair matrix per spin
+    float *d_v32[2] = {nullptr, nullptr};
+    double *d_h64 = nullptr;       // [n][n]
+    float *d_h32 = nullptr;
+    double *d_jpq = nullptr;       // [n][n] (pp|qq)
+    cis::Workspace ws[2];          // per dtype (0 FP64, 1 FP32)
+    cis::BlockTilesDev bt{};       // tiles of the caller-layout blocks
+    hipStream_t stream = nullptr;  // own stream for synchronous calls
+    // options
+    int precision = CISIGMA_FP64;
+    int max_space = 0;
+    int max_iter = 100;
+    int refine_every = 8;
+    double resid_tol = -1.0;
+    int verbose = 0;
+    // per-pass event timing of apply (CISIGMA_OPT_PROFILE)
+    bool profile = false;
+    std::vector<hipEvent_t> prof_events;   // pending pairs, (CISIGMA_NPASS + 1) events per call
+    std::vector<int> prof_pending;         // calls recorded but not yet summed
+    double prof_ms[CISIGMA_NPASS] = {0};
+    int prof_calls = 0;
+    std::string err;
+};
+
+// ---- launchers (defined in the .hip files) -------------------------------
+namespace cis {
+
+hipError_t build_string_tables(cisigma_ctx *ctx, int spin);
+hipError_t build_diag_tables(cisigma_ctx *ctx);
+
+// sigma pieces; dtype 0 = double, 1 = float
+// padded K extent of the (ij|kl) table used by the alpha-beta kernel
+int sigma_ab_kp(int npair);
+hipError_t launch_fill(void *x, int64_t n, int dtype, hipStream_t s);
+hipError_t launch_sigma_ab(const cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *X, void *Y, int dtype,
+                                  hipStream_t s);
+// caller vector -> alpha-major and beta-major padded copies
+hipError_t launch_scatter_in(const cisigma_ctx *ctx, const void *C, void *cp, void *ct, int dtype, hipStream_t s);
+// sigma = alpha-major accumulator + transpose of the beta-major accumulator
+hipError_t launch_gather_out(const cisigma_ctx *ctx, const void *sp, const void *st, void *sigma, int dtype,
+                             hipStream_t s);
+hipError_t launch_hdiag(const cisigma_ctx *ctx, double *out, hipStream_t s);
+inline BlockTilesDev block_tiles(const cisigma_ctx *ctx) { return ctx->bt; }
+
+// Davidson driver (davidson.hip)
+int davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats);
+// sigma of one device vector on the given stream (api.hip)
+int apply_sigma(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+
+}  // namespace cis
+
+int cis_set_error(cisigma_ctx *ctx, int code, const std::string &msg);

@@ -1,0 +1,280 @@
+// sigma_ss.hip -- same-spin parts sigma_1 (beta-beta) and sigma_2 (alpha-alpha)
+// of the sigma vector (Eq. 8).
+//
+// For one spin with N electrons the same-spin Hamiltonian of Eq. 6 is
+//   H_s = sum_pq h_pq a+_p a_q + 1/2 sum_pqrs (pq|rs) a+_p a+_r a_s a_q .
+// On N-electron strings the one-electron part equals
+//   1/(N-1) sum_pqr h_pq a+_p a+_r a_r a_q   (N >= 2),
+// so H_s is one two-body operator, written over ordered pairs P = (p<r),
+// Q = (q<s) as
+//   H_s = sum_{P,Q} V(P,Q) a+_p a+_r a_s a_q ,   V(P,Q) = T_pqrs - T_psrq,
+//   T_pqrs = (pq|rs) + (h_pq d_rs + d_pq h_rs)/(N-1).
+// Inserting the (N-2)-electron strings K between creator and annihilator pairs
+//   sigma(K+P, :) += e(K,P) sum_Q V(P,Q) e(K,Q) X(K+Q, :)
+// where e(K,Q) is the sign of a+_q a+_s |K>.  For each K this is one dense
+// product of the (pairs of empty orbitals of K)^2 block of V with the gathered
+// rows X(K+Q, :): a matrix-core GEMM, then a row scatter.  X is the CI matrix
+// with rows = strings of this spin (C for alpha; C transposed for beta).
+//
+// N = 1 has no pairs; its one-electron part is applied by k_one_electron.
+#include "internal.h"
+
+#include <type_traits>
+
+namespace cis {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    using acc_t = floatx4;
+    using vec_t = floatx4;   // 16-byte B load: 4 columns
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    // accumulator register r of a lane holds output row 4*(lane/16) + r, column lane%16
+    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+typedef double double2_t __attribute__((ext_vector_type(2)));
+template <> struct Mfma<double> {
+    using acc_t = doublex4;
+    using vec_t = double2_t;  // 16-byte B load: 2 columns
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // the FP64 form spaces a lane's rows by 4: register r holds row lane/16 + 4*r
+    static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <typename T>
+struct SsArgs {
+    const T *X;                 // rows = strings of this spin, padded layout
+    T *Y;                       // accumulator, same layout
+    const uint32_t *pairs;      // [nK][npv]
+    const T *V;                 // [nps][nps]
+    const int *stype, *sstart;  // row-spin string types and type starts
+    const int64_t *seg;         // [nts][nto]
+    const int *ld;              // [nto]
+    const int *tile_u, *tile_c0;
+    int npv, nK, nps, nto, ntiles;
+};
+
+template <typename T, int KS, int MBL>
+__global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
+    using M = Mfma<T>;
+    using acc_t = typename M::acc_t;
+    using vec_t = typename M::vec_t;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int TW = 16 * VEC;
+    constexpr int HALVES = kTileCols / TW;
+    constexpr int KP = 4 * KS, MP = 16 * MBL;
+    constexpr int NE = KP > MP ? KP : MP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *As = reinterpret_cast<T *>(smem_raw);            // [MP][KP+1]
+    int *rowJ = reinterpret_cast<int *>(As + MP * (KP + 1));
+    int *pid = rowJ + NE;
+    int *neg = pid + NE;
+
+    const int K = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ int any_valid;
+    if (tid == 0) any_valid = 0;
+    __syncthreads();
+    for (int q = tid; q < NE; q += 256) {
+        uint32_t w = (q < p.npv) ? p.pairs[int64_t(K) * p.npv + q] : kPairNone;
+        rowJ[q] = (w == kPairNone) ? -1 : int(w >> 11);
+        pid[q] = int((w >> 1) & 1023u);
+        neg[q] = int(w & 1u);
+        if (w != kPairNone) any_valid = 1;
+    }
+    __syncthreads();
+    if (!any_valid) return;
+    for (int idx = tid; idx < MP * KP; idx += 256) {
+        int P = idx / KP, Q = idx % KP;
+        T val = 0;
+        if (rowJ[P] >= 0 && rowJ[Q] >= 0) {
+            val = p.V[int64_t(pid[P]) * p.nps + pid[Q]];
+            if (neg[P] ^ neg[Q]) val = -val;
+        }
+        As[P * (KP + 1) + Q] = val;
+    }
+    __syncthreads();
+    T A[MBL][KS];
+#pragma unroll
+    for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+        for (int t = 0; t < KS; ++t) A[rb][t] = As[(rb * 16 + (lane & 15)) * (KP + 1) + 4 * t + (lane >> 4)];
+
+    int cur_u = -1;
+    int64_t boff[KS];     // row offsets of the gathered B rows for the current column type
+    int64_t ooff[MBL][4]; // row offsets of the output rows
+    for (int item = wave + 4 * blockIdx.y; item < p.ntiles * HALVES; item += 4 * gridDim.y) {
+        const int tile = item / HALVES;
+        const int u = p.tile_u[tile];
+        const int c0 = p.tile_c0[tile] + (item % HALVES) * TW;
+        if (u != cur_u) {
+            cur_u = u;
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                int J = rowJ[4 * t + (lane >> 4)];
+                int64_t o = -1;
+                if (J >= 0) {
+                    int tj = p.stype[J];
+                    int64_t s = p.seg[int64_t(tj) * p.nto + u];
+                    if (s >= 0) o = s + int64_t(J - p.sstart[tj]) * p.ld[u];
+                }
+                boff[t] = o;
+            }
+#pragma unroll
+            for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    int P = rb * 16 + M::out_row(lane, i);
+                    int J = rowJ[P];
+                    int64_t o = -1;
+                    if (J >= 0) {
+                        int tj = p.stype[J];
+                        int64_t s = p.seg[int64_t(tj) * p.nto + u];
+                        if (s >= 0) o = s + int64_t(J - p.sstart[tj]) * p.ld[u];
+                    }
+                    ooff[rb][i] = o;
+                }
+        }
+        const int col = c0 + VEC * (lane & 15);
+        acc_t acc[MBL][VEC];
+#pragma unroll
+        for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[rb][v] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            vec_t b = vec_t{};
+            if (boff[t] >= 0) b = *reinterpret_cast<const vec_t *>(p.X + boff[t] + col);
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+#pragma unroll
+                for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(A[rb][t], b[v], acc[rb][v]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (ooff[rb][i] < 0) continue;
+                T *dst = p.Y + ooff[rb][i] + col;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) unsafeAtomicAdd(dst + v, acc[rb][v][i]);
+            }
+    }
+}
+
+// one-electron same-spin part for strings with a single electron:
+// Y(I, :) += h_qq X(I, :) (q the occupied orbital) + sum_{J = a+_l a_q I... } s h_kl X(J, :)
+template <typename T>
+__global__ __launch_bounds__(256) void k_one_electron(const T *X, T *Y, const uint32_t *exc, int nexc,
+                                                      const uint32_t *str, const T *h, int n, const int *stype,
+                                                      const int *sstart, const int64_t *seg, const int *ld,
+                                                      const int *tile_u, const int *tile_c0, int ntiles, int nto) {
+    const int I = blockIdx.x;
+    const int ti = stype[I];
+    const int ri = I - sstart[ti];
+    for (int tile = blockIdx.y; tile < ntiles; tile += gridDim.y) {
+        const int u = tile_u[tile];
+        const int col = tile_c0[tile] + int(threadIdx.x);
+        if (threadIdx.x >= kTileCols) continue;
+        int64_t so = seg[int64_t(ti) * nto + u];
+        if (so < 0) continue;
+        T acc = 0;
+        for (uint32_t b = str[I]; b; b &= b - 1) {
+            int q = __ffs(b) - 1;
+            acc += h[q * n + q] * X[so + int64_t(ri) * ld[u] + col];
+        }
+        for (int e = 0; e < nexc; ++e) {
+            uint32_t w = exc[int64_t(I) * nexc + e];
+            if (w == kExcNone) continue;
+            int J = int(w >> 11), k = (w >> 6) & 31, l = (w >> 1) & 31;
+            int tj = stype[J];
+            int64_t s = seg[int64_t(tj) * nto + u];
+            if (s < 0) continue;
+            T x = X[s + int64_t(J - sstart[tj]) * ld[u] + col];
+            acc += ((w & 1) ? -h[k * n + l] : h[k * n + l]) * x;
+        }
+        Y[so + int64_t(ri) * ld[u] + col] += acc;
+    }
+}
+
+template <typename T, int KS, int MBL>
+hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
+    constexpr int KP = 4 * KS, MP = 16 * MBL;
+    constexpr int NE = KP > MP ? KP : MP;
+    size_t lds = size_t(MP) * (KP + 1) * sizeof(T) + 3 * NE * sizeof(int);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ss<T, KS, MBL>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    constexpr int TW = 16 * (16 / sizeof(T));
+    const int items = a.ntiles * (kTileCols / TW);
+    int ysplit = 1;
+    while (int64_t(a.nK) * ysplit < 2048 && 4 * ysplit < items) ysplit *= 2;
+    hipLaunchKernelGGL((k_sigma_ss<T, KS, MBL>), dim3(a.nK, ysplit), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_ss(const SsArgs<T> &a, hipStream_t s) {
+    const int ks = (a.npv + 3) / 4;
+    const int mbl = (a.npv + 15) / 16;
+    // (KS, MBL) pairs for npv = C(m, 2), m = empty orbitals + 2
+#define CIS_SS(K, MB) if (ks == K && mbl == MB) return run_ss<T, K, MB>(a, s);
+    CIS_SS(1, 1) CIS_SS(2, 1) CIS_SS(3, 1) CIS_SS(4, 1) CIS_SS(4, 2) CIS_SS(6, 2) CIS_SS(7, 2) CIS_SS(9, 3)
+    CIS_SS(12, 3) CIS_SS(14, 4) CIS_SS(17, 5) CIS_SS(20, 5) CIS_SS(23, 6) CIS_SS(27, 7) CIS_SS(30, 8)
+    CIS_SS(34, 9) CIS_SS(39, 10) CIS_SS(43, 11)
+#undef CIS_SS
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y, hipStream_t s) {
+    const auto &S = ctx->sp[spin];
+    const auto &L = ctx->pl[spin];
+    const int other = 1 - spin;
+    if (S.nel == 0 || S.nstr == 0) return hipSuccess;
+    if (S.nel == 1) {
+        const T *h = std::is_same<T, float>::value ? reinterpret_cast<const T *>(ctx->d_h32)
+                                                   : reinterpret_cast<const T *>(ctx->d_h64);
+        int ysplit = 1;
+        while (int64_t(S.nstr) * ysplit < 1024 && ysplit < L.ntiles) ysplit *= 2;
+        hipLaunchKernelGGL((k_one_electron<T>), dim3(S.nstr, ysplit), dim3(kTileCols), 0, s,
+                           static_cast<const T *>(X), static_cast<T *>(Y), S.d_exc, S.nexc, S.d_str, h, ctx->n,
+                           S.d_stype, ctx->d_tstart[spin], L.d_seg, L.d_ld, L.d_tile_u, L.d_tile_c0, L.ntiles,
+                           ctx->sp[other].ntype);
+        return hipGetLastError();
+    }
+    SsArgs<T> a{};
+    a.X = static_cast<const T *>(X);
+    a.Y = static_cast<T *>(Y);
+    a.pairs = S.d_pairs;
+    a.V = std::is_same<T, float>::value ? reinterpret_cast<const T *>(ctx->d_v32[spin])
+                                        : reinterpret_cast<const T *>(ctx->d_v64[spin]);
+    a.stype = S.d_stype;
+    a.sstart = ctx->d_tstart[spin];
+    a.seg = L.d_seg;
+    a.ld = L.d_ld;
+    a.tile_u = L.d_tile_u;
+    a.tile_c0 = L.d_tile_c0;
+    a.npv = S.npv;
+    a.nK = S.nK;
+    a.nps = ctx->nps;
+    a.nto = ctx->sp[other].ntype;
+    a.ntiles = L.ntiles;
+    return dispatch_ss<T>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *X, void *Y, int dtype,
+                                  hipStream_t s) {
+    return dtype == CISIGMA_FP32 ? same_spin_t<float>(ctx, spin, X, Y, s) : same_spin_t<double>(ctx, spin, X, Y, s);
+}
+
+}  // namespace cis

@@ -1,0 +1,148 @@
+// vec.hip -- layout conversion, fill and diagonal kernels.
+//
+// The caller's CI vector holds blocks (alpha type, beta type) row-major
+// [I_alpha][I_beta] (Sec. 3.1 TTSS blocks).  The sigma kernels work on two
+// padded copies: alpha-major (rows = alpha strings, for sigma_2 and sigma_3)
+// and beta-major (rows = beta strings, for sigma_1), so that every pass reads
+// whole, aligned rows.  scatter_in makes both copies in one read of C (a
+// 64x64 LDS-tiled transpose); gather_out forms
+// sigma = alpha-major accumulator + (beta-major accumulator)^T.
+#include "internal.h"
+
+namespace cis {
+
+namespace {
+
+template <typename T>
+__global__ void k_fill(T *x, int64_t n) {
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) x[i] = T(0);
+}
+
+// tiles: (block, r0, c0) with 64x64 extent; 256 threads
+template <typename T>
+__global__ __launch_bounds__(256) void k_scatter_in(const T *__restrict__ C, T *__restrict__ cp, T *__restrict__ ct,
+                                                   const BlockDev *__restrict__ blk, const int *__restrict__ tb,
+                                                   const int *__restrict__ tr, const int *__restrict__ tc) {
+    __shared__ T tile[64][65];
+    const int t = blockIdx.x;
+    const BlockDev B = blk[tb[t]];
+    const int r0 = tr[t], c0 = tc[t];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int r = r0 + 4 * i + ty, c = c0 + tx;
+        T v = 0;
+        if (r < B.na && c < B.nb) {
+            v = C[B.off + int64_t(r) * B.nb + c];
+            cp[B.sega + int64_t(r) * B.lda + c] = v;
+        }
+        tile[4 * i + ty][tx] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int rb = c0 + 4 * i + ty, ca = r0 + tx;   // beta row, alpha column
+        if (rb < B.nb && ca < B.na) ct[B.segb + int64_t(rb) * B.ldb + ca] = tile[tx][4 * i + ty];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_out(const T *__restrict__ sp, const T *__restrict__ st,
+                                                   T *__restrict__ sig, const BlockDev *__restrict__ blk,
+                                                   const int *__restrict__ tb, const int *__restrict__ tr,
+                                                   const int *__restrict__ tc) {
+    __shared__ T tile[64][65];
+    const int t = blockIdx.x;
+    const BlockDev B = blk[tb[t]];
+    const int r0 = tr[t], c0 = tc[t];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int rb = c0 + 4 * i + ty, ca = r0 + tx;
+        T v = 0;
+        if (rb < B.nb && ca < B.na) v = st[B.segb + int64_t(rb) * B.ldb + ca];
+        tile[tx][4 * i + ty] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int r = r0 + 4 * i + ty, c = c0 + tx;
+        if (r < B.na && c < B.nb)
+            sig[B.off + int64_t(r) * B.nb + c] = sp[B.sega + int64_t(r) * B.lda + c] + tile[4 * i + ty][tx];
+    }
+}
+
+// H_II = A_a(Ia) + A_b(Ib) + sum_{p in Ia, q in Ib} (pp|qq)
+__global__ __launch_bounds__(256) void k_hdiag(double *out, const BlockDev *__restrict__ blk, const int *tb,
+                                               const int *tr, const int *tc, const uint32_t *astr,
+                                               const uint32_t *bstr, const int *astart, const int *bstart,
+                                               const double *aa, const double *ab, const double *jpq, int n) {
+    const int t = blockIdx.x;
+    const BlockDev B = blk[tb[t]];
+    const int r0 = tr[t], c0 = tc[t];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = 0; i < 16; ++i) {
+        int r = r0 + 4 * i + ty, c = c0 + tx;
+        if (r >= B.na || c >= B.nb) continue;
+        int Ia = astart[B.ta] + r, Ib = bstart[B.tb] + c;
+        uint32_t xa = astr[Ia], xb = bstr[Ib];
+        double e = aa[Ia] + ab[Ib];
+        for (uint32_t a = xa; a; a &= a - 1) {
+            int pp = __ffs(a) - 1;
+            for (uint32_t b = xb; b; b &= b - 1) e += jpq[pp * n + __ffs(b) - 1];
+        }
+        out[B.off + int64_t(r) * B.nb + c] = e;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_fill(void *x, int64_t n, int dtype, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (dtype == CISIGMA_FP32)
+        hipLaunchKernelGGL(k_fill<float>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<float *>(x), n);
+    else
+        hipLaunchKernelGGL(k_fill<double>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<double *>(x), n);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_in(const cisigma_ctx *ctx, const void *C, void *cp, void *ct, int dtype, hipStream_t s) {
+    BlockTilesDev bt = block_tiles(ctx);
+    if (bt.ntiles == 0) return hipSuccess;
+    if (dtype == CISIGMA_FP32)
+        hipLaunchKernelGGL(k_scatter_in<float>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const float *>(C),
+                           static_cast<float *>(cp), static_cast<float *>(ct), bt.blk, bt.tb, bt.tr, bt.tc);
+    else
+        hipLaunchKernelGGL(k_scatter_in<double>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const double *>(C),
+                           static_cast<double *>(cp), static_cast<double *>(ct), bt.blk, bt.tb, bt.tr, bt.tc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_out(const cisigma_ctx *ctx, const void *sp, const void *st, void *sigma, int dtype,
+                             hipStream_t s) {
+    BlockTilesDev bt = block_tiles(ctx);
+    if (bt.ntiles == 0) return hipSuccess;
+    if (dtype == CISIGMA_FP32)
+        hipLaunchKernelGGL(k_gather_out<float>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const float *>(sp),
+                           static_cast<const float *>(st), static_cast<float *>(sigma), bt.blk, bt.tb, bt.tr, bt.tc);
+    else
+        hipLaunchKernelGGL(k_gather_out<double>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const double *>(sp),
+                           static_cast<const double *>(st), static_cast<double *>(sigma), bt.blk, bt.tb, bt.tr,
+                           bt.tc);
+    return hipGetLastError();
+}
+
+hipError_t launch_hdiag(const cisigma_ctx *ctx, double *out, hipStream_t s) {
+    BlockTilesDev bt = block_tiles(ctx);
+    if (bt.ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_hdiag, dim3(bt.ntiles), dim3(256), 0, s, out, bt.blk, bt.tb, bt.tr, bt.tc, ctx->sp[0].d_str,
+                       ctx->sp[1].d_str, ctx->d_tstart[0], ctx->d_tstart[1], ctx->sp[0].d_adiag,
+                       ctx->sp[1].d_adiag, ctx->d_jpq, ctx->n);
+    return hipGetLastError();
+}
+
+}  // namespace cis

@@ -1,0 +1,172 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+* string and single-excitation tables: bit-exact against the oracle's string
+  order (itself pinned to an itertools enumeration) and a Python brute force
+  of the excitation lists;
+* sigma = H C: element by element against the oracle on the same seeded
+  inputs; FP64 within 1e-10 and FP32 within 1e-5 relative (2-norm), the
+  tolerances of the FP64 and FP32 modes;
+* H_II against the oracle diagonal.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 1e-5
+
+
+def _cis():
+    import paper_1707_04346_amd as cis
+    return cis
+
+
+def make(norb, na, nb, nchol=None, seed=0, gas=None):
+    h, g = si.integrals(norb, nchol or 2 * norb, seed)
+    return _cis().Context(norb, na, nb, h, g, gas=gas), oracle.Space(norb, na, nb, h, g, gas=gas)
+
+
+def gpu_sigma(ctx, c, dtype):
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S = torch.full_like(C, float("nan"))
+    ctx.apply(C, S)
+    torch.cuda.synchronize()
+    return S.double().cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# (norb, nalpha, nbeta, gas)
+SMALL = [
+    (6, 3, 3, None),            # CAS(6,6), 400 determinants
+    (6, 3, 2, None),
+    (7, 2, 4, None),
+    (5, 1, 3, None),            # one alpha electron: one-electron same-spin kernel
+    (5, 0, 2, None),            # no alpha electrons: no alpha-beta part
+    (4, 4, 1, None),            # full alpha shell
+    (8, 4, 4, None),            # CAS(8,8)
+    (9, 5, 4, None),            # 126 x 126: ragged column tiles
+    (10, 3, 3, None),
+    (7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])),      # GAS, three spaces
+    (8, 3, 4, ([3, 5], [5, 7], [6, 7])),               # GAS, two spaces, n_a != n_b
+    (6, 3, 3, ([2, 2, 2], [0, 0, 6], [6, 6, 6])),      # unrestricted GAS (= CAS)
+]
+
+
+def _ids(c):
+    return f"n{c[0]}a{c[1]}b{c[2]}" + ("gas" if c[3] else "")
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[_ids(c) for c in SMALL])
+def test_tables_bit_exact(case):
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, gas=gas)
+    assert ctx.ndet == ref.ndet
+    for spin, ne in ((0, na), (1, nb)):
+        s_ref, _ = ref.strings(spin)
+        s_gpu = ctx.strings(spin)
+        assert np.array_equal(s_gpu, s_ref)
+        index = {int(x): i for i, x in enumerate(s_ref)}
+        exc = ctx.excitations(spin)
+        assert exc.shape == (len(s_ref), ne * (norb - ne))
+        brute = np.zeros_like(exc)
+        for I, x in enumerate(int(v) for v in s_ref):
+            occ = [p for p in range(norb) if (x >> p) & 1]
+            vir = [p for p in range(norb) if not (x >> p) & 1]
+            e = 0
+            for k in occ:
+                for l in vir:
+                    y = (x & ~(1 << k)) | (1 << l)
+                    J = index.get(y)
+                    if J is None:
+                        brute[I, e] = 0xFFFFFFFF
+                    else:
+                        lo, hi = min(k, l), max(k, l)
+                        between = bin(x & (((1 << hi) - 1) & ~((1 << (lo + 1)) - 1))).count("1")
+                        brute[I, e] = (J << 11) | (k << 6) | (l << 1) | (between & 1)
+                    e += 1
+        assert np.array_equal(exc, brute)
+    # host-side address agrees with the oracle's order
+    for i in range(0, ref.ndet, max(1, ref.ndet // 97)):
+        assert ctx.address(*ref.det(i)) == i
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[_ids(c) for c in SMALL])
+def test_sigma_fp64_full(case):
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, gas=gas, seed=3)
+    c = si.ci_vector(ctx.ndet, 5)
+    s_ref = ref.sigma(c)
+    s = gpu_sigma(ctx, c, torch.float64)
+    assert rel(s, s_ref) <= TOL64, rel(s, s_ref)
+
+
+@pytest.mark.parametrize("case", SMALL, ids=[_ids(c) for c in SMALL])
+def test_sigma_fp32_full(case):
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, gas=gas, seed=4)
+    c = si.ci_vector(ctx.ndet, 6)
+    s_ref = ref.sigma(c)
+    s = gpu_sigma(ctx, c, torch.float32)
+    assert rel(s, s_ref) <= TOL32, rel(s, s_ref)
+
+
+def test_sigma_cas12_fp64_and_fp32():
+    """CAS(12,12), 853,776 determinants: the full vector in both precisions."""
+    w = si.WORKLOADS["cas12"]
+    ctx, ref = make(w["norb"], w["nalpha"], w["nbeta"], w["nchol"], seed=0)
+    c = si.ci_vector(ctx.ndet, 0)
+    s_ref = ref.sigma(c)
+    assert rel(gpu_sigma(ctx, c, torch.float64), s_ref) <= TOL64
+    assert rel(gpu_sigma(ctx, c, torch.float32), s_ref) <= TOL32
+
+
+def test_sigma_uniform_vector_and_repeat():
+    """The paper's timing input (every coefficient 1/N, Sec. 5); two calls in a
+    row give the same FP64 result (the accumulators are cleared each call)."""
+    ctx, ref = make(8, 4, 4, seed=9)
+    c = si.ci_vector(ctx.ndet, kind="uniform")
+    s_ref = ref.sigma(c)
+    s1 = gpu_sigma(ctx, c, torch.float64)
+    s2 = gpu_sigma(ctx, c, torch.float64)
+    assert rel(s1, s_ref) <= TOL64 and rel(s2, s_ref) <= TOL64
+
+
+def test_hdiag():
+    for norb, na, nb, gas in [(6, 3, 3, None), (7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])), (5, 1, 3, None)]:
+        ctx, ref = make(norb, na, nb, gas=gas)
+        out = torch.empty(ctx.ndet, dtype=torch.float64, device="cuda")
+        ctx.hdiag(out)
+        torch.cuda.synchronize()
+        assert np.abs(out.cpu().numpy() - ref.hdiag()).max() < 1e-12
+
+
+def test_apply_rejects_aliasing_and_bad_dtype():
+    cis = _cis()
+    ctx, _ = make(6, 3, 3)
+    C = torch.zeros(ctx.ndet, dtype=torch.float64, device="cuda")
+    assert ctx.apply_raw(C.data_ptr(), C.data_ptr(), cis.FP64) == cis.EINVAL
+    assert ctx.apply_raw(C.data_ptr(), C.data_ptr() + 8, cis.FP64) == cis.EINVAL
+    S = torch.zeros_like(C)
+    assert ctx.apply_raw(C.data_ptr(), S.data_ptr(), 7) == cis.EINVAL
+    assert ctx.apply_raw(0, S.data_ptr(), cis.FP64) == cis.EINVAL
+    assert "overlap" in ctx.last_error() or "NULL" in ctx.last_error()
+
+
+def test_apply_on_a_side_stream():
+    ctx, ref = make(8, 4, 3, seed=2)
+    c = si.ci_vector(ctx.ndet, 1)
+    s_ref = ref.sigma(c)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        C = torch.tensor(c, dtype=torch.float64, device="cuda")
+        S = torch.empty_like(C)
+        ctx.apply(C, S, stream=st)
+    st.synchronize()
+    assert rel(S.cpu().numpy(), s_ref) <= TOL64
