@@ -126,14 +126,17 @@ def main():
 
     dt32, pp32, C32 = time_sigma(ctx, cis, torch, "fp32", args.steps, args.warmup)
     ms32 = 1e3 * dt32 / args.steps
-    log(f"fp32 sigma: {ms32:.2f} ms/step, passes {pp32}")
-    extra = {"init_seconds": init_s, "fp32_pass_ms": pp32}
+    path32 = ctx.last_path(cis.FP32)
+    log(f"fp32 sigma: {ms32:.2f} ms/step, passes {pp32}, path flags {path32}")
+    extra = {"init_seconds": init_s, "fp32_pass_ms": pp32,
+             "fp32_path": {"ab_owner_computes": bool(path32 & cis.PATH_AB_OWNER),
+                           "same_spin_materialised": bool(path32 & cis.PATH_SS_MATERIALISED)}}
     if not args.no_fp64:
         dt64, pp64, _ = time_sigma(ctx, cis, torch, "fp64", max(2, args.steps // 2), 1)
         ms64 = 1e3 * dt64 / max(2, args.steps // 2)
         extra.update({"fp64_sigma_per_s": 1e3 / ms64, "fp64_ms_per_step": ms64, "fp64_pass_ms": pp64,
                       "speedup_fp32_vs_fp64": ms64 / ms32})
-        log(f"fp64 sigma: {ms64:.2f} ms/step, passes {pp64}")
+        log(f"fp64 sigma: {ms64:.2f} ms/step, passes {pp64}, path flags {ctx.last_path(cis.FP64)}")
 
     # alpha-beta contraction: 2 * M * K * N flops issued by the matrix cores,
     # M = alpha excitations per string (na*(n-na)), K = orbital pairs k>=l (n(n+1)/2), N = determinants
@@ -143,7 +146,8 @@ def main():
     achieved = flops / ab_s / 1e12
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32"], "traffic": None,
-                "kernel": "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> scatter)",
+                "kernel": ("k_sigma_ab_x (owner-computes sigma_3: gathered C rows -> FP32 MFMA -> LDS scatter)"
+                           if path32 & cis.PATH_AB_OWNER else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
                 "flops_per_launch": flops, "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
     if not args.no_fp64:

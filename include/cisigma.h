@@ -73,12 +73,13 @@ extern "C" {
 #define CISIGMA_OPT_RESID_TOL 5    /* residual-norm threshold; default sqrt(tol) (mixed: max(sqrt(tol), 1e-5)) */
 #define CISIGMA_OPT_VERBOSE 6      /* print one line per Davidson iteration to stderr when nonzero */
 #define CISIGMA_OPT_PROFILE 7      /* nonzero: time every pass of cisigma_apply with HIP events (resets the totals) */
+#define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels */
 
 /* passes of one cisigma_apply, in order, as reported by cisigma_pass_times */
 #define CISIGMA_PASS_LAYOUT_IN 0   /* C -> padded alpha-major and beta-major copies */
 #define CISIGMA_PASS_CLEAR 1       /* clear the two accumulators */
-#define CISIGMA_PASS_SIGMA_AB 2    /* sigma_3: alpha-beta part (Eq. 8) */
-#define CISIGMA_PASS_SIGMA_AA 3    /* sigma_2: alpha-alpha part */
+#define CISIGMA_PASS_SIGMA_AA 2    /* sigma_2: alpha-alpha part (Eq. 8) */
+#define CISIGMA_PASS_SIGMA_AB 3    /* sigma_3: alpha-beta part */
 #define CISIGMA_PASS_SIGMA_BB 4    /* sigma_1: beta-beta part */
 #define CISIGMA_PASS_LAYOUT_OUT 5  /* accumulators -> sigma */
 #define CISIGMA_NPASS 6
@@ -210,6 +211,16 @@ int cisigma_davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies,
  * of profiled apply calls into *ncalls.  EINVAL when profiling is off.
  */
 int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls);
+
+/*
+ * cisigma_last_path -- which kernels the most recent cisigma_apply of dtype
+ * used, as CISIGMA_PATH_* flags in *flags (0 before any apply).  One-block
+ * (CAS) spaces normally take both fast paths; GAS spaces and shapes outside
+ * the fast kernels' range use the general scatter kernels (no flags).
+ */
+#define CISIGMA_PATH_AB_OWNER 1          /* sigma_3 by the owner-computes kernel (no global atomics) */
+#define CISIGMA_PATH_SS_MATERIALISED 2   /* same-spin parts by materialised pair products + gather */
+int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags);
 
 /* message of the most recent failure on ctx (never NULL) */
 const char *cisigma_last_error(const cisigma_ctx *ctx);

@@ -16,10 +16,18 @@ LIB_PATH = os.path.join(_HERE, "libcisigma.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP64, FP32 = 0, 1
 OPT_PRECISION, OPT_MAX_SPACE, OPT_MAX_ITER, OPT_REFINE_EVERY, OPT_RESID_TOL, OPT_VERBOSE, OPT_PROFILE = 1, 2, 3, 4, 5, 6, 7
-PASSES = ["layout_in", "clear", "sigma_ab", "sigma_aa", "sigma_bb", "layout_out"]
+PASSES = ["layout_in", "clear", "sigma_aa", "sigma_ab", "sigma_bb", "layout_out"]
+OPT_SIGMA_PATH = 8
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+
+# PyTorch ships its own HIP runtime; when torch is present it must be loaded
+# before this library so that the process holds a single HIP runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
 
 
 class _Gas(ctypes.Structure):
@@ -59,6 +67,8 @@ _lib.cisigma_hdiag.restype = _i32
 _lib.cisigma_hdiag.argtypes = [_vp, _vp, _vp]
 _lib.cisigma_davidson.restype = _i32
 _lib.cisigma_davidson.argtypes = [_vp, _i32, _f64, _vp, _vp, ctypes.POINTER(Stats)]
+_lib.cisigma_last_path.restype = _i32
+_lib.cisigma_last_path.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
 _lib.cisigma_pass_times.restype = _i32
 _lib.cisigma_pass_times.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
 _lib.cisigma_last_error.restype = ctypes.c_char_p
@@ -68,7 +78,8 @@ _lib.cisigma_strerror.argtypes = [_i32]
 
 EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "cisigma_address", "cisigma_strings",
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
-           "cisigma_pass_times", "cisigma_last_error", "cisigma_strerror"]
+           "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror"]
+PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
 class CisigmaError(RuntimeError):
@@ -124,7 +135,7 @@ class Context:
         self.ndet = int(_lib.cisigma_ndet(self._h))
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.cisigma_free(self._h)
             self._h = None
 
@@ -205,6 +216,12 @@ class Context:
         n = _i32()
         self._check(_lib.cisigma_pass_times(self._h, ms.ctypes.data, ctypes.byref(n)))
         return dict(zip(PASSES, ms.tolist())), n.value
+
+    def last_path(self, dtype=FP32):
+        """CISIGMA_PATH_* flags of the most recent apply of dtype."""
+        f = _i32()
+        self._check(_lib.cisigma_last_path(self._h, int(dtype), ctypes.byref(f)))
+        return f.value
 
     def last_error(self):
         return _lib.cisigma_last_error(self._h).decode()

@@ -91,16 +91,17 @@ void free_ctx(cisigma_ctx *c) {
     for (int s = 0; s < 2; ++s) {
         auto &T = c->sp[s];
         hipFree(T.d_str); hipFree(T.d_stype); hipFree(T.d_exc); hipFree(T.d_pairs);
-        hipFree(T.d_tkey); hipFree(T.d_tstart); hipFree(T.d_radix); hipFree(T.d_adiag);
+        hipFree(T.d_tkey); hipFree(T.d_tstart); hipFree(T.d_radix); hipFree(T.d_adiag); hipFree(T.d_pair_inv);
         auto &L = c->pl[s];
         hipFree(L.d_seg); hipFree(L.d_ld); hipFree(L.d_tile_u); hipFree(L.d_tile_c0);
         hipFree(c->d_tstart[s]);
         hipFree(c->d_v64[s]); hipFree(c->d_v32[s]);
         auto &W = c->ws[s];
-        hipFree(W.cp); hipFree(W.sp); hipFree(W.ct); hipFree(W.st);
+        hipFree(W.cp); hipFree(W.sp); hipFree(W.ct); hipFree(W.st); hipFree(W.ys);
     }
     hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
+    hipFree(c->plan.d_entries); hipFree(c->plan.d_thread_off);
     for (auto e : c->prof_events) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
@@ -244,6 +245,89 @@ int build_layouts(cisigma_ctx *c) {
     return CISIGMA_OK;
 }
 
+// Scatter plan of the owner-computes sigma_3 kernel (one-block spaces of up
+// to 16 orbitals), built on the host from the device beta excitation lists.
+int build_scatter_plan(cisigma_ctx *c) {
+    constexpr int NT = 32, WS = 33, EMAX = 24;
+    const auto &B = c->sp[1];
+    const int ld = c->pl[0].ld[0];
+    if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || ld >= 32768 || (c->npair + 1) * WS >= 8192)
+        return CISIGMA_OK;
+    std::vector<uint32_t> exc(size_t(B.nstr) * B.nexc), str(B.nstr);
+    HIP_OR_FAIL(c, hipMemcpy(exc.data(), B.d_exc, exc.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
+    HIP_OR_FAIL(c, hipMemcpy(str.data(), B.d_str, str.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
+    cis::ScatterPlan &P = c->plan;
+    P.ntile = ld / NT;
+    const uint32_t nulle = (1u << 29) | (uint32_t(ld) << 13) | uint32_t(c->npair * WS);
+    std::vector<uint32_t> entries, toff;
+    entries.reserve(size_t(B.nstr) * (B.nexc + c->nb) * 3 / 2);
+    toff.reserve(size_t(P.ntile) * 257);
+    struct Item { uint32_t tgt, off, neg; };
+    std::vector<Item> tile;
+    int emax = 0;
+    for (int t = 0; t < P.ntile; ++t) {
+        tile.clear();
+        for (int col = 0; col < NT; ++col) {
+            const int Jb = t * NT + col;
+            if (Jb >= B.nstr) break;
+            for (int e = 0; e < B.nexc; ++e) {
+                const uint32_t w = exc[size_t(Jb) * B.nexc + e];
+                if (w == cis::kExcNone) continue;
+                const int k = (w >> 6) & 31, l = (w >> 1) & 31;
+                tile.push_back({w >> 11, uint32_t(cis::pair_ge(k, l) * WS + col), w & 1u});
+            }
+            for (uint32_t b = str[Jb]; b; b &= b - 1) {
+                const int k = __builtin_ctz(b);
+                tile.push_back({uint32_t(Jb), uint32_t((k * (k + 1) / 2 + k) * WS + col), 0u});
+            }
+        }
+        std::stable_sort(tile.begin(), tile.end(), [](const Item &a, const Item &b) { return a.tgt < b.tgt; });
+        // target groups, then the smallest range capacity (multiple of 4) that
+        // packs them into at most 256 ranges
+        std::vector<std::pair<size_t, size_t>> groups;   // (first, count)
+        for (size_t i = 0; i < tile.size();) {
+            size_t j = i;
+            while (j < tile.size() && tile[j].tgt == tile[i].tgt) ++j;
+            groups.push_back({i, j - i});
+            i = j;
+        }
+        auto r4 = [](size_t x) { return (x + 3) / 4 * 4; };
+        auto ranges_for = [&](size_t cap) {
+            size_t nr = 0, cur = 0;
+            for (auto &g : groups) {
+                if (r4(g.second) > cap) return size_t(1) << 30;
+                if (cur > 0 && r4(cur + g.second) > cap) { ++nr; cur = 0; }
+                cur += g.second;
+            }
+            return nr + (cur > 0);
+        };
+        size_t cap = 4;
+        while (ranges_for(cap) > 256) cap += 4;
+        size_t gi = 0;
+        for (int th = 0; th < 256; ++th) {
+            toff.push_back(uint32_t(entries.size()));
+            size_t cur = 0;
+            while (gi < groups.size() && (cur == 0 || r4(cur + groups[gi].second) <= cap)) {
+                const auto &g = groups[gi++];
+                for (size_t q = g.first; q < g.first + g.second; ++q)
+                    entries.push_back((uint32_t(q == g.first) << 29) | (tile[q].neg << 28) | (tile[q].tgt << 13) | tile[q].off);
+                cur += g.second;
+            }
+            size_t cnt = cur;
+            while (cnt % 4) { entries.push_back(nulle); ++cnt; }
+            emax = std::max(emax, int(cnt));
+        }
+        if (gi != groups.size()) return CISIGMA_OK;   // cannot happen: ranges_for(cap) <= 256
+        toff.push_back(uint32_t(entries.size()));
+    }
+    if (emax > EMAX) return CISIGMA_OK;   // the kernel's register window is too small: no plan
+    P.emax = emax;
+    entries.insert(entries.end(), 4, nulle);
+    HIP_OR_FAIL(c, upload(&P.d_entries, entries), "init: scatter plan");
+    HIP_OR_FAIL(c, upload(&P.d_thread_off, toff), "init: scatter plan");
+    return CISIGMA_OK;
+}
+
 int ensure_workspace(cisigma_ctx *c, int dtype) {
     auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
     if (W.ready) return CISIGMA_OK;
@@ -260,6 +344,24 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     // padding columns of the C copies stay zero for good
     HIP_OR_FAIL(c, hipMemset(W.cp, 0, na), "apply: workspace");
     HIP_OR_FAIL(c, hipMemset(W.ct, 0, nb), "apply: workspace");
+    // materialised same-spin rows for one-type spins: all columns if they fit in half
+    // of what is free, else column chunks (multiples of 64)
+    if (c->cas) {
+        size_t rows = 0, cols = 0;
+        for (int s = 0; s < 2; ++s)
+            if (c->sp[s].nel >= 2) {
+                rows = std::max(rows, size_t(c->sp[s].nK) * c->sp[s].npv);
+                cols = std::max(cols, size_t(c->pl[s].ld[0]));
+            }
+        if (rows > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            size_t budget = fr / 2;
+            size_t chunk = std::min(cols, budget / (rows * es) / cis::kTileCols * cis::kTileCols);
+            if (chunk >= size_t(cis::kTileCols) && hipMalloc(&W.ys, rows * chunk * es) == hipSuccess)
+                W.ys_chunk = int(chunk);
+            else
+                W.ys = nullptr;
+        }
+    }
     HIP_OR_FAIL(c, hipDeviceSynchronize(), "apply: workspace");
     W.ready = true;
     return CISIGMA_OK;
@@ -273,6 +375,8 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     int rc = ensure_workspace(c, dtype);
     if (rc) return rc;
     auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
+    // one-type spins with room for the materialised same-spin rows avoid global atomics there
+    const bool mat = c->cas && c->ab_mode == 0 && W.ys != nullptr;
     hipEvent_t ev[CISIGMA_NPASS + 1];
     const bool prof = c->profile;
     if (prof) {
@@ -280,16 +384,21 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
         HIP_OR_FAIL(c, hipEventRecord(ev[0], s), "apply: profiling events");
     }
     auto mark = [&](int pass) -> hipError_t { return prof ? hipEventRecord(ev[pass + 1], s) : hipSuccess; };
+    c->last_path[dtype == CISIGMA_FP32] = mat ? CISIGMA_PATH_SS_MATERIALISED : 0;
     HIP_OR_FAIL(c, launch_scatter_in(c, C, W.cp, W.ct, dtype, s), "apply: layout conversion");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_LAYOUT_IN), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_fill(W.sp, c->pl[0].size, dtype, s), "apply: fill");
-    HIP_OR_FAIL(c, launch_fill(W.st, c->pl[1].size, dtype, s), "apply: fill");
+    for (int spin = 0; spin < 2; ++spin) {
+        if (mat && c->sp[spin].nel >= 2) continue;   // overwritten by the gather
+        HIP_OR_FAIL(c, launch_fill(spin == 0 ? W.sp : W.st, c->pl[spin].size, dtype, s), "apply: fill");
+    }
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_CLEAR), "apply: profiling events");
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, W.sp, dtype, s, mat ? W.ys : nullptr, W.ys_chunk),
+                "apply: sigma_2 (alpha-alpha)");
+    HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AA), "apply: profiling events");
     HIP_OR_FAIL(c, launch_sigma_ab(c, W.cp, W.sp, dtype, s), "apply: sigma_3 (alpha-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AB), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, W.sp, dtype, s), "apply: sigma_2 (alpha-alpha)");
-    HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AA), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s), "apply: sigma_1 (beta-beta)");
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s, mat ? W.ys : nullptr, W.ys_chunk),
+                "apply: sigma_1 (beta-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_BB), "apply: profiling events");
     HIP_OR_FAIL(c, launch_gather_out(c, W.sp, W.st, sigma, dtype, s), "apply: layout conversion");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_LAYOUT_OUT), "apply: profiling events");
@@ -329,6 +438,12 @@ CIS_API int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls) {
     ctx->prof_pending.clear();
     for (int p = 0; p < CISIGMA_NPASS; ++p) ms[p] = ctx->prof_ms[p];
     *ncalls = ctx->prof_calls;
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags) {
+    if (!ctx || !flags || (dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64)) return CISIGMA_EINVAL;
+    *flags = ctx->last_path[dtype == CISIGMA_FP32];
     return CISIGMA_OK;
 }
 
@@ -505,6 +620,7 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
         hipError_t e = cis::build_diag_tables(c);
         if (e != hipSuccess) rc = hip_fail(c, e, "init: diagonal tables");
     }
+    if (!rc) rc = build_scatter_plan(c);
     if (rc) {
         std::fprintf(stderr, "cisigma_init: %s\n", c->err.c_str());
         free_ctx(c);
@@ -594,6 +710,10 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             return CISIGMA_OK;
         case CISIGMA_OPT_VERBOSE:
             ctx->verbose = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_SIGMA_PATH:
+            if (value != 0 && value != 1) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0 or 1");
+            ctx->ab_mode = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_PROFILE:
             prof_reset(ctx);

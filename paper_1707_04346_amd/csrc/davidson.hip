@@ -272,14 +272,26 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     const bool mixed = std::is_same<T, float>::value;
     const int dt = mixed ? CISIGMA_FP32 : CISIGMA_FP64;
     const int64_t N = ctx->lay.ndet;
-    int max_space = ctx->max_space > 0 ? ctx->max_space : std::max(8 * nroots, 16);
+    const size_t es = sizeof(T);
+    int max_space = ctx->max_space;
+    if (max_space <= 0) {
+        // default: a generous subspace (restarts slow Davidson down on strongly
+        // correlated spaces), capped by what fits in 70% of free device memory
+        max_space = std::max(8 * nroots, 32);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            size_t fixed = size_t(2 * nroots) * N * es + size_t(nroots + 1) * N * 8 + (mixed ? size_t(N) * 8 : 0);
+            size_t avail = size_t(0.7 * double(fr));
+            int fit = avail > fixed ? int((avail - fixed) / (2 * size_t(N) * es)) : 0;
+            max_space = std::min(max_space, fit);
+        }
+    }
     max_space = std::max(max_space, 2 * nroots);
     if (int64_t(max_space) > N) max_space = int(N);
     if (max_space > 512) max_space = 512;
     double rtol = ctx->resid_tol > 0 ? ctx->resid_tol : std::sqrt(tol);
     if (mixed && ctx->resid_tol <= 0) rtol = std::max(rtol, 1e-5);
     Dev d{ctx, ctx->stream};
-    const size_t es = sizeof(T);
     T *B = nullptr, *S = nullptr, *SX = nullptr, *TB = nullptr;
     double *X64 = nullptr, *hd = nullptr, *sig64 = nullptr;
     // free-memory check before the big allocations

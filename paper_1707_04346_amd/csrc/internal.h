@@ -42,6 +42,7 @@ struct SpinTables {
     int *d_stype = nullptr;       // [nstr] type of each string
     uint32_t *d_exc = nullptr;    // [nstr][nexc] packed single excitations
     uint32_t *d_pairs = nullptr;  // [nK][npv] packed pair entries
+    int *d_pair_inv = nullptr;    // [nstr][nel(nel-1)/2] rows K*npv+e producing each string (one type only)
     uint64_t *d_tkey = nullptr;   // [ntype]
     int *d_tstart = nullptr;      // [ntype+1]
     uint32_t *d_radix = nullptr;  // [ntype][ngas]
@@ -111,11 +112,27 @@ struct BlockTilesDev {
     int ntiles;
 };
 
+// Conflict-free schedule of the beta-side scatter of the owner-computes
+// sigma_3 kernel (32-column tiles): per tile, every contribution (target beta
+// string, W row kl, column, sign) sorted by target and cut into 256
+// per-thread ranges of whole target groups, each padded to a multiple of 4
+// entries, so no two threads write the same sigma element within a tile.
+// entry = first-of-group << 29 | negative << 28 | target << 13 | (kl*33 + column)
+// no-op entry = 1 << 29 | ld << 13 | npair*33 (zero row of W, spare sigma slot).
+struct ScatterPlan {
+    uint32_t *d_entries = nullptr;
+    uint32_t *d_thread_off = nullptr;  // [ntile][257] entry offsets (multiples of 4)
+    int ntile = 0;
+    int emax = 0;                      // longest padded per-thread range
+};
+
 struct Workspace {
     void *cp = nullptr;    // C in the alpha-major padded layout
     void *sp = nullptr;    // sigma accumulator, alpha-major padded layout
     void *ct = nullptr;    // C in the beta-major padded layout
     void *st = nullptr;    // beta same-spin sigma, beta-major padded layout
+    void *ys = nullptr;    // materialised same-spin rows (one-type spins), ys_chunk columns each
+    int ys_chunk = 0;
     bool ready = false;
 };
 
@@ -144,6 +161,7 @@ struct cisigma_ctx {
     double *d_jpq = nullptr;       // [n][n] (pp|qq)
     cis::Workspace ws[2];          // per dtype (0 FP64, 1 FP32)
     cis::BlockTilesDev bt{};       // tiles of the caller-layout blocks
+    cis::ScatterPlan plan;         // beta-side scatter plan of the owner-computes sigma_3 kernel
     hipStream_t stream = nullptr;  // own stream for synchronous calls
     // options
     int precision = CISIGMA_FP64;
@@ -152,6 +170,9 @@ struct cisigma_ctx {
     int refine_every = 8;
     double resid_tol = -1.0;
     int verbose = 0;
+    int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]
+    // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
+    int ab_mode = 0;
     // per-pass event timing of apply (CISIGMA_OPT_PROFILE)
     bool profile = false;
     std::vector<hipEvent_t> prof_events;   // pending pairs, (CISIGMA_NPASS + 1) events per call
@@ -172,8 +193,11 @@ hipError_t build_diag_tables(cisigma_ctx *ctx);
 int sigma_ab_kp(int npair);
 hipError_t launch_fill(void *x, int64_t n, int dtype, hipStream_t s);
 hipError_t launch_sigma_ab(const cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+// Ys == nullptr: scatter with atomics into Y (Y holds what to add to).
+// Ys != nullptr (one-type spins): materialise into Ys chunk by chunk (chunk
+// columns, a multiple of 64) and gather into Y, overwriting Y.
 hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *X, void *Y, int dtype,
-                                  hipStream_t s);
+                                  hipStream_t s, void *Ys = nullptr, int chunk = 0);
 // caller vector -> alpha-major and beta-major padded copies
 hipError_t launch_scatter_in(const cisigma_ctx *ctx, const void *C, void *cp, void *ct, int dtype, hipStream_t s);
 // sigma = alpha-major accumulator + transpose of the beta-major accumulator

@@ -19,6 +19,7 @@
 // N = 1 has no pairs; its one-electron part is applied by k_one_electron.
 #include "internal.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace cis {
@@ -59,9 +60,14 @@ struct SsArgs {
     const int *ld;              // [nto]
     const int *tile_u, *tile_c0;
     int npv, nK, nps, nto, ntiles;
+    // store mode: rows K*npv+P of Ys (row stride ldy) over tiles [tile_begin, tile_end),
+    // column c stored at c - col_begin
+    T *Ys;
+    int64_t ldy;
+    int tile_begin, tile_end, col_begin;
 };
 
-template <typename T, int KS, int MBL>
+template <typename T, int KS, int MBL, bool STORE>
 __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
@@ -110,7 +116,9 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     int cur_u = -1;
     int64_t boff[KS];     // row offsets of the gathered B rows for the current column type
     int64_t ooff[MBL][4]; // row offsets of the output rows
-    for (int item = wave + 4 * blockIdx.y; item < p.ntiles * HALVES; item += 4 * gridDim.y) {
+    const int item_end = STORE ? p.tile_end * HALVES : p.ntiles * HALVES;
+    for (int item = (STORE ? p.tile_begin * HALVES : 0) + wave + 4 * blockIdx.y; item < item_end;
+         item += 4 * gridDim.y) {
         const int tile = item / HALVES;
         const int u = p.tile_u[tile];
         const int c0 = p.tile_c0[tile] + (item % HALVES) * TW;
@@ -157,15 +165,49 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
 #pragma unroll
                 for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(A[rb][t], b[v], acc[rb][v]);
         }
+        if (STORE) {
+            // plain stores: row K*npv + P of the materialised buffer belongs to this workgroup alone
 #pragma unroll
-        for (int rb = 0; rb < MBL; ++rb)
+            for (int rb = 0; rb < MBL; ++rb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (ooff[rb][i] < 0) continue;
-                T *dst = p.Y + ooff[rb][i] + col;
+                for (int i = 0; i < 4; ++i) {
+                    const int P = rb * 16 + M::out_row(lane, i);
+                    if (P >= p.npv) continue;
+                    vec_t o;
 #pragma unroll
-                for (int v = 0; v < VEC; ++v) unsafeAtomicAdd(dst + v, acc[rb][v][i]);
-            }
+                    for (int v = 0; v < VEC; ++v) o[v] = acc[rb][v][i];
+                    *reinterpret_cast<vec_t *>(p.Ys + (int64_t(K) * p.npv + P) * p.ldy + (col - p.col_begin)) = o;
+                }
+        } else {
+#pragma unroll
+            for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (ooff[rb][i] < 0) continue;
+                    T *dst = p.Y + ooff[rb][i] + col;
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) unsafeAtomicAdd(dst + v, acc[rb][v][i]);
+                }
+        }
+    }
+}
+
+// out(I, c) = sum over the occupied pairs of I of the materialised rows
+// Ys(K*npv + e, c): the owner-computes half of the same-spin part.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_gather(const T *__restrict__ Ys, int64_t ldy, int col_begin,
+                                                     int col_end, const int *__restrict__ inv, int per,
+                                                     T *__restrict__ out, int64_t ld) {
+    using vec_t = typename Mfma<T>::vec_t;
+    constexpr int VEC = 16 / sizeof(T);
+    __shared__ int rows[64];
+    const int I = blockIdx.x;
+    for (int q = threadIdx.x; q < per; q += blockDim.x) rows[q] = inv[int64_t(I) * per + q];
+    __syncthreads();
+    for (int c = col_begin + int(threadIdx.x) * VEC; c < col_end; c += int(blockDim.x) * VEC) {
+        vec_t acc = vec_t{};
+        for (int q = 0; q < per; ++q) acc += *reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q]) * ldy + (c - col_begin));
+        *reinterpret_cast<vec_t *>(out + int64_t(I) * ld + c) = acc;
     }
 }
 
@@ -204,28 +246,28 @@ __global__ __launch_bounds__(256) void k_one_electron(const T *X, T *Y, const ui
     }
 }
 
-template <typename T, int KS, int MBL>
+template <typename T, int KS, int MBL, bool STORE>
 hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
     constexpr int KP = 4 * KS, MP = 16 * MBL;
     constexpr int NE = KP > MP ? KP : MP;
     size_t lds = size_t(MP) * (KP + 1) * sizeof(T) + 3 * NE * sizeof(int);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ss<T, KS, MBL>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ss<T, KS, MBL, STORE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     constexpr int TW = 16 * (16 / sizeof(T));
-    const int items = a.ntiles * (kTileCols / TW);
+    const int items = (STORE ? a.tile_end - a.tile_begin : a.ntiles) * (kTileCols / TW);
     int ysplit = 1;
     while (int64_t(a.nK) * ysplit < 2048 && 4 * ysplit < items) ysplit *= 2;
-    hipLaunchKernelGGL((k_sigma_ss<T, KS, MBL>), dim3(a.nK, ysplit), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_sigma_ss<T, KS, MBL, STORE>), dim3(a.nK, ysplit), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, bool STORE>
 hipError_t dispatch_ss(const SsArgs<T> &a, hipStream_t s) {
     const int ks = (a.npv + 3) / 4;
     const int mbl = (a.npv + 15) / 16;
     // (KS, MBL) pairs for npv = C(m, 2), m = empty orbitals + 2
-#define CIS_SS(K, MB) if (ks == K && mbl == MB) return run_ss<T, K, MB>(a, s);
+#define CIS_SS(K, MB) if (ks == K && mbl == MB) return run_ss<T, K, MB, STORE>(a, s);
     CIS_SS(1, 1) CIS_SS(2, 1) CIS_SS(3, 1) CIS_SS(4, 1) CIS_SS(4, 2) CIS_SS(6, 2) CIS_SS(7, 2) CIS_SS(9, 3)
     CIS_SS(12, 3) CIS_SS(14, 4) CIS_SS(17, 5) CIS_SS(20, 5) CIS_SS(23, 6) CIS_SS(27, 7) CIS_SS(30, 8)
     CIS_SS(34, 9) CIS_SS(39, 10) CIS_SS(43, 11)
@@ -234,7 +276,8 @@ hipError_t dispatch_ss(const SsArgs<T> &a, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y, hipStream_t s) {
+hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y, void *Ys, int chunk,
+                       hipStream_t s) {
     const auto &S = ctx->sp[spin];
     const auto &L = ctx->pl[spin];
     const int other = 1 - spin;
@@ -267,14 +310,33 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
     a.nps = ctx->nps;
     a.nto = ctx->sp[other].ntype;
     a.ntiles = L.ntiles;
-    return dispatch_ss<T>(a, s);
+    if (!Ys) return dispatch_ss<T, false>(a, s);
+    // materialised form, one column chunk at a time: store rows K*npv+P, then gather per string
+    const int per = S.nel * (S.nel - 1) / 2;
+    const int64_t ld = L.ld[0];
+    for (int c0 = 0; c0 < ld; c0 += chunk) {
+        const int c1 = int(std::min<int64_t>(ld, c0 + chunk));
+        a.Ys = static_cast<T *>(Ys);
+        a.ldy = c1 - c0;
+        a.col_begin = c0;
+        a.tile_begin = c0 / kTileCols;
+        a.tile_end = c1 / kTileCols;
+        hipError_t e = dispatch_ss<T, true>(a, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_pair_gather<T>), dim3(S.nstr), dim3(256), 0, s, static_cast<const T *>(Ys),
+                           int64_t(c1 - c0), c0, c1, S.d_pair_inv, per, static_cast<T *>(Y), ld);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace
 
 hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *X, void *Y, int dtype,
-                                  hipStream_t s) {
-    return dtype == CISIGMA_FP32 ? same_spin_t<float>(ctx, spin, X, Y, s) : same_spin_t<double>(ctx, spin, X, Y, s);
+                                  hipStream_t s, void *Ys, int chunk) {
+    return dtype == CISIGMA_FP32 ? same_spin_t<float>(ctx, spin, X, Y, Ys, chunk, s)
+                                 : same_spin_t<double>(ctx, spin, X, Y, Ys, chunk, s);
 }
 
 }  // namespace cis

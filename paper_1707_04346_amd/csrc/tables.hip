@@ -146,6 +146,37 @@ __global__ void k_build_pairs(uint32_t *pairs, int nK, int kel, int npv, GasDesc
     pairs[tid] = out;
 }
 
+// inverse of the pair lists: for string I and each occupied pair p < r of I
+// (lexicographic), the row K*npv + e of the pair-list entry that produces I
+// from K = I - p - r, or -1 when I is not in the list of K.
+__global__ void k_build_pair_inv(int *inv, const uint32_t *str, int nstr, int nel, int npv, int n) {
+    const int per = nel * (nel - 1) / 2;
+    int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (per == 0 || tid >= int64_t(nstr) * per) return;
+    const int I = int(tid / per);
+    int slot = int(tid % per);
+    const uint32_t x = str[I];
+    // slot -> (a < b) over the occupied orbitals of I
+    int a = 0, rem = slot;
+    while (rem >= nel - 1 - a) { rem -= nel - 1 - a; ++a; }
+    const int b = a + 1 + rem;
+    uint32_t o = x;
+    for (int i = 0; i < a; ++i) o &= o - 1;
+    const int p = __ffs(o) - 1;
+    for (int i = a; i < b; ++i) o &= o - 1;
+    const int r = __ffs(o) - 1;
+    const uint32_t kb = x & ~(1u << p) & ~(1u << r);
+    // colex rank of K among (nel-2)-electron strings of n orbitals
+    uint32_t K = colex_rank(kb);
+    // positions of p and r among the empty orbitals of K
+    const int nv = n - (nel - 2);
+    const int ap = p - popc(kb & ((1u << p) - 1u));
+    const int ar = r - popc(kb & ((1u << r) - 1u));
+    const int e = ap * (nv - 1) - ap * (ap - 1) / 2 + (ar - ap - 1);
+    (void)nv;
+    inv[tid] = int(K) * npv + e;
+}
+
 // A_s[I] = sum_{p in I} h_pp + 1/2 sum_{p,q in I} ((pp|qq) - (pq|qp))
 __global__ void k_adiag(double *out, const uint32_t *str, int nstr, const double *h, const double *g4, int n) {
     int I = blockIdx.x * blockDim.x + threadIdx.x;
@@ -243,6 +274,15 @@ hipError_t build_string_tables(cisigma_ctx *ctx, int spin) {
         CIS_TRY(hipMalloc(&T.d_pairs, size_t(tot) * sizeof(uint32_t)));
         hipLaunchKernelGGL(k_build_pairs, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, ctx->stream, T.d_pairs,
                            T.nK, T.nel - 2, T.npv, g, tv);
+        CIS_TRY(hipGetLastError());
+    }
+    // inverse pair table (single-type spins only: the materialised same-spin path)
+    if (T.nel >= 2 && T.ntype == 1) {
+        int per = T.nel * (T.nel - 1) / 2;
+        int64_t tot = int64_t(T.nstr) * per;
+        CIS_TRY(hipMalloc(&T.d_pair_inv, size_t(tot) * sizeof(int)));
+        hipLaunchKernelGGL(k_build_pair_inv, dim3(unsigned((tot + 255) / 256)), dim3(256), 0, ctx->stream,
+                           T.d_pair_inv, T.d_str, T.nstr, T.nel, T.npv, g.n);
         CIS_TRY(hipGetLastError());
     }
     CIS_TRY(hipStreamSynchronize(ctx->stream));

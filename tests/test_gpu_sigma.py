@@ -170,3 +170,44 @@ def test_apply_on_a_side_stream():
         ctx.apply(C, S, stream=st)
     st.synchronize()
     assert rel(S.cpu().numpy(), s_ref) <= TOL64
+
+
+@pytest.mark.parametrize("case", [(6, 3, 3), (8, 4, 4), (9, 5, 4), (7, 2, 4), (10, 5, 5)],
+                         ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_sigma_general_path_matches_oracle(case, dtype):
+    """The general kernels (scatter with float atomics) that GAS spaces use,
+    forced on CAS spaces that would otherwise take the owner-computes path."""
+    cis = _cis()
+    norb, na, nb = case
+    ctx, ref = make(norb, na, nb, seed=11)
+    ctx.set_option(cis.OPT_SIGMA_PATH, 1)
+    c = si.ci_vector(ctx.ndet, 12)
+    s_ref = ref.sigma(c)
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert rel(gpu_sigma(ctx, c, dtype), s_ref) <= tol
+
+
+@pytest.mark.parametrize("case", [(6, 3, 3), (8, 4, 4), (10, 5, 5), (12, 6, 6)], ids=lambda c: f"n{c[0]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_cas_takes_the_fast_paths(case, dtype):
+    """One-block spaces run the owner-computes sigma_3 kernel and the
+    materialised same-spin products (no silent fallback), and stay exact."""
+    cis = _cis()
+    norb, na, nb = case
+    ctx, ref = make(norb, na, nb, seed=13)
+    c = si.ci_vector(ctx.ndet, 14)
+    s = gpu_sigma(ctx, c, dtype)
+    flags = ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64)
+    assert flags == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED, flags
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert rel(s, ref.sigma(c)) <= tol
+
+
+def test_gas_takes_the_general_path():
+    cis = _cis()
+    ctx, ref = make(7, 3, 3, gas=([2, 3, 2], [3, 5, 6], [4, 6, 6]))
+    c = si.ci_vector(ctx.ndet, 15)
+    s = gpu_sigma(ctx, c, torch.float64)
+    assert ctx.last_path(cis.FP64) == 0
+    assert rel(s, ref.sigma(c)) <= TOL64
