@@ -79,6 +79,42 @@ def cpu_baseline(spec, h, g, C_dev, target_s):
                       f"the {sp.ndet} rows of one sigma build"}
 
 
+def copy_calibration(torch, mib):
+    """A plain streaming kernel of known size (read mib MiB, write mib MiB),
+    launched so that a counter run (FETCH_SIZE / WRITE_SIZE) over this program
+    also measures what those counters read for a known number of bytes."""
+    n = mib * (1 << 20) // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+
+
+def stored_traffic(kernel_tag):
+    """HBM bytes per launch of the alpha-beta kernel from the committed counter
+    summary, or None when the kernel source changed after the counters were
+    taken (the summary records the source's SHA-256)."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_1707_04346_amd", "csrc", "sigma_ab.hip")
+    prof = os.path.join(ROOT, "profiles", f"{kernel_tag}_cas16_fp32_traffic.txt")
+    if not (os.path.exists(src) and os.path.exists(prof)):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    fields = {}
+    for ln in open(prof):
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("kernel_source_sha256") != sha:
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def davidson_runs(ctx, cis, nroots, tol):
     out = {}
     for mode, prec in (("fp64", cis.FP64), ("mixed_fp32", cis.FP32)):
@@ -107,6 +143,8 @@ def main():
     ap.add_argument("--davidson", action="store_true", help="also time Davidson to convergence, FP64 vs mixed")
     ap.add_argument("--nroots", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain copy kernel of this many MiB (for counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -144,14 +182,19 @@ def main():
     flops = 2.0 * M * K * ctx.ndet
     ab_s = pp32["sigma_ab"] / 1e3
     achieved = flops / ab_s / 1e12
+    owner = bool(path32 & cis.PATH_AB_OWNER)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
-                "frac": achieved / PEAK["fp32"], "traffic": None,
+                "frac": achieved / PEAK["fp32"],
+                "traffic": stored_traffic("k_sigma_ab_x" if owner else "k_sigma_ab") if args.workload == "cas16" else None,
                 "kernel": ("k_sigma_ab_x (owner-computes sigma_3: gathered C rows -> FP32 MFMA -> LDS scatter)"
-                           if path32 & cis.PATH_AB_OWNER else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
+                           if owner else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
                 "flops_per_launch": flops, "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
     if not args.no_fp64:
         extra["sigma_ab_tflops_fp64"] = flops / (pp64["sigma_ab"] / 1e3) / 1e12
+
+    if args.copy_calibration_mib > 0:
+        copy_calibration(torch, args.copy_calibration_mib)
 
     if args.davidson:
         extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol)

@@ -74,6 +74,8 @@ extern "C" {
 #define CISIGMA_OPT_VERBOSE 6      /* print one line per Davidson iteration to stderr when nonzero */
 #define CISIGMA_OPT_PROFILE 7      /* nonzero: time every pass of cisigma_apply with HIP events (resets the totals) */
 #define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels */
+#define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products: at most this many columns per chunk
+                                      (a positive multiple of 64); 0 (default): as many as fit in memory */
 
 /* passes of one cisigma_apply, in order, as reported by cisigma_pass_times */
 #define CISIGMA_PASS_LAYOUT_IN 0   /* C -> padded alpha-major and beta-major copies */

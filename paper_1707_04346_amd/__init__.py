@@ -18,6 +18,7 @@ FP64, FP32 = 0, 1
 OPT_PRECISION, OPT_MAX_SPACE, OPT_MAX_ITER, OPT_REFINE_EVERY, OPT_RESID_TOL, OPT_VERBOSE, OPT_PROFILE = 1, 2, 3, 4, 5, 6, 7
 PASSES = ["layout_in", "clear", "sigma_aa", "sigma_ab", "sigma_bb", "layout_out"]
 OPT_SIGMA_PATH = 8
+OPT_SS_CHUNK = 9
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")

@@ -101,7 +101,7 @@ void free_ctx(cisigma_ctx *c) {
     }
     hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
-    hipFree(c->plan.d_entries); hipFree(c->plan.d_thread_off);
+    hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
     for (auto e : c->prof_events) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
@@ -247,26 +247,32 @@ int build_layouts(cisigma_ctx *c) {
 
 // Scatter plan of the owner-computes sigma_3 kernel (one-block spaces of up
 // to 16 orbitals), built on the host from the device beta excitation lists.
+// Per 32-column tile of source strings Jb: every contribution (target Ib,
+// W element (kl, column), sign) -- the single beta excitations of each Jb and
+// the diagonal kk terms of Ib = Jb -- sorted by target; the sorted list is cut
+// at target-group boundaries into four wave ranges of at most 64*ew entries,
+// and lane l of a wave takes entries [l*ew, (l+1)*ew) of its range.  Entry
+// words as the kernel reads them: bit 31 group start, bits 16..30 target dword
+// index, bits 0..15 W byte offset with the sign in bit 0; padding entries start
+// a group, read W element 0 and write the spare slot ld.  One encoding per
+// element size.  Without a plan (a shape no kernel covers) the general kernel runs.
 int build_scatter_plan(cisigma_ctx *c) {
-    constexpr int NT = 32, WS = 33, EMAX = 24;
+    constexpr int NT = 32, WS = 33;
     const auto &B = c->sp[1];
     const int ld = c->pl[0].ld[0];
-    if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || ld >= 32768 || (c->npair + 1) * WS >= 8192)
+    const int mp = 32 * ((c->npair + 31) / 32);
+    if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || size_t(mp) * WS * 8 >= 65536 ||
+        2 * (size_t(ld) + 1) >= 32768)
         return CISIGMA_OK;
     std::vector<uint32_t> exc(size_t(B.nstr) * B.nexc), str(B.nstr);
     HIP_OR_FAIL(c, hipMemcpy(exc.data(), B.d_exc, exc.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
     HIP_OR_FAIL(c, hipMemcpy(str.data(), B.d_str, str.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
-    cis::ScatterPlan &P = c->plan;
-    P.ntile = ld / NT;
-    const uint32_t nulle = (1u << 29) | (uint32_t(ld) << 13) | uint32_t(c->npair * WS);
-    std::vector<uint32_t> entries, toff;
-    entries.reserve(size_t(B.nstr) * (B.nexc + c->nb) * 3 / 2);
-    toff.reserve(size_t(P.ntile) * 257);
-    struct Item { uint32_t tgt, off, neg; };
-    std::vector<Item> tile;
-    int emax = 0;
-    for (int t = 0; t < P.ntile; ++t) {
-        tile.clear();
+    struct Item { uint32_t tgt, widx, neg, start; };
+    const int ntile = ld / NT;
+    std::vector<std::vector<Item>> tiles(ntile);
+    int need = 1;
+    for (int t = 0; t < ntile; ++t) {
+        auto &tile = tiles[t];
         for (int col = 0; col < NT; ++col) {
             const int Jb = t * NT + col;
             if (Jb >= B.nstr) break;
@@ -274,57 +280,73 @@ int build_scatter_plan(cisigma_ctx *c) {
                 const uint32_t w = exc[size_t(Jb) * B.nexc + e];
                 if (w == cis::kExcNone) continue;
                 const int k = (w >> 6) & 31, l = (w >> 1) & 31;
-                tile.push_back({w >> 11, uint32_t(cis::pair_ge(k, l) * WS + col), w & 1u});
+                tile.push_back({w >> 11, uint32_t(cis::pair_ge(k, l) * WS + col), w & 1u, 0u});
             }
             for (uint32_t b = str[Jb]; b; b &= b - 1) {
                 const int k = __builtin_ctz(b);
-                tile.push_back({uint32_t(Jb), uint32_t((k * (k + 1) / 2 + k) * WS + col), 0u});
+                tile.push_back({uint32_t(Jb), uint32_t(cis::pair_ge(k, k) * WS + col), 0u, 0u});
             }
         }
         std::stable_sort(tile.begin(), tile.end(), [](const Item &a, const Item &b) { return a.tgt < b.tgt; });
-        // target groups, then the smallest range capacity (multiple of 4) that
-        // packs them into at most 256 ranges
-        std::vector<std::pair<size_t, size_t>> groups;   // (first, count)
-        for (size_t i = 0; i < tile.size();) {
+        for (size_t i = 0; i < tile.size(); ++i) tile[i].start = (i == 0 || tile[i].tgt != tile[i - 1].tgt);
+        // smallest ew whose wave capacity 64*ew packs the groups into four ranges
+        auto fits = [&](size_t cap) {
+            int ranges = 1;
+            size_t cur = 0;
+            for (size_t i = 0; i < tile.size();) {
+                size_t j = i + 1;
+                while (j < tile.size() && !tile[j].start) ++j;
+                const size_t g = j - i;
+                if (g > cap) return false;
+                if (cur + g > cap) { ++ranges; cur = 0; }
+                cur += g;
+                i = j;
+            }
+            return ranges <= 4;
+        };
+        while (!fits(size_t(64) * need)) ++need;
+    }
+    const int ew = cis::sigma_ab_owner_width(c->sp[0].nexc, c->npair, need);
+    if (ew == 0) return CISIGMA_OK;
+    const size_t per_tile = size_t(4) * ew * 64;
+    std::vector<uint32_t> plan[2] = {std::vector<uint32_t>(per_tile * ntile), std::vector<uint32_t>(per_tile * ntile)};
+    for (int es_i = 0; es_i < 2; ++es_i) {
+        const uint32_t es = es_i == 0 ? 8 : 4;   // [0]: FP64, [1]: FP32
+        const uint32_t pad = (1u << 31) | ((uint32_t(ld) * es / 4) << 16);
+        std::fill(plan[es_i].begin(), plan[es_i].end(), pad);
+    }
+    for (int t = 0; t < ntile; ++t) {
+        const auto &tile = tiles[t];
+        const size_t cap = size_t(64) * ew;
+        size_t i = 0;
+        for (int wv = 0; wv < 4 && i < tile.size(); ++wv) {
+            // this wave's range: whole groups up to the capacity
             size_t j = i;
-            while (j < tile.size() && tile[j].tgt == tile[i].tgt) ++j;
-            groups.push_back({i, j - i});
+            while (j < tile.size()) {
+                size_t g = j + 1;
+                while (g < tile.size() && !tile[g].start) ++g;
+                if (g - i > cap) break;
+                j = g;
+            }
+            for (size_t e = i; e < j; ++e) {
+                const size_t r = e - i;
+                const size_t lane = r / ew, q = r % ew;
+                const size_t slot = size_t(t) * per_tile + (size_t(wv) * ew + q) * 64 + lane;
+                const Item &it = tile[e];
+                for (int es_i = 0; es_i < 2; ++es_i) {
+                    const uint32_t es = es_i == 0 ? 8 : 4;
+                    plan[es_i][slot] = (it.start << 31) | ((it.tgt * es / 4) << 16) | (it.widx * es) | it.neg;
+                }
+            }
             i = j;
         }
-        auto r4 = [](size_t x) { return (x + 3) / 4 * 4; };
-        auto ranges_for = [&](size_t cap) {
-            size_t nr = 0, cur = 0;
-            for (auto &g : groups) {
-                if (r4(g.second) > cap) return size_t(1) << 30;
-                if (cur > 0 && r4(cur + g.second) > cap) { ++nr; cur = 0; }
-                cur += g.second;
-            }
-            return nr + (cur > 0);
-        };
-        size_t cap = 4;
-        while (ranges_for(cap) > 256) cap += 4;
-        size_t gi = 0;
-        for (int th = 0; th < 256; ++th) {
-            toff.push_back(uint32_t(entries.size()));
-            size_t cur = 0;
-            while (gi < groups.size() && (cur == 0 || r4(cur + groups[gi].second) <= cap)) {
-                const auto &g = groups[gi++];
-                for (size_t q = g.first; q < g.first + g.second; ++q)
-                    entries.push_back((uint32_t(q == g.first) << 29) | (tile[q].neg << 28) | (tile[q].tgt << 13) | tile[q].off);
-                cur += g.second;
-            }
-            size_t cnt = cur;
-            while (cnt % 4) { entries.push_back(nulle); ++cnt; }
-            emax = std::max(emax, int(cnt));
-        }
-        if (gi != groups.size()) return CISIGMA_OK;   // cannot happen: ranges_for(cap) <= 256
-        toff.push_back(uint32_t(entries.size()));
+        if (i != tile.size()) return CISIGMA_OK;   // cannot happen: ew >= need
     }
-    if (emax > EMAX) return CISIGMA_OK;   // the kernel's register window is too small: no plan
-    P.emax = emax;
-    entries.insert(entries.end(), 4, nulle);
-    HIP_OR_FAIL(c, upload(&P.d_entries, entries), "init: scatter plan");
-    HIP_OR_FAIL(c, upload(&P.d_thread_off, toff), "init: scatter plan");
+    cis::ScatterPlan &P = c->plan;
+    HIP_OR_FAIL(c, upload(&P.d_entries[0], plan[0]), "init: scatter plan");
+    HIP_OR_FAIL(c, upload(&P.d_entries[1], plan[1]), "init: scatter plan");
+    P.ntile = ntile;
+    P.ew = ew;
     return CISIGMA_OK;
 }
 
@@ -392,12 +414,13 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
         HIP_OR_FAIL(c, launch_fill(spin == 0 ? W.sp : W.st, c->pl[spin].size, dtype, s), "apply: fill");
     }
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_CLEAR), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, W.sp, dtype, s, mat ? W.ys : nullptr, W.ys_chunk),
+    const int chunk = c->ss_chunk > 0 ? std::min(c->ss_chunk, W.ys_chunk) : W.ys_chunk;
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, W.sp, dtype, s, mat ? W.ys : nullptr, chunk),
                 "apply: sigma_2 (alpha-alpha)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AA), "apply: profiling events");
     HIP_OR_FAIL(c, launch_sigma_ab(c, W.cp, W.sp, dtype, s), "apply: sigma_3 (alpha-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AB), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s, mat ? W.ys : nullptr, W.ys_chunk),
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s, mat ? W.ys : nullptr, chunk),
                 "apply: sigma_1 (beta-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_BB), "apply: profiling events");
     HIP_OR_FAIL(c, launch_gather_out(c, W.sp, W.st, sigma, dtype, s), "apply: layout conversion");
@@ -714,6 +737,11 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
         case CISIGMA_OPT_SIGMA_PATH:
             if (value != 0 && value != 1) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0 or 1");
             ctx->ab_mode = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_SS_CHUNK:
+            if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
+            ctx->ss_chunk = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_PROFILE:
             prof_reset(ctx);

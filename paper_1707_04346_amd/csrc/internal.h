@@ -120,10 +120,9 @@ struct BlockTilesDev {
 // entry = first-of-group << 29 | negative << 28 | target << 13 | (kl*33 + column)
 // no-op entry = 1 << 29 | ld << 13 | npair*33 (zero row of W, spare sigma slot).
 struct ScatterPlan {
-    uint32_t *d_entries = nullptr;
-    uint32_t *d_thread_off = nullptr;  // [ntile][257] entry offsets (multiples of 4)
+    uint32_t *d_entries[2] = {nullptr, nullptr};  // [FP64, FP32] entry encodings, [ntile][4][ew][64]
     int ntile = 0;
-    int emax = 0;                      // longest padded per-thread range
+    int ew = 0;                                    // entries per lane and tile (0: no plan)
 };
 
 struct Workspace {
@@ -173,6 +172,7 @@ struct cisigma_ctx {
     int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
     int ab_mode = 0;
+    int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)
     // per-pass event timing of apply (CISIGMA_OPT_PROFILE)
     bool profile = false;
     std::vector<hipEvent_t> prof_events;   // pending pairs, (CISIGMA_NPASS + 1) events per call
@@ -193,6 +193,13 @@ hipError_t build_diag_tables(cisigma_ctx *ctx);
 int sigma_ab_kp(int npair);
 hipError_t launch_fill(void *x, int64_t n, int dtype, hipStream_t s);
 hipError_t launch_sigma_ab(const cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+// owner-computes sigma_3 (one-block spaces with a scatter plan): false when the
+// shape has no compiled kernel (nothing launched), else *err is the launch status
+bool launch_sigma_ab_owner(const cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s,
+                           hipError_t *err);
+// plan width (entries per lane and tile) the owner-computes kernel uses for a
+// shape that needs `need`; 0 when no compiled kernel covers it
+int sigma_ab_owner_width(int anexc, int npair, int need);
 // Ys == nullptr: scatter with atomics into Y (Y holds what to add to).
 // Ys != nullptr (one-type spins): materialise into Ys chunk by chunk (chunk
 // columns, a multiple of 64) and gather into Y, overwriting Y.

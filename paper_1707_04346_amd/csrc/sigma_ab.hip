@@ -16,35 +16,13 @@
 // sum_kl v(kl) D(kl, Ib), v(kl) = sum_{j in Ja} (jj|kl); they are summed on the
 // vector ALU while D is gathered.
 #include "internal.h"
+#include "mfma.h"
 
 #include <type_traits>
 
 namespace cis {
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-typedef double double2_t __attribute__((ext_vector_type(2)));
-template <> struct Mfma<float> {
-    using acc_t = floatx4;
-    using vec_t = floatx4;
-    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // accumulator register r of a lane holds output row 4*(lane/16) + r, column lane%16
-    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-template <> struct Mfma<double> {
-    using acc_t = doublex4;
-    using vec_t = double2_t;
-    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // the FP64 form spaces a lane's rows by 4: register r holds row lane/16 + 4*r
-    static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
 
 template <typename T>
 struct AbArgs {
@@ -273,237 +251,6 @@ __global__ __launch_bounds__(256) void k_sigma_ab_direct(AbArgs<T> p, int64_t to
     unsafeAtomicAdd(p.sp + so + int64_t(Ia - p.astart[ta]) * p.ld[tb] + (Ib - p.bstart[tb]), acc);
 }
 
-// ---------------------------------------------------------------------------
-// Owner-computes form of sigma_3 for one-block (CAS) spaces.  One workgroup
-// per output alpha string Ia holds the whole sigma row of Ia in LDS:
-//
-//   R(a, Jb)  = C(Ja_a, Jb)        a = the single alpha excitations Ja_a of Ia, plus Ia itself
-//   W(kl, Jb) = sum_a A(kl, a) R(a, Jb),  A(kl, a) = s_a (i_a j_a|kl),  A(kl, Ia) = sum_{j in Ia} (jj|kl)
-//   sigma(Ia, Ib) += sum_{(kl, Jb): Ib = E_kl Jb} <Ib|E_kl|Jb> W(kl, Jb)       (LDS float atomics)
-//
-// The gathered rows R are coalesced row reads of C; the contraction runs on
-// the matrix cores; the beta-side scatter stays in LDS, so the kernel makes
-// no global atomics and writes each sigma row once.
-template <typename T>
-struct AbxArgs {
-    const T *cp;           // C, alpha-major padded (row stride ld)
-    T *sp;                 // sigma accumulator, same layout (read, then overwritten)
-    const uint32_t *aexc;  // [Na][anexc]
-    const uint32_t *bexc;  // [Nb][bnexc]
-    const uint32_t *astr, *bstr;
-    const T *gp;           // [n*n][kp]
-    const uint32_t *plan;        // scatter plan entries (tile width NT)
-    const uint32_t *plan_off;    // [ntile][257]
-    int anexc, bnexc, n, kp, npair, Na, Nb, ld;
-};
-
-// KS: k steps over the gathered rows (4*KS >= anexc+1); RBW: 16-row blocks of
-// kl per wave.  32-column tiles; the four waves are 2 column blocks x 2
-// row-block groups.  The gathered-row tile (B) and the W tile share one LDS
-// buffer, which keeps a workgroup at ~71 KB for CAS(16,16) in FP32 so two
-// workgroups share a CU and one's scatter overlaps the other's matrix work.
-// Per tile: the next tile's rows and this tile's scatter plan are loaded to
-// registers while the matrix cores run.
-constexpr int kAbxNT = 32;
-constexpr int kAbxWS = kAbxNT + 1;       // W row stride
-constexpr int kAbxEmax = 24;             // plan entries per thread and tile (register window)
-
-template <typename T, int KS, int RBW>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_sigma_ab_x(AbxArgs<T> p) {
-    using M = Mfma<T>;
-    using acc_t = typename M::acc_t;
-    using vec_t = typename M::vec_t;
-    constexpr int KP = 4 * KS;
-    constexpr int NT = kAbxNT;
-    constexpr int VEC = 16 / sizeof(T);
-    constexpr int BS = NT + (sizeof(T) == 4 ? 16 : 0);   // B row stride (bank spread for MFMA reads)
-    constexpr int WS = kAbxWS;
-    constexpr int MP = 16 * RBW * 2;                       // W rows (>= npair + 1; rows >= npair stay zero)
-    constexpr int EMAX = kAbxEmax;
-    constexpr int VPR = NT / VEC;                          // 16-byte vectors per gathered row
-    constexpr int NPRE = (KP * VPR + 255) / 256;           // prefetched vectors per thread
-    constexpr int USZ = KP * BS > MP * WS ? KP * BS : MP * WS;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *U = reinterpret_cast<T *>(smem_raw);                    // B tile, then W tile
-    T *sig = U + USZ;                                          // [ld + 1]; slot ld absorbs no-op entries
-    int *jrow = reinterpret_cast<int *>(sig + p.ld + 4);       // [KP]
-
-    const int Ia = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int cb = wave & 1, grp = wave >> 1;
-    const int64_t rowoff = int64_t(Ia) * p.ld;
-    for (int c = tid * VEC; c < p.ld; c += 256 * VEC)
-        *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
-    if (tid == 0) sig[p.ld] = T(0);
-    for (int k = tid; k < KP; k += 256) {
-        int J = -1;
-        if (k < p.anexc) {
-            uint32_t e = p.aexc[int64_t(Ia) * p.anexc + k];
-            J = (e == kExcNone) ? -1 : int(e >> 11);
-        } else if (k == p.anexc) {
-            J = Ia;
-        }
-        jrow[k] = J;
-    }
-    // A fragments: row m (kl) = 16*rb + lane%16, column k (gathered row) = 4t + lane/16
-    T A[RBW][KS];
-    const uint32_t xa = p.astr[Ia];
-#pragma unroll
-    for (int t = 0; t < KS; ++t) {
-        const int k = 4 * t + (lane >> 4);
-        const T *g = nullptr;
-        T sg = 0;
-        if (k < p.anexc) {
-            uint32_t e = p.aexc[int64_t(Ia) * p.anexc + k];
-            if (e != kExcNone) {
-                const int i = (e >> 6) & 31, j = (e >> 1) & 31;   // <Ia|E_ij|Ja>, Ja = Ia - i + j
-                g = p.gp + int64_t(i * p.n + j) * p.kp;
-                sg = (e & 1) ? T(-1) : T(1);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < RBW; ++r) {
-            const int m = (grp * RBW + r) * 16 + (lane & 15);
-            T val = 0;
-            if (m < p.npair) {
-                if (g) {
-                    val = sg * g[m];
-                } else if (k == p.anexc) {
-                    for (uint32_t b = xa; b; b &= b - 1) {
-                        const int j = __ffs(b) - 1;
-                        val += p.gp[int64_t(j * p.n + j) * p.kp + m];
-                    }
-                }
-            }
-            A[r][t] = val;
-        }
-    }
-    __syncthreads();
-
-    // gathered rows of one tile: vector v -> row v / VPR, columns (v % VPR) * VEC
-    auto fetch = [&](int c0, vec_t *buf) {
-#pragma unroll
-        for (int q = 0; q < NPRE; ++q) {
-            const int v = tid + q * 256;
-            vec_t x = vec_t{};
-            if (v < KP * VPR) {
-                const int J = jrow[v / VPR];
-                if (J >= 0) x = *reinterpret_cast<const vec_t *>(p.cp + int64_t(J) * p.ld + c0 + (v % VPR) * VEC);
-            }
-            buf[q] = x;
-        }
-    };
-    auto stash = [&](const vec_t *buf) {
-#pragma unroll
-        for (int q = 0; q < NPRE; ++q) {
-            const int v = tid + q * 256;
-            if (v < KP * VPR) *reinterpret_cast<vec_t *>(U + (v / VPR) * BS + (v % VPR) * VEC) = buf[q];
-        }
-    };
-    vec_t bpre[NPRE];
-    fetch(0, bpre);
-    stash(bpre);
-    __syncthreads();
-
-    // no-op plan entry: the zero row of W, the spare sigma slot, starts a group
-    const uint32_t nulle = (1u << 29) | (uint32_t(p.ld) << 13) | uint32_t(p.npair * WS);
-    const int ntile = p.ld / NT;
-    for (int tile = 0; tile < ntile; ++tile) {
-        const int c0 = tile * NT;
-        // ---- in flight during the matrix work: next tile's rows, this tile's plan
-        if (tile + 1 < ntile) fetch(c0 + NT, bpre);
-        const uint32_t pbeg = p.plan_off[tile * 257 + tid];
-        const int pn = int(p.plan_off[tile * 257 + tid + 1] - pbeg);
-        uint4 ent[EMAX / 4];
-#pragma unroll
-        for (int q = 0; q < EMAX / 4; ++q)
-            ent[q] = 4 * q < pn ? *reinterpret_cast<const uint4 *>(p.plan + pbeg + 4 * q)
-                               : make_uint4(nulle, nulle, nulle, nulle);
-        // ---- W = A R on the matrix cores
-        acc_t acc[RBW];
-#pragma unroll
-        for (int r = 0; r < RBW; ++r) acc[r] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int t = 0; t < KS; ++t) {
-            const T b = U[(4 * t + (lane >> 4)) * BS + cb * 16 + (lane & 15)];
-#pragma unroll
-            for (int r = 0; r < RBW; ++r) acc[r] = M::op(A[r][t], b, acc[r]);
-        }
-        __syncthreads();                       // everyone is done reading B
-#pragma unroll
-        for (int r = 0; r < RBW; ++r)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                U[((grp * RBW + r) * 16 + M::out_row(lane, i)) * WS + cb * 16 + (lane & 15)] = acc[r][i];
-        __syncthreads();
-        // ---- beta-side scatter into the LDS sigma row.  The plan gives this
-        // thread every contribution to its targets in this tile (sorted, whole
-        // groups) and no other thread touches them: all reads first, then for
-        // every entry store old + running group sum (a group's last store wins).
-        uint32_t w[EMAX];
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) w[q] = ent[q / 4][q % 4];
-        T val[EMAX], old[EMAX];
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) {
-            val[q] = U[w[q] & 8191u];
-            old[q] = sig[(w[q] >> 13) & 32767u];
-        }
-        T run = 0;
-#pragma unroll
-        for (int q = 0; q < EMAX; ++q) {
-            run = ((w[q] >> 29) & 1u) ? T(0) : run;
-            run += ((w[q] >> 28) & 1u) ? -val[q] : val[q];
-            sig[(w[q] >> 13) & 32767u] = old[q] + run;
-        }
-        __syncthreads();                       // W consumed
-        if (tile + 1 < ntile) stash(bpre);
-        __syncthreads();
-    }
-    for (int cc = tid * VEC; cc < p.ld; cc += 256 * VEC)
-        *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
-}
-
-template <typename T, int KS, int RBW>
-size_t abx_lds_t(int ld) {
-    constexpr int KP = 4 * KS, BS = kAbxNT + (sizeof(T) == 4 ? 16 : 0), MP = 16 * RBW * 2;
-    constexpr int USZ = KP * BS > MP * kAbxWS ? KP * BS : MP * kAbxWS;
-    return size_t(USZ + ld + 4) * sizeof(T) + KP * sizeof(int);
-}
-
-template <typename T, int KS, int RBW>
-hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s) {
-    const size_t lds = abx_lds_t<T, KS, RBW>(a.ld);
-    if (lds > 160 * 1024 || 32 * RBW < a.npair + 1 || 4 * KS < a.anexc + 1) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RBW>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RBW>), dim3(a.Na), dim3(256), lds, s, a);
-    return hipGetLastError();
-}
-
-// (KS, row blocks) of the owner-computes kernel for the CAS(n, n/2) shapes
-// n = 4..16; returns false when no instantiation covers the shape
-template <typename T>
-bool dispatch_abx(const AbxArgs<T> &a, hipStream_t s, hipError_t *err) {
-    const int ks = (a.anexc + 1 + 3) / 4;
-    const int rbw = (a.npair + 1 + 31) / 32;   // 16-row blocks per group, two groups, one spare zero row
-#define CIS_ABX(K, R) \
-    if (ks == K && rbw == R) { *err = run_abx<T, K, R>(a, s); return true; }
-    CIS_ABX(2, 1) CIS_ABX(3, 1) CIS_ABX(4, 1) CIS_ABX(5, 2) CIS_ABX(6, 2) CIS_ABX(7, 2) CIS_ABX(8, 3)
-    CIS_ABX(10, 3) CIS_ABX(11, 3) CIS_ABX(13, 4) CIS_ABX(15, 4) CIS_ABX(17, 5)
-#undef CIS_ABX
-    return false;
-}
-
-template <typename T>
-size_t abx_lds_for(int ld, int npair, int anexc) {
-    const int ks = (anexc + 1 + 3) / 4, rbw = (npair + 1 + 31) / 32;
-    const int KP = 4 * ks, BS = kAbxNT + (sizeof(T) == 4 ? 16 : 0), MP = 32 * rbw;
-    const int usz = KP * BS > MP * kAbxWS ? KP * BS : MP * kAbxWS;
-    return size_t(usz + ld + 4) * sizeof(T) + KP * sizeof(int);
-}
-
 template <typename T, int KS, int RBW, int NT>
 hipError_t run_ab(const AbArgs<T> &a, hipStream_t s) {
     constexpr int KP = 4 * KS;
@@ -581,19 +328,10 @@ hipError_t sigma_ab_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStrea
     int ks = ks_for(ctx->kp);
     a.kp = ctx->kp;
     if (ctx->cas && ctx->ab_mode != 1) {
-        AbxArgs<T> x{};
-        x.cp = a.cp; x.sp = a.sp; x.aexc = a.aexc; x.bexc = a.bexc; x.astr = a.astr; x.bstr = a.bstr; x.gp = a.gp;
-        x.anexc = a.anexc; x.bnexc = a.bnexc; x.n = a.n; x.kp = a.kp; x.npair = ctx->npair;
-        x.Na = a.Na; x.Nb = a.Nb; x.ld = L.ld[0];
-        const ScatterPlan &P = ctx->plan;
-        x.plan = P.d_entries;
-        x.plan_off = P.d_thread_off;
-        if (P.d_entries && abx_lds_for<T>(x.ld, x.npair, x.anexc) <= 160 * 1024) {
-            hipError_t e = hipSuccess;
-            if (dispatch_abx<T>(x, s, &e)) {
-                if (e == hipSuccess) const_cast<cisigma_ctx *>(ctx)->last_path[sizeof(T) == 4] |= CISIGMA_PATH_AB_OWNER;
-                return e;
-            }
+        hipError_t e = hipSuccess;
+        if (launch_sigma_ab_owner(ctx, cp, sp, sizeof(T) == 4 ? CISIGMA_FP32 : CISIGMA_FP64, s, &e)) {
+            if (e == hipSuccess) const_cast<cisigma_ctx *>(ctx)->last_path[sizeof(T) == 4] |= CISIGMA_PATH_AB_OWNER;
+            return e;
         }
     }
     const int mb = (A.nexc + 15) / 16;   // 16-row blocks of alpha excitations

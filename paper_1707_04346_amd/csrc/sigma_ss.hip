@@ -18,6 +18,7 @@
 //
 // N = 1 has no pairs; its one-electron part is applied by k_one_electron.
 #include "internal.h"
+#include "mfma.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -25,29 +26,6 @@
 namespace cis {
 namespace {
 
-typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef double doublex4 __attribute__((ext_vector_type(4)));
-
-template <typename T> struct Mfma;
-template <> struct Mfma<float> {
-    using acc_t = floatx4;
-    using vec_t = floatx4;   // 16-byte B load: 4 columns
-    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    // accumulator register r of a lane holds output row 4*(lane/16) + r, column lane%16
-    static __device__ __forceinline__ int out_row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
-typedef double double2_t __attribute__((ext_vector_type(2)));
-template <> struct Mfma<double> {
-    using acc_t = doublex4;
-    using vec_t = double2_t;  // 16-byte B load: 2 columns
-    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    // the FP64 form spaces a lane's rows by 4: register r holds row lane/16 + 4*r
-    static __device__ __forceinline__ int out_row(int lane, int r) { return (lane >> 4) + 4 * r; }
-};
 
 template <typename T>
 struct SsArgs {
