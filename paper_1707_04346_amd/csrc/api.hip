@@ -260,7 +260,7 @@ int build_scatter_plan(cisigma_ctx *c) {
     constexpr int NT = 32, WS = 33;
     const auto &B = c->sp[1];
     const int ld = c->pl[0].ld[0];
-    const int mp = 32 * ((c->npair + 31) / 32);
+    const int mp = 16 * ((c->npair + 15) / 16);
     if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || size_t(mp) * WS * 8 >= 65536 ||
         2 * (size_t(ld) + 1) >= 32768)
         return CISIGMA_OK;
@@ -354,7 +354,10 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
     if (W.ready) return CISIGMA_OK;
     size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
-    size_t na = size_t(std::max<int64_t>(c->pl[0].size, 1)) * es;
+    // one-block spaces: one extra zero row after the alpha-major copy (rows the
+    // owner-computes sigma_3 kernel reads in place of missing excitations)
+    const int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
+    size_t na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
     size_t nb = size_t(std::max<int64_t>(c->pl[1].size, 1)) * es;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2 * (na + nb) + (64u << 20) > fr)

@@ -97,71 +97,44 @@ __device__ __forceinline__ double flip_if(double u, uint32_t w) {
     return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(u)) ^ m));
 }
 
-// KS: k steps over the gathered rows (4*KS >= anexc+1); RBW: 16-row blocks of
-// kl per wave; EW: plan entries per lane and tile.  The four waves are 2 column
-// blocks x 2 row-block groups of the 32-column tile.  The gathered-row tile (B)
-// and the W tile share one LDS buffer, which keeps a workgroup at ~73 KB for
-// CAS(16,16) in FP32 so two workgroups share a CU and one's scatter overlaps the
-// other's matrix work.  The next tile's rows and this tile's plan are loaded to
-// registers while the matrix cores run.
-template <typename T, int KS, int RBW, int EW>
-__global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_sigma_ab_x(AbxArgs<T> p) {
-    using M = Mfma<T>;
-    using acc_t = typename M::acc_t;
-    using vec_t = typename M::vec_t;
-    constexpr int KP = 4 * KS;
-    constexpr int NT = kAbxNT;
-    constexpr int VEC = 16 / sizeof(T);
-    constexpr int BS = NT + (sizeof(T) == 4 ? 16 : 0);   // B row stride (bank spread for MFMA reads)
-    constexpr int WS = kAbxWS;
-    constexpr int MP = 16 * RBW * 2;                       // W rows (>= npair; rows >= npair are zero)
-    constexpr int VPR = NT / VEC;                          // 16-byte vectors per gathered row
-    constexpr int NPRE = (KP * VPR + 255) / 256;           // prefetched vectors per thread
-    constexpr int USZ = KP * BS > MP * WS ? KP * BS : MP * WS;
-    constexpr int PT = 4 * EW * 64;                        // plan words per tile
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *U = reinterpret_cast<T *>(smem_raw);                    // B tile, then W tile
-    T *sig = U + USZ;                                          // [ld + 1]; slot ld takes the padding entries
-    int *jrow = reinterpret_cast<int *>(sig + p.ld + 4);       // [KP]
+// ---- pieces of the two kernel forms ------------------------------------------
+//
+// KS: k steps over the gathered rows (4*KS >= anexc+1); RB: 16-row blocks of kl
+// (16*RB >= npair); RBW: row blocks per producing wave; EW: plan entries per
+// lane and tile.  A producing wave owns one 16-column half of the 32-column
+// tile (cb) and a run of row blocks [rb0, rb0 + nrb).
 
-    const int Ia = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int cb = wave & 1, grp = wave >> 1;
-    const int64_t rowoff = int64_t(Ia) * p.ld;
-    for (int c = tid * VEC; c < p.ld; c += 256 * VEC)
-        *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
-    if (tid == 0) sig[p.ld] = T(0);
-    for (int k = tid; k < KP; k += 256) {
-        int J = -1;
-        if (k < p.anexc) {
-            uint32_t e = p.aexc[int64_t(Ia) * p.anexc + k];
-            J = (e == kExcNone) ? -1 : int(e >> 11);
-        } else if (k == p.anexc) {
-            J = Ia;
-        }
-        jrow[k] = J;
-    }
-    // A fragments: row m (kl) = 16*rb + lane%16, column k (gathered row) = 4t + lane/16
-    T A[RBW][KS];
+// A fragments of Ia for the wave's row blocks -- row m (kl) = 16*(rb0 + r) +
+// lane%16, column k = 4t + lane/16 -- and the byte offsets of the gathered rows
+// (missing excitations read the zero row Na).
+template <typename T, int KS, int RBW>
+__device__ __forceinline__ void abx_fragments(const AbxArgs<T> &p, int Ia, int lane, int cb, int rb0, int nrb,
+                                              T (&A)[RBW][KS], uint32_t (&boff)[KS]) {
     const uint32_t xa = p.astr[Ia];
+    const uint32_t col = uint32_t(cb * 16 + (lane & 15));
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
         const int k = 4 * t + (lane >> 4);
+        int J = p.Na;
         const T *g = nullptr;
         T sg = 0;
         if (k < p.anexc) {
-            uint32_t e = p.aexc[int64_t(Ia) * p.anexc + k];
+            const uint32_t e = p.aexc[int64_t(Ia) * p.anexc + k];
             if (e != kExcNone) {
+                J = int(e >> 11);
                 const int i = (e >> 6) & 31, j = (e >> 1) & 31;   // <Ia|E_ij|Ja>, Ja = Ia - i + j
                 g = p.gp + int64_t(i * p.n + j) * p.kp;
                 sg = (e & 1) ? T(-1) : T(1);
             }
+        } else if (k == p.anexc) {
+            J = Ia;
         }
+        boff[t] = (uint32_t(J) * uint32_t(p.ld) + col) * uint32_t(sizeof(T));
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-            const int m = (grp * RBW + r) * 16 + (lane & 15);
+            const int m = (rb0 + r) * 16 + (lane & 15);
             T val = 0;
-            if (m < p.npair) {
+            if (r < nrb && m < p.npair) {
                 if (g) {
                     val = sg * g[m];
                 } else if (k == p.anexc) {
@@ -174,134 +147,248 @@ __global__ __launch_bounds__(256, sizeof(T) == 4 ? 2 : 1) void k_sigma_ab_x(AbxA
             A[r][t] = val;
         }
     }
-    __syncthreads();
+}
 
-    // gathered rows of one tile: vector v -> row v / VPR, columns (v % VPR) * VEC
-    auto fetch = [&](int c0, vec_t *buf) {
+template <typename T, int KS>
+__device__ __forceinline__ void abx_load(const AbxArgs<T> &p, const uint32_t (&boff)[KS], int tile, T (&b)[KS]) {
+    const char *base = reinterpret_cast<const char *>(p.cp + int64_t(tile) * kAbxNT);
 #pragma unroll
-        for (int q = 0; q < NPRE; ++q) {
-            const int v = tid + q * 256;
-            vec_t x = vec_t{};
-            if (v < KP * VPR) {
-                const int J = jrow[v / VPR];
-                if (J >= 0) x = *reinterpret_cast<const vec_t *>(p.cp + int64_t(J) * p.ld + c0 + (v % VPR) * VEC);
-            }
-            buf[q] = x;
-        }
-    };
-    auto stash = [&](const vec_t *buf) {
-#pragma unroll
-        for (int q = 0; q < NPRE; ++q) {
-            const int v = tid + q * 256;
-            if (v < KP * VPR) *reinterpret_cast<vec_t *>(U + (v / VPR) * BS + (v % VPR) * VEC) = buf[q];
-        }
-    };
-    vec_t bpre[NPRE];
-    fetch(0, bpre);
-    stash(bpre);
-    __syncthreads();
+    for (int t = 0; t < KS; ++t) b[t] = *reinterpret_cast<const T *>(base + boff[t]);
+}
 
-    const char *ub = reinterpret_cast<const char *>(U);
-    char *sb = reinterpret_cast<char *>(sig);
-    const uint32_t *pw = p.plan + wave * (EW * 64) + lane;
-    const int ntile = p.ld / NT;
-    for (int tile = 0; tile < ntile; ++tile) {
-        const int c0 = tile * NT;
-        // ---- in flight during the matrix work: next tile's rows, this tile's plan
-        if (tile + 1 < ntile) fetch(c0 + NT, bpre);
-        uint32_t ent[EW];
+// W = A R on the matrix cores for the rows held in b; as each k step is
+// consumed, b[t] is reloaded with the rows of tile `next` (always a valid tile).
+template <typename T, int KS, int RBW>
+__device__ __forceinline__ void abx_products(const AbxArgs<T> &p, const T (&A)[RBW][KS], const uint32_t (&boff)[KS],
+                                             int next, T (&b)[KS], typename Mfma<T>::acc_t (&acc)[RBW]) {
+    using M = Mfma<T>;
+    const char *base = reinterpret_cast<const char *>(p.cp + int64_t(next) * kAbxNT);
 #pragma unroll
-        for (int q = 0; q < EW; ++q) ent[q] = pw[int64_t(tile) * PT + q * 64];
-        // ---- W = A R on the matrix cores
-        acc_t acc[RBW];
+    for (int r = 0; r < RBW; ++r) acc[r] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
-        for (int r = 0; r < RBW; ++r) acc[r] = acc_t{0, 0, 0, 0};
+    for (int t = 0; t < KS; ++t) {
 #pragma unroll
-        for (int t = 0; t < KS; ++t) {
-            const T b = U[(4 * t + (lane >> 4)) * BS + cb * 16 + (lane & 15)];
+        for (int r = 0; r < RBW; ++r) acc[r] = M::op(A[r][t], b[t], acc[r]);
+        b[t] = *reinterpret_cast<const T *>(base + boff[t]);
+    }
+}
+
+template <typename T, int RBW>
+__device__ __forceinline__ void abx_store_w(T *W, const typename Mfma<T>::acc_t (&acc)[RBW], int lane, int cb,
+                                            int rb0, int nrb) {
+    using M = Mfma<T>;
 #pragma unroll
-            for (int r = 0; r < RBW; ++r) acc[r] = M::op(A[r][t], b, acc[r]);
-        }
-        __syncthreads();                       // everyone is done reading B
-#pragma unroll
-        for (int r = 0; r < RBW; ++r)
+    for (int r = 0; r < RBW; ++r)
+        if (r < nrb)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                U[((grp * RBW + r) * 16 + M::out_row(lane, i)) * WS + cb * 16 + (lane & 15)] = acc[r][i];
-        __syncthreads();
-        // ---- beta-side scatter into the LDS sigma row
-        T val[EW], old[EW];
-        uint32_t ta[EW];
+                W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
+}
+
+// Beta-side scatter of one tile by one wave (plan entries ent of this lane).
+// Branch-free: writes that end no group go to the lane's discard slot `spare`.
+template <typename T, int EW>
+__device__ __forceinline__ void abx_scatter(const T *W, T *sig, const uint32_t (&ent)[EW], int lane, uint32_t spare) {
+    const char *wb = reinterpret_cast<const char *>(W);
+    char *sb = reinterpret_cast<char *>(sig);
+    auto tgt = [&](int q) { return (ent[q] >> 14) & 0x1fffcu; };
+    T val[EW], old[EW];
 #pragma unroll
-        for (int q = 0; q < EW; ++q) {
-            val[q] = flip_if(*reinterpret_cast<const T *>(ub + (ent[q] & 0xfffcu)), ent[q]);
-            ta[q] = (ent[q] >> 14) & 0x1fffcu;
-            old[q] = *reinterpret_cast<const T *>(sb + ta[q]);
-        }
-        // entry q ends a group when entry q+1 starts one; the lane's last entry
-        // does when the next lane's first one starts a group (the last lane: always)
-        const int nx = __builtin_amdgcn_update_dpp(int(0x80000000u), int(ent[0]), kWaveShl1, 0xf, 0xf, false);
-        const bool end_last = lane == 63 || nx < 0;
-        T run = 0;
-        bool seen_end = false, any_start = false;
-        uint32_t first_end = 0;
+    for (int q = 0; q < EW; ++q) {
+        val[q] = flip_if(*reinterpret_cast<const T *>(wb + (ent[q] & 0xfffcu)), ent[q]);
+        old[q] = *reinterpret_cast<const T *>(sb + tgt(q));
+    }
+    // entry q ends a group when entry q+1 starts one; the lane's last entry
+    // does when the next lane's first one starts a group (the last lane: always)
+    const int nx = __builtin_amdgcn_update_dpp(int(0x80000000u), int(ent[0]), kWaveShl1, 0xf, 0xf, false);
+    const bool end_last = lane == 63 || nx < 0;
+    T run = 0;
+    bool seen_end = false, any_start = false;
+    uint32_t first_end = spare;
 #pragma unroll
-        for (int q = 0; q < EW; ++q) {
-            const bool st = int(ent[q]) < 0;
-            any_start = any_start || st;
-            run = st ? val[q] : run + val[q];
-            const bool en = (q + 1 < EW) ? int(ent[q + 1]) < 0 : end_last;
-            if (en) *reinterpret_cast<T *>(sb + ta[q]) = old[q] + run;
-            first_end = (en && !seen_end) ? ta[q] : first_end;
-            seen_end = seen_end || en;
-        }
-        // the group open at the end of each lane continues in the next lanes
-        const T carry = wave_segmented_carry<T>(end_last ? T(0) : run, any_start ? 1 : 0);
-        if (int(ent[0]) >= 0 && seen_end) {
-            T *d = reinterpret_cast<T *>(sb + first_end);
-            *d = *d + carry;
-        }
-        __syncthreads();                       // W consumed
-        if (tile + 1 < ntile) stash(bpre);
+    for (int q = 0; q < EW; ++q) {
+        const bool st = int(ent[q]) < 0;
+        any_start = any_start || st;
+        run = st ? val[q] : run + val[q];
+        const bool en = (q + 1 < EW) ? int(ent[q + 1]) < 0 : end_last;
+        *reinterpret_cast<T *>(sb + (en ? tgt(q) : spare)) = old[q] + run;
+        first_end = (en && !seen_end) ? tgt(q) : first_end;
+        seen_end = seen_end || en;
+    }
+    // the group open at the end of each lane continues in the next lanes; a
+    // lane whose first group began earlier adds what those lanes hold
+    const T carry = wave_segmented_carry<T>(end_last ? T(0) : run, any_start ? 1 : 0);
+    T *d = reinterpret_cast<T *>(sb + (int(ent[0]) >= 0 ? first_end : spare));
+    *d = *d + carry;
+}
+
+// ---- four-wave form (FP64): every wave multiplies and scatters ----------------
+//
+// The four waves are 2 column halves x 2 groups of row blocks.  Per tile one
+// branch-free stretch holds the next tile's products and this tile's scatter,
+// then W is stored between two barriers.  LDS: the W tile and the sigma row.
+template <typename T, int KS, int RB, int EW>
+__global__ __launch_bounds__(256, 1) void k_sigma_ab_x(AbxArgs<T> p) {
+    using acc_t = typename Mfma<T>::acc_t;
+    using vec_t = typename Mfma<T>::vec_t;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int RBW = (RB + 1) / 2;
+    constexpr int MP = 16 * RB;
+    constexpr int PT = 4 * EW * 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *W = reinterpret_cast<T *>(smem_raw);                // [MP][WS]
+    T *sig = W + MP * kAbxWS;                              // [ld + 64]: slots ld.. take discarded writes
+
+    const int Ia = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int cb = wave & 1, grp = wave >> 1;
+    const int rb0 = grp == 0 ? 0 : RBW, nrb = grp == 0 ? RBW : RB - RBW;
+    const int64_t rowoff = int64_t(Ia) * p.ld;
+    for (int c = tid * VEC; c < p.ld; c += 256 * VEC)
+        *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
+    T A[RBW][KS];
+    uint32_t boff[KS];
+    abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
+
+    const int ntile = p.ld / kAbxNT;
+    const uint32_t *pw = p.plan + wave * (EW * 64) + lane;
+    const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
+    T b[KS];
+    acc_t acc[RBW];
+    uint32_t ent[EW], ent_next[EW];
+    abx_load<T, KS>(p, boff, 0, b);
+    abx_products<T, KS, RBW>(p, A, boff, ntile > 1 ? 1 : 0, b, acc);
+#pragma unroll
+    for (int q = 0; q < EW; ++q) ent[q] = pw[q * 64];
+    __syncthreads();                           // the sigma row is in LDS
+    abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
+    __syncthreads();
+    for (int tile = 0; tile < ntile; ++tile) {
+        const int t1 = tile + 1 < ntile ? tile + 1 : tile, t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
+#pragma unroll
+        for (int q = 0; q < EW; ++q) ent_next[q] = pw[int64_t(t1) * PT + q * 64];
+        abx_products<T, KS, RBW>(p, A, boff, t2, b, acc);   // next tile's W (after the last: discarded)
+        abx_scatter<T, EW>(W, sig, ent, lane, spare);
+        __syncthreads();                       // W of this tile consumed
+        if (tile + 1 < ntile) abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < EW; ++q) ent[q] = ent_next[q];
     }
     for (int cc = tid * VEC; cc < p.ld; cc += 256 * VEC)
         *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
 }
 
-template <typename T>
-size_t abx_lds(int ld, int ks, int rbw) {
-    const int KP = 4 * ks, BS = kAbxNT + (sizeof(T) == 4 ? 16 : 0), MP = 32 * rbw;
-    const int usz = KP * BS > MP * kAbxWS ? KP * BS : MP * kAbxWS;
-    return size_t(usz + ld + 4) * sizeof(T) + KP * sizeof(int);
+// ---- eight-wave form (FP32): four producing and four scattering waves ---------
+//
+// Waves 0-3 compute W of tile t+1 into one of two W buffers while waves 4-7
+// scatter tile t from the other; one barrier per tile.  The SIMDs interleave
+// the two kinds of work (matrix cores against vector ALU and LDS) and each role
+// keeps only its own registers.  LDS: two W tiles and the sigma row (~88 KB for
+// CAS(16,16)).
+template <typename T, int KS, int RB, int EW>
+__global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
+    using acc_t = typename Mfma<T>::acc_t;
+    using vec_t = typename Mfma<T>::vec_t;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int RBW = (RB + 1) / 2;
+    constexpr int MP = 16 * RB;
+    constexpr int PT = 4 * EW * 64;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *W0 = reinterpret_cast<T *>(smem_raw);               // [2][MP][WS]
+    T *W1 = W0 + MP * kAbxWS;
+    T *sig = W1 + MP * kAbxWS;                             // [ld + 64]: slots ld.. take discarded writes
+
+    const int Ia = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the roles branch per wave
+    const int64_t rowoff = int64_t(Ia) * p.ld;
+    for (int c = tid * VEC; c < p.ld; c += 512 * VEC)
+        *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
+    const int ntile = p.ld / kAbxNT;
+    __syncthreads();                           // the sigma row is in LDS
+    if (wave < 4) {
+        const int cb = wave & 1, grp = wave >> 1;
+        const int rb0 = grp == 0 ? 0 : RBW, nrb = grp == 0 ? RBW : RB - RBW;
+        T A[RBW][KS];
+        uint32_t boff[KS];
+        abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        T b[KS];
+        acc_t acc[RBW];
+        abx_load<T, KS>(p, boff, 0, b);
+        abx_products<T, KS, RBW>(p, A, boff, ntile > 1 ? 1 : 0, b, acc);
+        abx_store_w<T, RBW>(W0, acc, lane, cb, rb0, nrb);
+        __syncthreads();                       // W of tile 0 ready
+        for (int tile = 0; tile < ntile; ++tile) {
+            if (tile + 1 < ntile) {
+                const int t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
+                abx_products<T, KS, RBW>(p, A, boff, t2, b, acc);
+                abx_store_w<T, RBW>((tile + 1) & 1 ? W1 : W0, acc, lane, cb, rb0, nrb);
+            }
+            __syncthreads();
+        }
+    } else {
+        const uint32_t *pw = p.plan + (wave - 4) * (EW * 64) + lane;
+        const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
+        uint32_t ent[EW], ent_next[EW];
+#pragma unroll
+        for (int q = 0; q < EW; ++q) ent[q] = pw[q * 64];
+        __syncthreads();                       // W of tile 0 ready
+        for (int tile = 0; tile < ntile; ++tile) {
+            const int t1 = tile + 1 < ntile ? tile + 1 : tile;
+#pragma unroll
+            for (int q = 0; q < EW; ++q) ent_next[q] = pw[int64_t(t1) * PT + q * 64];
+            abx_scatter<T, EW>(tile & 1 ? W1 : W0, sig, ent, lane, spare);
+#pragma unroll
+            for (int q = 0; q < EW; ++q) ent[q] = ent_next[q];
+            __syncthreads();                   // tile consumed; the next W is ready
+        }
+    }
+    for (int cc = tid * VEC; cc < p.ld; cc += 512 * VEC)
+        *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
 }
 
-template <typename T, int KS, int RBW, int EW>
+// LDS bytes: the W tile (two for the eight-wave FP32 form) and the sigma row
+// with its 64 discard slots
+template <typename T>
+size_t abx_lds(int ld, int rb) {
+    const size_t nw = sizeof(T) == 4 ? 2 : 1;
+    return (nw * 16 * rb * kAbxWS + ld + 64) * sizeof(T);
+}
+
+template <typename T, int KS, int RB, int EW>
 hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s) {
-    const size_t lds = abx_lds<T>(a.ld, KS, RBW);
-    if (lds > 160 * 1024 || 32 * RBW < a.npair || 4 * KS < a.anexc + 1) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RBW, EW>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RBW, EW>), dim3(a.Na), dim3(256), lds, s, a);
+    const size_t lds = abx_lds<T>(a.ld, RB);
+    if (lds > 160 * 1024 || 16 * RB < a.npair || 4 * KS < a.anexc + 1) return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 4) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_ws<T, KS, RB, EW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_sigma_ab_ws<T, KS, RB, EW>), dim3(a.Na), dim3(512), lds, s, a);
+    } else {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RB, EW>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW>), dim3(a.Na), dim3(256), lds, s, a);
+    }
     return hipGetLastError();
 }
 
 int ks_of(int anexc) { return (anexc + 1 + 3) / 4; }
-int rbw_of(int npair) { return (npair + 31) / 32; }
+int rb_of(int npair) { return (npair + 15) / 16; }
 
-// The compiled (KS, RBW, EW) shapes: for each (KS, RBW) of the CAS(n, n/2)
-// spaces n = 4..16 (and the neighbouring open-shell ones) one plan width sized
-// for CAS(n, n/2) and a wider one.
+// The compiled (KS, RB, EW) shapes: for each (KS, RB) of the CAS(n, n/2)
+// spaces n = 4..16 and their open-shell neighbours, the plan width of
+// CAS(n, n/2) and a wider one.
 #define CIS_ABX_SHAPES(X)                                                                              \
-    X(2, 1, 2) X(2, 1, 16) X(3, 1, 2) X(3, 1, 16) X(4, 1, 4) X(4, 1, 16) X(5, 2, 4) X(5, 2, 16)         \
-    X(6, 2, 4) X(6, 2, 16) X(7, 2, 4) X(7, 2, 16) X(8, 3, 6) X(8, 3, 16)                          \
-    X(10, 3, 6) X(10, 3, 16) X(11, 3, 8) X(11, 3, 16) X(13, 4, 8) X(13, 4, 16) X(15, 4, 10)            \
-    X(15, 4, 16) X(17, 5, 10) X(17, 5, 16)
+    X(2, 1, 2) X(2, 1, 16) X(3, 2, 2) X(3, 2, 16) X(4, 2, 4) X(4, 2, 16) X(4, 3, 4) X(4, 3, 16)         \
+    X(5, 3, 4) X(5, 3, 16) X(6, 3, 4) X(6, 3, 16) X(6, 4, 4) X(6, 4, 16) X(7, 4, 4) X(7, 4, 16)         \
+    X(8, 5, 6) X(8, 5, 16) X(10, 5, 6) X(10, 5, 16) X(11, 6, 8) X(11, 6, 16) X(13, 7, 8) X(13, 7, 16)   \
+    X(15, 8, 10) X(15, 8, 16) X(17, 9, 10) X(17, 9, 16)
 
-int width_for(int ks, int rbw, int need) {
+int width_for(int ks, int rb, int need) {
     int best = 0;
-#define CIS_W(K, R, E) if (ks == K && rbw == R && E >= need && (best == 0 || E < best)) best = E;
+#define CIS_W(K, R, E) if (ks == K && rb == R && E >= need && (best == 0 || E < best)) best = E;
     CIS_ABX_SHAPES(CIS_W)
 #undef CIS_W
     return best;
@@ -309,9 +396,9 @@ int width_for(int ks, int rbw, int need) {
 
 template <typename T>
 bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err) {
-    const int ks = ks_of(a.anexc), rbw = rbw_of(a.npair);
+    const int ks = ks_of(a.anexc), rb = rb_of(a.npair);
 #define CIS_RUN(K, R, E) \
-    if (ks == K && rbw == R && ew == E) { *err = run_abx<T, K, R, E>(a, s); return true; }
+    if (ks == K && rb == R && ew == E) { *err = run_abx<T, K, R, E>(a, s); return true; }
     CIS_ABX_SHAPES(CIS_RUN)
 #undef CIS_RUN
     return false;
@@ -337,14 +424,16 @@ bool owner_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hi
     x.npair = ctx->npair;
     x.Na = A.nstr;
     x.ld = ctx->pl[0].ld[0];
-    if (abx_lds<T>(x.ld, ks_of(x.anexc), rbw_of(x.npair)) > 160 * 1024) return false;
+    if (abx_lds<T>(x.ld, rb_of(x.npair)) > 160 * 1024) return false;
+    // 32-bit byte offsets of the gathered rows, the zero row Na included
+    if ((uint64_t(x.Na) + 1) * uint64_t(x.ld) * sizeof(T) >= (uint64_t(1) << 32)) return false;
     return dispatch_abx<T>(x, P.ew, s, err);
 }
 
 }  // namespace
 
 int sigma_ab_owner_width(int anexc, int npair, int need) {
-    return width_for(ks_of(anexc), rbw_of(npair), need);
+    return width_for(ks_of(anexc), rb_of(npair), need);
 }
 
 bool launch_sigma_ab_owner(const cisigma_ctx *ctx, const void *cp, void *sp, int dtype, hipStream_t s,
