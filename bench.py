@@ -97,7 +97,7 @@ def stored_traffic(kernel_tag):
     summary, or None when the kernel source changed after the counters were
     taken (the summary records the source's SHA-256)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1707_04346_amd", "csrc", "sigma_ab.hip")
+    src = os.path.join(ROOT, "paper_1707_04346_amd", "csrc", "sigma_abx.hip" if kernel_tag == "k_sigma_ab_ws" else "sigma_ab.hip")
     prof = os.path.join(ROOT, "profiles", f"{kernel_tag}_cas16_fp32_traffic.txt")
     if not (os.path.exists(src) and os.path.exists(prof)):
         return None
@@ -185,9 +185,9 @@ def main():
     owner = bool(path32 & cis.PATH_AB_OWNER)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32"],
-                "traffic": stored_traffic("k_sigma_ab_x" if owner else "k_sigma_ab") if args.workload == "cas16" else None,
-                "kernel": ("k_sigma_ab_x (owner-computes sigma_3: gathered C rows -> FP32 MFMA -> LDS scatter)"
-                           if owner else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
+                "traffic": stored_traffic("k_sigma_ab_ws" if owner else "k_sigma_ab") if args.workload == "cas16" else None,
+                "kernel": ("k_sigma_ab_ws (owner-computes sigma_3: gathered C rows -> FP32 MFMA on four waves, "
+                           "LDS scatter on four waves)" if owner else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
                 "flops_per_launch": flops, "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
     if not args.no_fp64:
