@@ -354,11 +354,11 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
     if (W.ready) return CISIGMA_OK;
     size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
-    // one-block spaces: one extra zero row after the alpha-major copy (rows the
-    // owner-computes sigma_3 kernel reads in place of missing excitations)
+    // one-block spaces: one extra zero row after each copy (rows the owner-computes
+    // sigma_3 and the pair-product kernels read in place of missing ones)
     const int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
     size_t na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
-    size_t nb = size_t(std::max<int64_t>(c->pl[1].size, 1)) * es;
+    size_t nb = size_t(std::max<int64_t>(c->pl[1].size + (c->cas ? c->pl[1].ld[0] : 0), 1)) * es;
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2 * (na + nb) + (64u << 20) > fr)
         return cis_set_error(c, CISIGMA_ENOMEM, "apply: not enough device memory for the sigma workspace");

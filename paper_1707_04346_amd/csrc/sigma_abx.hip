@@ -29,6 +29,7 @@
 // sigma slot ld.
 #include "internal.h"
 #include "mfma.h"
+#include "bufio.h"
 
 #include <type_traits>
 
@@ -46,8 +47,11 @@ struct AbxArgs {
     const uint32_t *astr;  // [Na]
     const T *gp;           // [n*n][kp]
     const uint32_t *plan;  // [ntile][4 waves][EW][64 lanes]
+    uint32_t cp_bytes;     // bytes of C including the zero row (< 2^31)
+    uint32_t plan_bytes;   // bytes of the plan (< 2^31)
     int anexc, n, kp, npair, Na, ld;
 };
+
 
 // DPP lane moves (gfx9 controls).  Lanes without a valid source read 0.
 constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138, kWaveShl1 = 0x130;
@@ -129,7 +133,7 @@ __device__ __forceinline__ void abx_fragments(const AbxArgs<T> &p, int Ia, int l
         } else if (k == p.anexc) {
             J = Ia;
         }
-        boff[t] = (uint32_t(J) * uint32_t(p.ld) + col) * uint32_t(sizeof(T));
+        boff[t] = (uint32_t(J) * uint32_t(p.ld) + col) * uint32_t(sizeof(T));   // < cp_bytes
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
             const int m = (rb0 + r) * 16 + (lane & 15);
@@ -150,26 +154,29 @@ __device__ __forceinline__ void abx_fragments(const AbxArgs<T> &p, int Ia, int l
 }
 
 template <typename T, int KS>
-__device__ __forceinline__ void abx_load(const AbxArgs<T> &p, const uint32_t (&boff)[KS], int tile, T (&b)[KS]) {
-    const char *base = reinterpret_cast<const char *>(p.cp + int64_t(tile) * kAbxNT);
+__device__ __forceinline__ void abx_load(__amdgpu_buffer_rsrc_t cr, const uint32_t (&boff)[KS], int tile, T (&b)[KS]) {
+    const uint32_t soff = uint32_t(tile) * uint32_t(kAbxNT * sizeof(T));
 #pragma unroll
-    for (int t = 0; t < KS; ++t) b[t] = *reinterpret_cast<const T *>(base + boff[t]);
+    for (int t = 0; t < KS; ++t) buffer_ld(b[t], cr, boff[t], soff);
 }
 
 // W = A R on the matrix cores for the rows held in b; as each k step is
-// consumed, b[t] is reloaded with the rows of tile `next` (always a valid tile).
+// consumed, b[t] is reloaded with the rows of tile `next` (always a valid
+// tile), so the loads stay in flight for a whole tile.
 template <typename T, int KS, int RBW>
-__device__ __forceinline__ void abx_products(const AbxArgs<T> &p, const T (&A)[RBW][KS], const uint32_t (&boff)[KS],
-                                             int next, T (&b)[KS], typename Mfma<T>::acc_t (&acc)[RBW]) {
+__device__ __forceinline__ void abx_products(__amdgpu_buffer_rsrc_t cr, const T (&A)[RBW][KS],
+                                             const uint32_t (&boff)[KS], int next, T (&b)[KS],
+                                             typename Mfma<T>::acc_t (&acc)[RBW]) {
     using M = Mfma<T>;
-    const char *base = reinterpret_cast<const char *>(p.cp + int64_t(next) * kAbxNT);
+    const uint32_t soff = uint32_t(next) * uint32_t(kAbxNT * sizeof(T));
 #pragma unroll
     for (int r = 0; r < RBW; ++r) acc[r] = typename M::acc_t{0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
 #pragma unroll
         for (int r = 0; r < RBW; ++r) acc[r] = M::op(A[r][t], b[t], acc[r]);
-        b[t] = *reinterpret_cast<const T *>(base + boff[t]);
+        buffer_ld(b[t], cr, boff[t], soff);
+        __builtin_amdgcn_sched_barrier(0);   // keep the reload next to its k step
     }
 }
 
@@ -251,23 +258,24 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_x(AbxArgs<T> p) {
     abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
 
     const int ntile = p.ld / kAbxNT;
-    const uint32_t *pw = p.plan + wave * (EW * 64) + lane;
+    const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes), pr = buffer_of(p.plan, p.plan_bytes);
+    const uint32_t pl = uint32_t(wave * (EW * 64) + lane) * 4u;   // this lane's plan byte offset in a tile
     const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
     T b[KS];
     acc_t acc[RBW];
     uint32_t ent[EW], ent_next[EW];
-    abx_load<T, KS>(p, boff, 0, b);
-    abx_products<T, KS, RBW>(p, A, boff, ntile > 1 ? 1 : 0, b, acc);
+    abx_load<T, KS>(cr, boff, 0, b);
+    abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
 #pragma unroll
-    for (int q = 0; q < EW; ++q) ent[q] = pw[q * 64];
+    for (int q = 0; q < EW; ++q) ent[q] = buffer_ld_u32(pr, pl + q * 256u, 0u);
     __syncthreads();                           // the sigma row is in LDS
     abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
     __syncthreads();
     for (int tile = 0; tile < ntile; ++tile) {
         const int t1 = tile + 1 < ntile ? tile + 1 : tile, t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
 #pragma unroll
-        for (int q = 0; q < EW; ++q) ent_next[q] = pw[int64_t(t1) * PT + q * 64];
-        abx_products<T, KS, RBW>(p, A, boff, t2, b, acc);   // next tile's W (after the last: discarded)
+        for (int q = 0; q < EW; ++q) ent_next[q] = buffer_ld_u32(pr, pl + q * 256u, uint32_t(t1) * (PT * 4u));
+        abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);   // next tile's W (after the last: discarded)
         abx_scatter<T, EW>(W, sig, ent, lane, spare);
         __syncthreads();                       // W of this tile consumed
         if (tile + 1 < ntile) abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
@@ -313,31 +321,33 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         T A[RBW][KS];
         uint32_t boff[KS];
         abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes);
         T b[KS];
         acc_t acc[RBW];
-        abx_load<T, KS>(p, boff, 0, b);
-        abx_products<T, KS, RBW>(p, A, boff, ntile > 1 ? 1 : 0, b, acc);
+        abx_load<T, KS>(cr, boff, 0, b);
+        abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
         abx_store_w<T, RBW>(W0, acc, lane, cb, rb0, nrb);
         __syncthreads();                       // W of tile 0 ready
         for (int tile = 0; tile < ntile; ++tile) {
             if (tile + 1 < ntile) {
                 const int t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
-                abx_products<T, KS, RBW>(p, A, boff, t2, b, acc);
+                abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);
                 abx_store_w<T, RBW>((tile + 1) & 1 ? W1 : W0, acc, lane, cb, rb0, nrb);
             }
             __syncthreads();
         }
     } else {
-        const uint32_t *pw = p.plan + (wave - 4) * (EW * 64) + lane;
+        const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
+        const uint32_t pl = uint32_t((wave - 4) * (EW * 64) + lane) * 4u;
         const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
         uint32_t ent[EW], ent_next[EW];
 #pragma unroll
-        for (int q = 0; q < EW; ++q) ent[q] = pw[q * 64];
+        for (int q = 0; q < EW; ++q) ent[q] = buffer_ld_u32(pr, pl + q * 256u, 0u);
         __syncthreads();                       // W of tile 0 ready
         for (int tile = 0; tile < ntile; ++tile) {
             const int t1 = tile + 1 < ntile ? tile + 1 : tile;
 #pragma unroll
-            for (int q = 0; q < EW; ++q) ent_next[q] = pw[int64_t(t1) * PT + q * 64];
+            for (int q = 0; q < EW; ++q) ent_next[q] = buffer_ld_u32(pr, pl + q * 256u, uint32_t(t1) * (PT * 4u));
             abx_scatter<T, EW>(tile & 1 ? W1 : W0, sig, ent, lane, spare);
 #pragma unroll
             for (int q = 0; q < EW; ++q) ent[q] = ent_next[q];
@@ -425,8 +435,12 @@ bool owner_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hi
     x.Na = A.nstr;
     x.ld = ctx->pl[0].ld[0];
     if (abx_lds<T>(x.ld, rb_of(x.npair)) > 160 * 1024) return false;
-    // 32-bit byte offsets of the gathered rows, the zero row Na included
-    if ((uint64_t(x.Na) + 1) * uint64_t(x.ld) * sizeof(T) >= (uint64_t(1) << 32)) return false;
+    // 32-bit byte offsets of the gathered rows (the zero row Na included) and of the plan
+    const uint64_t cpb = (uint64_t(x.Na) + 1) * uint64_t(x.ld) * sizeof(T);
+    const uint64_t plb = uint64_t(P.ntile) * 4 * P.ew * 64 * sizeof(uint32_t);
+    if (cpb >= (uint64_t(1) << 31) || plb >= (uint64_t(1) << 31)) return false;
+    x.cp_bytes = uint32_t(cpb);
+    x.plan_bytes = uint32_t(plb);
     return dispatch_abx<T>(x, P.ew, s, err);
 }
 

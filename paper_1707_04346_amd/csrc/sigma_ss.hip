@@ -19,6 +19,7 @@
 // N = 1 has no pairs; its one-electron part is applied by k_one_electron.
 #include "internal.h"
 #include "mfma.h"
+#include "bufio.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -170,6 +171,122 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     }
 }
 
+// One-block (CAS) spaces, materialised form: the pair products of one K for the
+// columns [col_begin, col_end), stored as rows K*npv + P of Ys (row stride ldy).
+// Each wave walks 16*VEC-column items; the gathered rows of its next item are
+// loaded while the matrix cores work on the current one.  Missing rows read the
+// zero row nstr of X.
+template <typename T>
+struct SsyArgs {
+    const T *X;              // rows = strings of this spin (row stride ld); row nstr is zero
+    T *Ys;                   // [nK*npv][ldy]
+    const uint32_t *pairs;   // [nK][npv]
+    const T *V;              // [nps][nps]
+    uint32_t x_bytes;        // bytes of X including the zero row (< 2^31)
+    int npv, nK, nps, nstr, ld;
+    int64_t ldy;
+    int col_begin, col_end;  // multiples of 16*VEC
+};
+
+template <typename T, int KS, int MBL>
+__global__ __launch_bounds__(256, 2) void k_sigma_ss_y(SsyArgs<T> p) {
+    using M = Mfma<T>;
+    using acc_t = typename M::acc_t;
+    using vec_t = typename M::vec_t;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int TW = 16 * VEC;
+    constexpr int KP = 4 * KS, MP = 16 * MBL;
+    constexpr int NE = KP > MP ? KP : MP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *As = reinterpret_cast<T *>(smem_raw);            // [MP][KP+1]
+    int *rowJ = reinterpret_cast<int *>(As + MP * (KP + 1));
+    int *pid = rowJ + NE;
+    int *neg = pid + NE;
+
+    const int K = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int q = tid; q < NE; q += 256) {
+        const uint32_t w = (q < p.npv) ? p.pairs[int64_t(K) * p.npv + q] : kPairNone;
+        rowJ[q] = (w == kPairNone) ? -1 : int(w >> 11);
+        pid[q] = int((w >> 1) & 1023u);
+        neg[q] = int(w & 1u);
+    }
+    __syncthreads();
+    for (int idx = tid; idx < MP * KP; idx += 256) {
+        const int P = idx / KP, Q = idx % KP;
+        T val = 0;
+        if (rowJ[P] >= 0 && rowJ[Q] >= 0) {
+            val = p.V[int64_t(pid[P]) * p.nps + pid[Q]];
+            if (neg[P] ^ neg[Q]) val = -val;
+        }
+        As[P * (KP + 1) + Q] = val;
+    }
+    __syncthreads();
+    T A[MBL][KS];
+#pragma unroll
+    for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+        for (int t = 0; t < KS; ++t) A[rb][t] = As[(rb * 16 + (lane & 15)) * (KP + 1) + 4 * t + (lane >> 4)];
+    // byte offsets: gathered row of k step t (row 4t + lane/16) and this lane's column
+    uint32_t boff[KS];
+#pragma unroll
+    for (int t = 0; t < KS; ++t) {
+        int J = rowJ[4 * t + (lane >> 4)];
+        if (J < 0) J = p.nstr;
+        boff[t] = (uint32_t(J) * uint32_t(p.ld) + uint32_t(VEC * (lane & 15))) * uint32_t(sizeof(T));
+    }
+    // byte offsets of this lane's output rows within the K's block of Ys
+    uint32_t yoff[MBL][4];
+#pragma unroll
+    for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            yoff[rb][i] = (uint32_t(rb * 16 + M::out_row(lane, i)) * uint32_t(p.ldy) + uint32_t(VEC * (lane & 15))) *
+                          uint32_t(sizeof(T));
+    const __amdgpu_buffer_rsrc_t xr = buffer_of(p.X, p.x_bytes);
+    const __amdgpu_buffer_rsrc_t yr =
+        buffer_of(p.Ys + int64_t(K) * p.npv * p.ldy, uint32_t(int64_t(p.npv) * p.ldy * sizeof(T)));
+    const int nitems = (p.col_end - p.col_begin) / TW;
+    auto load = [&](int it, vec_t (&b)[KS]) {
+        const uint32_t soff = uint32_t(p.col_begin + it * TW) * uint32_t(sizeof(T));
+#pragma unroll
+        for (int t = 0; t < KS; ++t) buffer_ld(b[t], xr, boff[t], soff);
+    };
+    auto step = [&](int it, const vec_t (&b)[KS], vec_t (&bn)[KS]) {
+        load(it + 4 < nitems ? it + 4 : it, bn);
+        __builtin_amdgcn_sched_barrier(0);     // the next item's loads go out first
+        acc_t acc[MBL][VEC];
+#pragma unroll
+        for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v) acc[rb][v] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < KS; ++t)
+#pragma unroll
+            for (int v = 0; v < VEC; ++v)
+#pragma unroll
+                for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(A[rb][t], b[t][v], acc[rb][v]);
+        const uint32_t soff = uint32_t(it * TW) * uint32_t(sizeof(T));
+#pragma unroll
+        for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (rb * 16 + M::out_row(lane, i) >= p.npv) continue;
+                vec_t o;
+#pragma unroll
+                for (int v = 0; v < VEC; ++v) o[v] = acc[rb][v][i];
+                buffer_st(o, yr, yoff[rb][i], soff);
+            }
+    };
+    if (wave >= nitems) return;
+    vec_t b0[KS], b1[KS];
+    load(wave, b0);
+    for (int it = wave; it < nitems; it += 8) {
+        step(it, b0, b1);
+        if (it + 4 < nitems) step(it + 4, b1, b0);
+    }
+}
+
 // out(I, c) = sum over the occupied pairs of I of the materialised rows
 // Ys(K*npv + e, c): the owner-computes half of the same-spin part.
 template <typename T>
@@ -240,6 +357,30 @@ hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T, int KS, int MBL>
+hipError_t run_ssy(const SsyArgs<T> &a, hipStream_t s) {
+    constexpr int KP = 4 * KS, MP = 16 * MBL;
+    constexpr int NE = KP > MP ? KP : MP;
+    const size_t lds = size_t(MP) * (KP + 1) * sizeof(T) + 3 * NE * sizeof(int);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ss_y<T, KS, MBL>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sigma_ss_y<T, KS, MBL>), dim3(a.nK), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_ssy(const SsyArgs<T> &a, hipStream_t s) {
+    const int ks = (a.npv + 3) / 4;
+    const int mbl = (a.npv + 15) / 16;
+#define CIS_SSY(K, MB) if (ks == K && mbl == MB) return run_ssy<T, K, MB>(a, s);
+    CIS_SSY(1, 1) CIS_SSY(2, 1) CIS_SSY(3, 1) CIS_SSY(4, 1) CIS_SSY(4, 2) CIS_SSY(6, 2) CIS_SSY(7, 2) CIS_SSY(9, 3)
+    CIS_SSY(12, 3) CIS_SSY(14, 4) CIS_SSY(17, 5) CIS_SSY(20, 5) CIS_SSY(23, 6) CIS_SSY(27, 7) CIS_SSY(30, 8)
+    CIS_SSY(34, 9) CIS_SSY(39, 10) CIS_SSY(43, 11)
+#undef CIS_SSY
+    return hipErrorInvalidValue;
+}
+
 template <typename T, bool STORE>
 hipError_t dispatch_ss(const SsArgs<T> &a, hipStream_t s) {
     const int ks = (a.npv + 3) / 4;
@@ -292,14 +433,34 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
     // materialised form, one column chunk at a time: store rows K*npv+P, then gather per string
     const int per = S.nel * (S.nel - 1) / 2;
     const int64_t ld = L.ld[0];
+    const uint64_t x_bytes = (uint64_t(S.nstr) + 1) * uint64_t(ld) * sizeof(T);   // the zero row included
     for (int c0 = 0; c0 < ld; c0 += chunk) {
         const int c1 = int(std::min<int64_t>(ld, c0 + chunk));
-        a.Ys = static_cast<T *>(Ys);
-        a.ldy = c1 - c0;
-        a.col_begin = c0;
-        a.tile_begin = c0 / kTileCols;
-        a.tile_end = c1 / kTileCols;
-        hipError_t e = dispatch_ss<T, true>(a, s);
+        hipError_t e;
+        if (x_bytes < (uint64_t(1) << 31) && uint64_t(S.npv) * uint64_t(c1 - c0) * sizeof(T) < (uint64_t(1) << 31)) {
+            SsyArgs<T> y{};
+            y.X = static_cast<const T *>(X);
+            y.Ys = static_cast<T *>(Ys);
+            y.pairs = S.d_pairs;
+            y.V = a.V;
+            y.x_bytes = uint32_t(x_bytes);
+            y.npv = S.npv;
+            y.nK = S.nK;
+            y.nps = ctx->nps;
+            y.nstr = S.nstr;
+            y.ld = int(ld);
+            y.ldy = c1 - c0;
+            y.col_begin = c0;
+            y.col_end = c1;
+            e = dispatch_ssy<T>(y, s);
+        } else {
+            a.Ys = static_cast<T *>(Ys);
+            a.ldy = c1 - c0;
+            a.col_begin = c0;
+            a.tile_begin = c0 / kTileCols;
+            a.tile_end = c1 / kTileCols;
+            e = dispatch_ss<T, true>(a, s);
+        }
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_pair_gather<T>), dim3(S.nstr), dim3(256), 0, s, static_cast<const T *>(Ys),
                            int64_t(c1 - c0), c0, c1, S.d_pair_inv, per, static_cast<T *>(Y), ld);
