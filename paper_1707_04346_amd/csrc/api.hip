@@ -249,25 +249,36 @@ int build_layouts(cisigma_ctx *c) {
 // to 16 orbitals), built on the host from the device beta excitation lists.
 // Per 32-column tile of source strings Jb: every contribution (target Ib,
 // W element (kl, column), sign) -- the single beta excitations of each Jb and
-// the diagonal kk terms of Ib = Jb -- sorted by target; the sorted list is cut
-// at target-group boundaries into four wave ranges of at most 64*ew entries,
-// and lane l of a wave takes entries [l*ew, (l+1)*ew) of its range.  Entry
-// words as the kernel reads them: bit 31 group start, bits 16..30 target dword
-// index, bits 0..15 W byte offset with the sign in bit 0; padding entries start
-// a group, read W element 0 and write the spare slot ld.  One encoding per
-// element size.  Without a plan (a shape no kernel covers) the general kernel runs.
+// the diagonal kk terms of Ib = Jb -- sorted so that equal targets ("groups")
+// are contiguous, cut at group boundaries into four wave ranges of at most
+// 64*ew entries; lane l of a wave takes entries [l*ew, (l+1)*ew) of its range.
+// Words per wave and tile, as the kernel reads them ([q][lane] order):
+//   entry   : bits 16..31 the sigma slot the entry's running sum is written to
+//             -- the group's target if the entry ends its group, else the
+//             lane's discard slot ld + lane -- as a byte offset (FP32) or an
+//             element index (FP64); bits 0..15 the W byte offset, its bit 0
+//             (always clear) replaced by the sign
+//   header  : bit 0 set when the lane's first entry starts a group (or the lane
+//             is padding); the rest is the byte offset the carry from earlier
+//             lanes is added to (the target of the lane's first group if that
+//             group began in an earlier lane and ends in this one, else the
+//             discard slot)
+// A group may span at most four lanes (the kernel carries partial sums over
+// three).  One encoding per element size.  Without a plan (a shape no kernel
+// covers) the general kernel runs.
 int build_scatter_plan(cisigma_ctx *c) {
     constexpr int NT = 32, WS = 33;
     const auto &B = c->sp[1];
     const int ld = c->pl[0].ld[0];
     const int mp = 16 * ((c->npair + 15) / 16);
+    // 16-bit fields: W byte offsets (FP64 the larger) and slot offsets (FP32 bytes, FP64 elements)
     if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || size_t(mp) * WS * 8 >= 65536 ||
-        2 * (size_t(ld) + 1) >= 32768)
+        (size_t(ld) + 64) * 4 >= 65536)
         return CISIGMA_OK;
     std::vector<uint32_t> exc(size_t(B.nstr) * B.nexc), str(B.nstr);
     HIP_OR_FAIL(c, hipMemcpy(exc.data(), B.d_exc, exc.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
     HIP_OR_FAIL(c, hipMemcpy(str.data(), B.d_str, str.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
-    struct Item { uint32_t tgt, widx, neg, start; };
+    struct Item { uint32_t tgt, widx, neg, start, end; };
     const int ntile = ld / NT;
     std::vector<std::vector<Item>> tiles(ntile);
     int need = 1;
@@ -280,15 +291,18 @@ int build_scatter_plan(cisigma_ctx *c) {
                 const uint32_t w = exc[size_t(Jb) * B.nexc + e];
                 if (w == cis::kExcNone) continue;
                 const int k = (w >> 6) & 31, l = (w >> 1) & 31;
-                tile.push_back({w >> 11, uint32_t(cis::pair_ge(k, l) * WS + col), w & 1u, 0u});
+                tile.push_back({w >> 11, uint32_t(cis::pair_ge(k, l) * WS + col), w & 1u, 0u, 0u});
             }
             for (uint32_t b = str[Jb]; b; b &= b - 1) {
                 const int k = __builtin_ctz(b);
-                tile.push_back({uint32_t(Jb), uint32_t(cis::pair_ge(k, k) * WS + col), 0u, 0u});
+                tile.push_back({uint32_t(Jb), uint32_t(cis::pair_ge(k, k) * WS + col), 0u, 0u, 0u});
             }
         }
         std::stable_sort(tile.begin(), tile.end(), [](const Item &a, const Item &b) { return a.tgt < b.tgt; });
-        for (size_t i = 0; i < tile.size(); ++i) tile[i].start = (i == 0 || tile[i].tgt != tile[i - 1].tgt);
+        for (size_t i = 0; i < tile.size(); ++i) {
+            tile[i].start = (i == 0 || tile[i].tgt != tile[i - 1].tgt);
+            tile[i].end = (i + 1 == tile.size() || tile[i].tgt != tile[i + 1].tgt);
+        }
         // smallest ew whose wave capacity 64*ew packs the groups into four ranges
         auto fits = [&](size_t cap) {
             int ranges = 1;
@@ -306,21 +320,13 @@ int build_scatter_plan(cisigma_ctx *c) {
         };
         while (!fits(size_t(64) * need)) ++need;
     }
-    const int ew = cis::sigma_ab_owner_width(c->sp[0].nexc, c->npair, need);
-    if (ew == 0) return CISIGMA_OK;
-    const size_t per_tile = size_t(4) * ew * 64;
-    std::vector<uint32_t> plan[2] = {std::vector<uint32_t>(per_tile * ntile), std::vector<uint32_t>(per_tile * ntile)};
-    for (int es_i = 0; es_i < 2; ++es_i) {
-        const uint32_t es = es_i == 0 ? 8 : 4;   // [0]: FP64, [1]: FP32
-        const uint32_t pad = (1u << 31) | ((uint32_t(ld) * es / 4) << 16);
-        std::fill(plan[es_i].begin(), plan[es_i].end(), pad);
-    }
-    for (int t = 0; t < ntile; ++t) {
-        const auto &tile = tiles[t];
+    // wave ranges of a tile for entries-per-lane ew; false when a group would
+    // span more than four lanes
+    auto ranges_of = [&](const std::vector<Item> &tile, int ew, std::vector<std::pair<size_t, size_t>> &rg) {
+        rg.clear();
         const size_t cap = size_t(64) * ew;
         size_t i = 0;
         for (int wv = 0; wv < 4 && i < tile.size(); ++wv) {
-            // this wave's range: whole groups up to the capacity
             size_t j = i;
             while (j < tile.size()) {
                 size_t g = j + 1;
@@ -328,25 +334,68 @@ int build_scatter_plan(cisigma_ctx *c) {
                 if (g - i > cap) break;
                 j = g;
             }
-            for (size_t e = i; e < j; ++e) {
-                const size_t r = e - i;
-                const size_t lane = r / ew, q = r % ew;
-                const size_t slot = size_t(t) * per_tile + (size_t(wv) * ew + q) * 64 + lane;
-                const Item &it = tile[e];
-                for (int es_i = 0; es_i < 2; ++es_i) {
-                    const uint32_t es = es_i == 0 ? 8 : 4;
-                    plan[es_i][slot] = (it.start << 31) | ((it.tgt * es / 4) << 16) | (it.widx * es) | it.neg;
-                }
+            for (size_t g0 = i; g0 < j;) {
+                size_t g1 = g0 + 1;
+                while (g1 < j && !tile[g1].start) ++g1;
+                if ((g1 - 1 - i) / ew - (g0 - i) / ew > 3) return false;
+                g0 = g1;
             }
+            rg.push_back({i, j});
             i = j;
         }
-        if (i != tile.size()) return CISIGMA_OK;   // cannot happen: ew >= need
+        return i == tile.size();
+    };
+    int ew = 0;
+    for (int cand : {cis::sigma_ab_owner_width(c->sp[0].nexc, c->npair, need), 16}) {
+        if (cand < need || cis::sigma_ab_owner_width(c->sp[0].nexc, c->npair, cand) != cand) continue;
+        std::vector<std::pair<size_t, size_t>> rg;
+        bool ok = true;
+        for (int t = 0; t < ntile && ok; ++t) ok = ranges_of(tiles[t], cand, rg);
+        if (ok) { ew = cand; break; }
     }
-    cis::ScatterPlan &P = c->plan;
-    HIP_OR_FAIL(c, upload(&P.d_entries[0], plan[0]), "init: scatter plan");
-    HIP_OR_FAIL(c, upload(&P.d_entries[1], plan[1]), "init: scatter plan");
-    P.ntile = ntile;
-    P.ew = ew;
+    if (ew == 0) return CISIGMA_OK;
+    const size_t per_wave = size_t(ew + 1) * 64, per_tile = 4 * per_wave;
+    std::vector<uint32_t> plan[2] = {std::vector<uint32_t>(per_tile * ntile), std::vector<uint32_t>(per_tile * ntile)};
+    std::vector<std::pair<size_t, size_t>> rg;
+    for (int es_i = 0; es_i < 2; ++es_i) {
+        const uint32_t es = es_i == 0 ? 8 : 4;   // [0]: FP64, [1]: FP32
+        auto &P = plan[es_i];
+        for (int t = 0; t < ntile; ++t) {
+            const auto &tile = tiles[t];
+            ranges_of(tile, ew, rg);
+            for (int wv = 0; wv < 4; ++wv) {
+                const size_t base = (size_t(t) * 4 + wv) * per_wave;
+                const size_t i = wv < int(rg.size()) ? rg[wv].first : 0, j = wv < int(rg.size()) ? rg[wv].second : 0;
+                for (int lane = 0; lane < 64; ++lane) {
+                    const uint32_t spare = (uint32_t(ld) + lane) * es;          // discard slot, bytes
+                    const uint32_t unit = es == 4 ? 1 : 8;                       // slot field unit, bytes
+                    uint32_t hdr = spare | 1u;
+                    for (int q = 0; q < ew; ++q) {
+                        const size_t e = i + size_t(lane) * ew + q;
+                        uint32_t word = (spare / unit) << 16;                    // padding: W element 0, discard slot
+                        if (e < j) {
+                            const Item &it = tile[e];
+                            const uint32_t slot = it.end ? it.tgt * es : spare;
+                            word = ((slot / unit) << 16) | (it.widx * es) | it.neg;
+                            if (q == 0 && !it.start) {
+                                // continued group: its end in this lane takes the carry
+                                hdr = spare;
+                                for (size_t f = e; f < i + size_t(lane + 1) * ew && f < j; ++f)
+                                    if (tile[f].end) { hdr = tile[f].tgt * es; break; }
+                            }
+                        }
+                        P[base + size_t(q) * 64 + lane] = word;
+                    }
+                    P[base + size_t(ew) * 64 + lane] = hdr;
+                }
+            }
+        }
+    }
+    cis::ScatterPlan &SP = c->plan;
+    HIP_OR_FAIL(c, upload(&SP.d_entries[0], plan[0]), "init: scatter plan");
+    HIP_OR_FAIL(c, upload(&SP.d_entries[1], plan[1]), "init: scatter plan");
+    SP.ntile = ntile;
+    SP.ew = ew;
     return CISIGMA_OK;
 }
 

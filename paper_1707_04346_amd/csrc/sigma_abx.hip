@@ -23,10 +23,13 @@
 // two lanes write the same target and no wave range splits a group, so the LDS
 // read-modify-writes never conflict.
 //
-// Plan entry (32 bits):  bit 31 group start | bits 16..30 target dword index
-// (sigma slot x element size / 4) | bits 2..15 W byte offset / 4 | bit 0 sign.
-// Padding entries start a group of their own, read W(0, 0) and write the spare
-// sigma slot ld.
+// Plan words per wave and tile, lane-interleaved: EW entry words (bits 16..31:
+// the sigma slot the entry's running sum goes to -- the group's target when the
+// entry ends its group, else the lane's discard slot ld + lane -- in bytes for
+// FP32, elements for FP64; bits 0..15: W byte offset with the sign in bit 0)
+// and a header (bit 0: the lane's first entry starts a group; the rest: where
+// the carry from earlier lanes is added).  A group spans at most four lanes, so
+// the carry needs three lane shifts.
 #include "internal.h"
 #include "mfma.h"
 #include "bufio.h"
@@ -54,7 +57,7 @@ struct AbxArgs {
 
 
 // DPP lane moves (gfx9 controls).  Lanes without a valid source read 0.
-constexpr int kRowShr = 0x110, kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138, kWaveShl1 = 0x130;
+constexpr int kWaveShr1 = 0x138;
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ int dpp_i(int v) {
@@ -72,33 +75,26 @@ __device__ __forceinline__ double dpp_t(double v) {
     return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-// Exclusive segmented sum across the wave: lane l receives the sum of v over
-// lanes j < l back to (and including) the nearest lane j with f != 0.
-template <typename T>
-__device__ __forceinline__ T wave_segmented_carry(T v, int f) {
-#define CIS_SCAN_STEP(CTRL, ROWS)                       \
-    {                                                   \
-        const T tv = dpp_t<CTRL, ROWS>(v);              \
-        const int tf = dpp_i<CTRL, ROWS>(f);            \
-        v = f ? v : v + tv;                             \
-        f |= tf;                                        \
-    }
-    CIS_SCAN_STEP(kRowShr + 1, 0xf)
-    CIS_SCAN_STEP(kRowShr + 2, 0xf)
-    CIS_SCAN_STEP(kRowShr + 4, 0xf)
-    CIS_SCAN_STEP(kRowShr + 8, 0xf)
-    CIS_SCAN_STEP(kRowBcast15, 0xa)
-    CIS_SCAN_STEP(kRowBcast31, 0xc)
-#undef CIS_SCAN_STEP
-    return dpp_t<kWaveShr1, 0xf>(v);
-}
-
+// u with its sign flipped when bit 0 of w is set
 __device__ __forceinline__ float flip_if(float u, uint32_t w) {
     return __int_as_float(__float_as_int(u) ^ int(w << 31));
 }
 __device__ __forceinline__ double flip_if(double u, uint32_t w) {
     const unsigned long long m = static_cast<unsigned long long>(w & 1u) << 63;
     return __longlong_as_double(static_cast<long long>(static_cast<unsigned long long>(__double_as_longlong(u)) ^ m));
+}
+
+// Partial group sums held by the three preceding lanes: lane l receives
+// tail(l-1), plus tail(l-2) when lane l-1 has no group boundary, plus tail(l-3)
+// when lane l-2 has none either (f: the lane has a group boundary).
+template <typename T>
+__device__ __forceinline__ T carry3(T tail, int f) {
+    const T t1 = dpp_t<kWaveShr1, 0xf>(tail);
+    const int f1 = dpp_i<kWaveShr1, 0xf>(f);
+    const T t2 = dpp_t<kWaveShr1, 0xf>(t1);
+    const int f2 = dpp_i<kWaveShr1, 0xf>(f1);
+    const T t3 = dpp_t<kWaveShr1, 0xf>(t2);
+    return t1 + (f1 ? T(0) : t2 + (f2 ? T(0) : t3));
 }
 
 // ---- pieces of the two kernel forms ------------------------------------------
@@ -192,41 +188,46 @@ __device__ __forceinline__ void abx_store_w(T *W, const typename Mfma<T>::acc_t 
                 W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
 }
 
-// Beta-side scatter of one tile by one wave (plan entries ent of this lane).
-// Branch-free: writes that end no group go to the lane's discard slot `spare`.
+// Beta-side scatter of one tile by one wave; w, hdr: this lane's plan words.
+// Every entry writes old + running group sum to its slot (the group's target
+// at the group's last entry, the discard slot otherwise), so no two lanes write
+// one target and the writes need no branches.
 template <typename T, int EW>
-__device__ __forceinline__ void abx_scatter(const T *W, T *sig, const uint32_t (&ent)[EW], int lane, uint32_t spare) {
+__device__ __forceinline__ void abx_scatter(const T *W, T *sig, const uint32_t (&w)[EW], uint32_t hdr,
+                                            uint32_t spare) {
+    constexpr int TS = sizeof(T) == 4 ? 0 : 3;   // slot field unit: bytes (FP32), elements (FP64)
     const char *wb = reinterpret_cast<const char *>(W);
     char *sb = reinterpret_cast<char *>(sig);
-    auto tgt = [&](int q) { return (ent[q] >> 14) & 0x1fffcu; };
     T val[EW], old[EW];
+    uint32_t t[EW];
 #pragma unroll
     for (int q = 0; q < EW; ++q) {
-        val[q] = flip_if(*reinterpret_cast<const T *>(wb + (ent[q] & 0xfffcu)), ent[q]);
-        old[q] = *reinterpret_cast<const T *>(sb + tgt(q));
+        t[q] = (w[q] >> 16) << TS;
+        val[q] = flip_if(*reinterpret_cast<const T *>(wb + (w[q] & 0xfffeu)), w[q]);
+        old[q] = *reinterpret_cast<const T *>(sb + t[q]);
     }
-    // entry q ends a group when entry q+1 starts one; the lane's last entry
-    // does when the next lane's first one starts a group (the last lane: always)
-    const int nx = __builtin_amdgcn_update_dpp(int(0x80000000u), int(ent[0]), kWaveShl1, 0xf, 0xf, false);
-    const bool end_last = lane == 63 || nx < 0;
     T run = 0;
-    bool seen_end = false, any_start = false;
-    uint32_t first_end = spare;
+    bool any_start = (hdr & 1u) != 0;
 #pragma unroll
     for (int q = 0; q < EW; ++q) {
-        const bool st = int(ent[q]) < 0;
+        // entry q starts a group when entry q-1 ended one
+        const bool st = q == 0 ? (hdr & 1u) != 0 : t[q - 1] != spare;
         any_start = any_start || st;
         run = st ? val[q] : run + val[q];
-        const bool en = (q + 1 < EW) ? int(ent[q + 1]) < 0 : end_last;
-        *reinterpret_cast<T *>(sb + (en ? tgt(q) : spare)) = old[q] + run;
-        first_end = (en && !seen_end) ? tgt(q) : first_end;
-        seen_end = seen_end || en;
+        *reinterpret_cast<T *>(sb + t[q]) = old[q] + run;
     }
-    // the group open at the end of each lane continues in the next lanes; a
-    // lane whose first group began earlier adds what those lanes hold
-    const T carry = wave_segmented_carry<T>(end_last ? T(0) : run, any_start ? 1 : 0);
-    T *d = reinterpret_cast<T *>(sb + (int(ent[0]) >= 0 ? first_end : spare));
+    const T tail = t[EW - 1] != spare ? T(0) : run;   // the part of a group that continues in the next lane
+    const T carry = carry3<T>(tail, any_start ? 1 : 0);
+    T *d = reinterpret_cast<T *>(sb + (hdr & ~3u));
     *d = *d + carry;
+}
+
+template <int EW>
+__device__ __forceinline__ void abx_plan_load(__amdgpu_buffer_rsrc_t pr, uint32_t pl, uint32_t soff, uint32_t (&w)[EW],
+                                              uint32_t &hdr) {
+#pragma unroll
+    for (int q = 0; q < EW; ++q) w[q] = buffer_ld_u32(pr, pl + q * 256u, soff);
+    hdr = buffer_ld_u32(pr, pl + EW * 256u, soff);
 }
 
 // ---- four-wave form (FP64): every wave multiplies and scatters ----------------
@@ -241,7 +242,8 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_x(AbxArgs<T> p) {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int RBW = (RB + 1) / 2;
     constexpr int MP = 16 * RB;
-    constexpr int PT = 4 * EW * 64;
+    constexpr int PW = (EW + 1) * 64;                      // plan words per wave and tile
+    constexpr int PT = 4 * PW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *W = reinterpret_cast<T *>(smem_raw);                // [MP][WS]
     T *sig = W + MP * kAbxWS;                              // [ld + 64]: slots ld.. take discarded writes
@@ -259,29 +261,28 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_x(AbxArgs<T> p) {
 
     const int ntile = p.ld / kAbxNT;
     const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes), pr = buffer_of(p.plan, p.plan_bytes);
-    const uint32_t pl = uint32_t(wave * (EW * 64) + lane) * 4u;   // this lane's plan byte offset in a tile
+    const uint32_t pl = uint32_t(wave * PW + lane) * 4u;   // this lane's plan byte offset in a tile
     const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
     T b[KS];
     acc_t acc[RBW];
-    uint32_t ent[EW], ent_next[EW];
+    uint32_t pw_[EW], ph, nw_[EW], nh;
     abx_load<T, KS>(cr, boff, 0, b);
     abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
-#pragma unroll
-    for (int q = 0; q < EW; ++q) ent[q] = buffer_ld_u32(pr, pl + q * 256u, 0u);
+    abx_plan_load<EW>(pr, pl, 0u, pw_, ph);
     __syncthreads();                           // the sigma row is in LDS
     abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
     __syncthreads();
     for (int tile = 0; tile < ntile; ++tile) {
         const int t1 = tile + 1 < ntile ? tile + 1 : tile, t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
-#pragma unroll
-        for (int q = 0; q < EW; ++q) ent_next[q] = buffer_ld_u32(pr, pl + q * 256u, uint32_t(t1) * (PT * 4u));
+        abx_plan_load<EW>(pr, pl, uint32_t(t1) * (PT * 4u), nw_, nh);
         abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);   // next tile's W (after the last: discarded)
-        abx_scatter<T, EW>(W, sig, ent, lane, spare);
+        abx_scatter<T, EW>(W, sig, pw_, ph, spare);
         __syncthreads();                       // W of this tile consumed
         if (tile + 1 < ntile) abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < EW; ++q) ent[q] = ent_next[q];
+        for (int q = 0; q < EW; ++q) pw_[q] = nw_[q];
+        ph = nh;
     }
     for (int cc = tid * VEC; cc < p.ld; cc += 256 * VEC)
         *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
@@ -301,7 +302,8 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
     constexpr int VEC = 16 / sizeof(T);
     constexpr int RBW = (RB + 1) / 2;
     constexpr int MP = 16 * RB;
-    constexpr int PT = 4 * EW * 64;
+    constexpr int PW = (EW + 1) * 64;                      // plan words per wave and tile
+    constexpr int PT = 4 * PW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *W0 = reinterpret_cast<T *>(smem_raw);               // [2][MP][WS]
     T *W1 = W0 + MP * kAbxWS;
@@ -338,19 +340,18 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         }
     } else {
         const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
-        const uint32_t pl = uint32_t((wave - 4) * (EW * 64) + lane) * 4u;
+        const uint32_t pl = uint32_t((wave - 4) * PW + lane) * 4u;
         const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
-        uint32_t ent[EW], ent_next[EW];
-#pragma unroll
-        for (int q = 0; q < EW; ++q) ent[q] = buffer_ld_u32(pr, pl + q * 256u, 0u);
+        uint32_t pw_[EW], ph, nw_[EW], nh;
+        abx_plan_load<EW>(pr, pl, 0u, pw_, ph);
         __syncthreads();                       // W of tile 0 ready
         for (int tile = 0; tile < ntile; ++tile) {
             const int t1 = tile + 1 < ntile ? tile + 1 : tile;
+            abx_plan_load<EW>(pr, pl, uint32_t(t1) * (PT * 4u), nw_, nh);
+            abx_scatter<T, EW>(tile & 1 ? W1 : W0, sig, pw_, ph, spare);
 #pragma unroll
-            for (int q = 0; q < EW; ++q) ent_next[q] = buffer_ld_u32(pr, pl + q * 256u, uint32_t(t1) * (PT * 4u));
-            abx_scatter<T, EW>(tile & 1 ? W1 : W0, sig, ent, lane, spare);
-#pragma unroll
-            for (int q = 0; q < EW; ++q) ent[q] = ent_next[q];
+            for (int q = 0; q < EW; ++q) pw_[q] = nw_[q];
+            ph = nh;
             __syncthreads();                   // tile consumed; the next W is ready
         }
     }
@@ -437,7 +438,7 @@ bool owner_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hi
     if (abx_lds<T>(x.ld, rb_of(x.npair)) > 160 * 1024) return false;
     // 32-bit byte offsets of the gathered rows (the zero row Na included) and of the plan
     const uint64_t cpb = (uint64_t(x.Na) + 1) * uint64_t(x.ld) * sizeof(T);
-    const uint64_t plb = uint64_t(P.ntile) * 4 * P.ew * 64 * sizeof(uint32_t);
+    const uint64_t plb = uint64_t(P.ntile) * 4 * (P.ew + 1) * 64 * sizeof(uint32_t);
     if (cpb >= (uint64_t(1) << 31) || plb >= (uint64_t(1) << 31)) return false;
     x.cp_bytes = uint32_t(cpb);
     x.plan_bytes = uint32_t(plb);
