@@ -11,8 +11,10 @@ Prints one JSON line with
   * cpu_baseline: the CPU oracle (plain Slater-Condon sigma) on a bounded
     random sample of output determinants of the same workload, scaled to
     sigma builds/s;
-  * extra: the FP64 sigma rate, per-pass times and, with --davidson, the time
-    to converge the Davidson energies in FP64 and in mixed precision.
+  * extra: the FP64 sigma rate, per-pass times and the time to converge the
+    Davidson energies (3 roots) in FP64 and in mixed precision (FP32 sigma and
+    basis, FP64 projected problem and final refinement), with the largest
+    energy difference between the two.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16]
 """
@@ -115,8 +117,10 @@ def stored_traffic(kernel_tag):
         return None
 
 
-def davidson_runs(ctx, cis, nroots, tol):
+def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose):
     out = {}
+    ctx.set_option(cis.OPT_MAX_ITER, max_iter)
+    ctx.set_option(cis.OPT_VERBOSE, 1 if verbose else 0)
     for mode, prec in (("fp64", cis.FP64), ("mixed_fp32", cis.FP32)):
         ctx.set_option(cis.OPT_PRECISION, prec)
         t0 = time.perf_counter()
@@ -140,9 +144,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--davidson", action="store_true", help="also time Davidson to convergence, FP64 vs mixed")
+    ap.add_argument("--no-davidson", action="store_true", help="skip timing Davidson to convergence (FP64 vs mixed)")
     ap.add_argument("--nroots", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=300)
+    ap.add_argument("--verbose", action="store_true", help="one line per Davidson iteration on stderr")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain copy kernel of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -196,8 +202,8 @@ def main():
     if args.copy_calibration_mib > 0:
         copy_calibration(torch, args.copy_calibration_mib)
 
-    if args.davidson:
-        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol)
+    if not args.no_davidson:
+        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose)
 
     cpu = None
     if not args.no_cpu:

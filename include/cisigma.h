@@ -69,7 +69,8 @@ extern "C" {
 #define CISIGMA_OPT_PRECISION 1    /* Davidson vectors and sigma: CISIGMA_FP64 (plain) or CISIGMA_FP32 (mixed) */
 #define CISIGMA_OPT_MAX_SPACE 2    /* Davidson subspace size before collapse (>= 2*nroots); default 8*nroots, min 16 */
 #define CISIGMA_OPT_MAX_ITER 3     /* Davidson iteration limit; default 100 */
-#define CISIGMA_OPT_REFINE_EVERY 4 /* mixed mode: rebuild the FP64 sigma of the basis every R iterations; default 8 */
+#define CISIGMA_OPT_REFINE_EVERY 4 /* mixed mode: also refine in FP64 every R iterations; default 0 = only when the
+                                      FP32 iteration meets the convergence test */
 #define CISIGMA_OPT_RESID_TOL 5    /* residual-norm threshold; default sqrt(tol) (mixed: max(sqrt(tol), 1e-5)) */
 #define CISIGMA_OPT_VERBOSE 6      /* print one line per Davidson iteration to stderr when nonzero */
 #define CISIGMA_OPT_PROFILE 7      /* nonzero: time every pass of cisigma_apply with HIP events (resets the totals) */
@@ -198,9 +199,10 @@ int cisigma_hdiag(cisigma_ctx *ctx, double *hdiag, void *stream);
  * max_iter is reached (energies and vectors are the last Ritz values).
  * In mixed mode (CISIGMA_OPT_PRECISION = CISIGMA_FP32) basis vectors and
  * sigma builds are FP32 while the projected matrix, orthogonalisation and
- * residual norms accumulate in FP64, the basis sigma is rebuilt in FP64 every
- * REFINE_EVERY iterations, and the returned energies are FP64 Rayleigh
- * quotients <x|H x>/<x|x> with an FP64 sigma.
+ * residual norms accumulate in FP64; when the FP32 iteration meets the test
+ * (and every REFINE_EVERY iterations if that option is nonzero) the Ritz
+ * vectors get an FP64 sigma, convergence is judged on their FP64 residuals,
+ * and the returned energies are FP64 Rayleigh quotients <x|H x>/<x|x>.
  */
 int cisigma_davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs,
                      cisigma_stats *stats);

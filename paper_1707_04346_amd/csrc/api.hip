@@ -776,7 +776,7 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             ctx->max_iter = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_REFINE_EVERY:
-            if (value < 1 || value > 100000) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: refine_every out of range");
+            if (value < 0 || value > 100000) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: refine_every out of range");
             ctx->refine_every = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_RESID_TOL:

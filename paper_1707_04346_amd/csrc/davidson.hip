@@ -12,10 +12,11 @@
 // host each iteration.  The projected eigenproblem is solved on the host by
 // cyclic Jacobi rotations.
 //
-// Mixed precision (FP32 basis and sigma): every refine_every iterations, and
-// whenever the FP32 iteration meets the convergence test, the Ritz vectors
-// are formed in FP64, their sigma is rebuilt in FP64, and the basis collapses
-// onto them with the FP64 sigma (iterative refinement).  Convergence is only
+// Mixed precision (FP32 basis and sigma): whenever the FP32 iteration meets
+// the convergence test (and, if refine_every > 0, every refine_every
+// iterations), the Ritz vectors are formed in FP64, their sigma is rebuilt in
+// FP64, and the basis collapses onto them with the FP64 sigma (iterative
+// refinement).  Convergence is only
 // declared there, on FP64 residual norms, and the returned energies are the
 // FP64 Rayleigh quotients.
 #include <algorithm>
@@ -32,6 +33,7 @@ namespace cis {
 namespace {
 
 constexpr int kRedBlocks = 1024;
+constexpr int kRitzRoots = 4;     // roots per pass of the batched Ritz kernel
 constexpr int kGroup = 8;
 
 template <typename T>
@@ -82,36 +84,54 @@ __global__ void k_reduce_partials(const double *partial, int nb, int nx, double 
     out[i] = s;
 }
 
-// x = sum_i y_i B_i ; s = sum_i y_i S_i ; r = s - theta x ; t = r / (theta - hd)
-// writes x (FP64), optionally s (storage type) and t; partial sums of r.r
-template <typename T>
-__global__ __launch_bounds__(256) void k_ritz(const T *B, const T *S, int64_t sv, int m, const double *y,
-                                              double theta, const double *hd, double *xout, T *sout, T *tout,
-                                              int64_t N, double *partial) {
+// Ritz vectors, their sigma, residual-norm partials and preconditioned
+// corrections of up to R roots in one pass over the basis (B and S are read
+// once for all roots).  y: [nr][m] root-major coefficients, theta: [nr].
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int64_t sv, int m, int nr,
+                                                    const double *y, const double *theta, const double *hd,
+                                                    double *xout, T *sout, T *tout, int64_t N, double *partial) {
     __shared__ double sh[8];
-    __shared__ double ys[512];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) ys[i] = y[i];
+    __shared__ double ys[R][512];
+    __shared__ double th[R];
+    for (int i = threadIdx.x; i < R * m; i += blockDim.x) ys[i / m][i % m] = (i / m) < nr ? y[i] : 0.0;
+    if (threadIdx.x < R) th[threadIdx.x] = threadIdx.x < nr ? theta[threadIdx.x] : 0.0;
     __syncthreads();
-    double rr = 0;
+    double rr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) rr[r] = 0;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-        double x = 0, s = 0;
+        double x[R], s[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = s[r] = 0;
         for (int i = 0; i < m; ++i) {
-            x += ys[i] * double(B[i * sv + n]);
-            s += ys[i] * double(S[i * sv + n]);
+            const double b = double(B[i * sv + n]), c = double(S[i * sv + n]);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                x[r] += ys[r][i] * b;
+                s[r] += ys[r][i] * c;
+            }
         }
-        double r = s - theta * x;
-        rr += r * r;
-        if (xout) xout[n] = x;
-        if (sout) sout[n] = T(s);
-        if (tout) {
-            double d = theta - hd[n];
-            if (fabs(d) < 1e-8) d = d < 0 ? -1e-8 : 1e-8;
-            tout[n] = T(r / d);
+        const double h = hd[n];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r >= nr) break;
+            const double res = s[r] - th[r] * x[r];
+            rr[r] += res * res;
+            xout[r * N + n] = x[r];
+            sout[r * N + n] = T(s[r]);
+            double dd = th[r] - h;
+            if (fabs(dd) < 1e-8) dd = dd < 0 ? -1e-8 : 1e-8;
+            tout[r * N + n] = T(res / dd);
         }
     }
-    double tot = block_sum(rr, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const double tot = block_sum(rr[r], sh);
+        if (threadIdx.x == 0 && r < nr) partial[int64_t(r) * gridDim.x + blockIdx.x] = tot;
+        __syncthreads();
+    }
 }
 
 // partial sums of |y - e x|^2
@@ -240,7 +260,7 @@ void jacobi_eig(std::vector<double> A, int n, std::vector<double> &w, std::vecto
 struct Dev {
     cisigma_ctx *ctx;
     hipStream_t s;
-    double *partial = nullptr, *dvec = nullptr;
+    double *partial = nullptr, *dvec = nullptr, *ybuf = nullptr;
     int64_t *pidx = nullptr;
     int grid(int64_t N) const {
         int64_t g = (N + 255) / 256;
@@ -304,7 +324,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     }
     auto cleanup = [&]() {
         hipFree(B); hipFree(S); hipFree(SX); hipFree(TB); hipFree(X64); hipFree(hd); hipFree(sig64);
-        hipFree(d.partial); hipFree(d.dvec); hipFree(d.pidx);
+        hipFree(d.partial); hipFree(d.dvec); hipFree(d.pidx); hipFree(d.ybuf);
     };
     struct Guard { std::function<void()> f; ~Guard() { f(); } } guard{cleanup};
     DV_TRY(hipMalloc(&B, size_t(max_space) * N * es));
@@ -318,6 +338,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     // per-block (argmin) or per-vector (dots, <= 512) results
     DV_TRY(hipMalloc(&d.dvec, size_t(std::max(kRedBlocks, 512)) * sizeof(double)));
     DV_TRY(hipMalloc(&d.pidx, kRedBlocks * sizeof(int64_t)));
+    DV_TRY(hipMalloc(&d.ybuf, size_t(kRitzRoots) * (512 + 1) * sizeof(double)));
     DV_TRY(launch_hdiag(ctx, hd, d.s));
 
     const int g = d.grid(N);
@@ -354,6 +375,34 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         if (dtype == CISIGMA_FP32) ++nsig32; else ++nsig64;
         return r;
     };
+    // Ritz vectors (FP64), their sigma and corrections for all roots from the
+    // eigenvectors Yv (m x m, column r = root r); optionally the residual norms
+    auto ritz_all = [&](int mm, const std::vector<double> &Yv, bool norms) -> hipError_t {
+        for (int r0 = 0; r0 < nroots; r0 += kRitzRoots) {
+            const int nr = std::min(kRitzRoots, nroots - r0);
+            std::vector<double> yy(size_t(nr) * mm + nr);
+            for (int r = 0; r < nr; ++r)
+                for (int i = 0; i < mm; ++i) yy[size_t(r) * mm + i] = Yv[size_t(i) * mm + r0 + r];
+            for (int r = 0; r < nr; ++r) yy[size_t(nr) * mm + r] = theta[r0 + r];
+            hipError_t e = hipMemcpyAsync(d.ybuf, yy.data(), yy.size() * sizeof(double), hipMemcpyHostToDevice, d.s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_ritz_multi<T, kRitzRoots>), dim3(g), dim3(256), 0, d.s, B, S, N, mm, nr, d.ybuf,
+                               d.ybuf + size_t(nr) * mm, hd, X64 + int64_t(r0) * N, SX + int64_t(r0) * N,
+                               TB + int64_t(r0) * N, N, d.partial);
+            if (norms) {
+                std::vector<double> part(size_t(nr) * g);
+                e = hipMemcpyAsync(part.data(), d.partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, d.s);
+                if (e == hipSuccess) e = hipStreamSynchronize(d.s);
+                if (e != hipSuccess) return e;
+                for (int r = 0; r < nr; ++r) {
+                    double ss = 0;
+                    for (int b = 0; b < g; ++b) ss += part[size_t(r) * g + b];
+                    rnorm[r0 + r] = std::sqrt(ss);
+                }
+            }
+        }
+        return hipGetLastError();
+    };
     while (true) {
         // (4) sigma of the new vectors and the new columns of G
         for (int k = m; k < m + nnew; ++k) {
@@ -370,23 +419,12 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         jacobi_eig(Gm, m, w, Y);
         ++iter;
         ++since_ref;
+        for (int r = 0; r < nroots; ++r) theta[r] = w[r];
         // Ritz vectors and residual norms
-        std::vector<double> yk(m);
+        DV_TRY(ritz_all(m, Y, true));
         bool all_ok = true;
-        for (int r = 0; r < nroots; ++r) {
-            theta[r] = w[r];
-            for (int i = 0; i < m; ++i) yk[i] = Y[size_t(i) * m + r];
-            DV_TRY(hipMemcpyAsync(d.dvec, yk.data(), m * sizeof(double), hipMemcpyHostToDevice, d.s));
-            hipLaunchKernelGGL((k_ritz<T>), dim3(g), dim3(256), 0, d.s, B, S, N, m, d.dvec, theta[r], hd,
-                               X64 + int64_t(r) * N, SX + int64_t(r) * N, TB + int64_t(r) * N, N, d.partial);
-            std::vector<double> part(g);
-            DV_TRY(hipMemcpyAsync(part.data(), d.partial, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
-            DV_TRY(hipStreamSynchronize(d.s));
-            double ss = 0;
-            for (double v : part) ss += v;
-            rnorm[r] = std::sqrt(ss);
+        for (int r = 0; r < nroots; ++r)
             if (!(std::fabs(theta[r] - theta_old[r]) <= tol && rnorm[r] <= rtol)) all_ok = false;
-        }
         if (ctx->verbose) {
             std::fprintf(stderr, "davidson it %3d dim %3d", iter, m);
             for (int r = 0; r < nroots; ++r) std::fprintf(stderr, "  E%d %.12f |r| %.3e", r, theta[r], rnorm[r]);
@@ -394,7 +432,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         }
         for (int r = 0; r < nroots; ++r) theta_old[r] = theta[r];
         bool refined_now = false;
-        if (mixed && (all_ok || since_ref >= ctx->refine_every || iter >= ctx->max_iter)) {
+        if (mixed && (all_ok || (ctx->refine_every > 0 && since_ref >= ctx->refine_every) || iter >= ctx->max_iter)) {
             // FP64 refinement: rebuild sigma of the Ritz vectors in FP64
             refined_now = true;
             ++nref;
@@ -451,13 +489,8 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int i = 0; i < m; ++i)
                 for (int j = 0; j < m; ++j) Gm2[size_t(i) * m + j] = G[size_t(i) * max_space + j];
             jacobi_eig(Gm2, m, w, Y);
-            for (int r = 0; r < nroots; ++r) {
-                theta[r] = w[r];
-                for (int i = 0; i < m; ++i) yk[i] = Y[size_t(i) * m + r];
-                DV_TRY(hipMemcpyAsync(d.dvec, yk.data(), m * sizeof(double), hipMemcpyHostToDevice, d.s));
-                hipLaunchKernelGGL((k_ritz<T>), dim3(g), dim3(256), 0, d.s, B, S, N, m, d.dvec, theta[r], hd,
-                                   X64 + int64_t(r) * N, SX + int64_t(r) * N, TB + int64_t(r) * N, N, d.partial);
-            }
+            for (int r = 0; r < nroots; ++r) theta[r] = w[r];
+            DV_TRY(ritz_all(m, Y, false));
         } else if (!mixed) {
             if (all_ok) { converged = true; break; }
         }

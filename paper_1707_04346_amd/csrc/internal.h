@@ -166,7 +166,7 @@ struct cisigma_ctx {
     int precision = CISIGMA_FP64;
     int max_space = 0;
     int max_iter = 100;
-    int refine_every = 8;
+    int refine_every = 0;          // mixed mode: 0 = refine only when the FP32 iteration converges
     double resid_tol = -1.0;
     int verbose = 0;
     int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]

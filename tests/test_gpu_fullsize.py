@@ -1,0 +1,123 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+The oracle cannot build whole sigma vectors of 1.6e8 determinants in test
+time, so it computes sampled output determinants one by one (its row-sampled
+Slater-Condon sigma) and the GPU vector is compared there; properties that hold
+at any size check every element:
+
+* symmetry of H:  <C2|H C1> = <C1|H C2> for two random vectors;
+* alpha <-> beta exchange (n_alpha = n_beta):  sigma(C^T) = sigma(C)^T, which
+  runs the alpha and beta halves of every pass on exchanged data.
+
+Tolerances: relative 2-norm over the sample, 1e-10 (FP64) and 1e-5 (FP32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+TOL = {torch.float64: 1e-10, torch.float32: 1e-5}
+
+
+def _cis():
+    import paper_1707_04346_amd as cis
+    return cis
+
+
+def workload(name):
+    w = si.WORKLOADS[name]
+    h, g = si.integrals(w["norb"], w["nchol"], 0)
+    ctx = _cis().Context(w["norb"], w["nalpha"], w["nbeta"], h, g, gas=w["gas"])
+    ref = oracle.Space(w["norb"], w["nalpha"], w["nbeta"], h, g, gas=w["gas"])
+    return ctx, ref
+
+
+def sample_rows(ndet, nrand, seed, extra=()):
+    rng = np.random.default_rng(seed)
+    rows = np.concatenate([rng.integers(0, ndet, nrand), np.asarray(extra, dtype=np.int64)])
+    return np.unique(np.clip(rows, 0, ndet - 1))
+
+
+@pytest.fixture(scope="module")
+def cas16():
+    ctx, ref = workload("cas16")
+    c = si.ci_vector(ctx.ndet, 0)
+    yield ctx, ref, c
+    ctx.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_cas16_sampled_rows(cas16, dtype):
+    """CAS(16,16), 165,636,900 determinants: 4096 random rows plus the first and
+    last rows and the ends of the first and last 32-column tiles."""
+    cis = _cis()
+    ctx, ref, c = cas16
+    n = 12870
+    extra = [0, 1, 31, 32, n - 1, n, ctx.ndet - 1, ctx.ndet - n, (n - 1) * n + 31, (n - 1) * n + n - 32]
+    rows = sample_rows(ctx.ndet, 4096, 21, extra)
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S = torch.empty_like(C)
+    ctx.apply(C, S)
+    torch.cuda.synchronize()
+    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) == \
+        cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
+    got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
+    want = ref.sigma_rows(rows, c)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err <= TOL[dtype], err
+
+
+def test_cas16_symmetric_operator(cas16):
+    ctx, _, _ = cas16
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    C1 = torch.randn(ctx.ndet, dtype=torch.float64, device="cuda", generator=g)
+    C2 = torch.randn(ctx.ndet, dtype=torch.float64, device="cuda", generator=g)
+    S1, S2 = torch.empty_like(C1), torch.empty_like(C2)
+    ctx.apply(C1, S1)
+    ctx.apply(C2, S2)
+    a, b = float(C2 @ S1), float(C1 @ S2)
+    scale = float(torch.linalg.vector_norm(C1) * torch.linalg.vector_norm(S2))
+    assert abs(a - b) <= 1e-12 * scale, (a, b)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_cas16_alpha_beta_exchange(cas16, dtype):
+    """sigma(C^T) = sigma(C)^T for every element: the exchanged vector runs the
+    beta data through the alpha kernels and the other way round."""
+    ctx, _, _ = cas16
+    n = 12870
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6)
+    C = torch.randn(n, n, dtype=dtype, device="cuda", generator=g)
+    Ct = C.t().contiguous()
+    S, St = torch.empty_like(C), torch.empty_like(C)
+    ctx.apply(C.reshape(-1), S.reshape(-1))
+    ctx.apply(Ct.reshape(-1), St.reshape(-1))
+    err = float(torch.linalg.vector_norm(St - S.t()) / torch.linalg.vector_norm(S))
+    assert err <= TOL[dtype], err
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_gas20_sampled_rows(dtype):
+    """GAS(20,20) 6/8/6 with cumulative bounds [10,12], [18,20], [20,20]:
+    22,065,484 determinants in 36 blocks; random rows plus the first and last
+    determinant of every block."""
+    ctx, ref = workload("gas20")
+    c = si.ci_vector(ctx.ndet, 0)
+    offs = ctx.layout()["offset"]
+    extra = list(offs[:-1]) + [int(o) - 1 for o in offs[1:]]
+    rows = sample_rows(ctx.ndet, 2048, 22, extra)
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S = torch.empty_like(C)
+    ctx.apply(C, S)
+    torch.cuda.synchronize()
+    got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
+    want = ref.sigma_rows(rows, c)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    ctx.close()
+    assert err <= TOL[dtype], err
