@@ -102,6 +102,7 @@ void free_ctx(cisigma_ctx *c) {
     hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
     hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
+    hipFree(c->d_act_start); hipFree(c->d_act_tiles);
     for (auto e : c->prof_events) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
@@ -242,6 +243,53 @@ int build_layouts(cisigma_ctx *c) {
     HIP_OR_FAIL(c, upload(&c->bt.tb, tb), "init: block upload");
     HIP_OR_FAIL(c, upload(&c->bt.tr, tr), "init: block upload");
     HIP_OR_FAIL(c, upload(&c->bt.tc, tc), "init: block upload");
+    return CISIGMA_OK;
+}
+
+// Active beta tiles of the general sigma_3 kernel.  A workgroup for source
+// alpha string Ja (type ta) and an output beta tile of type u does work only
+// when some single alpha excitation of Ja lands in a type allowed with u (a
+// sigma block to write) and some single beta excitation into u starts from a
+// type allowed with ta (a C block to read); a single excitation moves at most
+// one electron between GAS spaces.
+int build_active_tiles(cisigma_ctx *c) {
+    const auto &A = c->sp[0], &B = c->sp[1];
+    const int ng = c->gas.ngas;
+    const auto &L = c->pl[0];
+    auto reach = [&](const cis::SpinTables &S, int t) {
+        std::vector<int> out{t};
+        for (int i = 0; i < ng; ++i)
+            for (int j = 0; j < ng; ++j) {
+                if (i == j || S.tocc[size_t(t) * ng + i] == 0) continue;
+                std::vector<int> occ(S.tocc.begin() + size_t(t) * ng, S.tocc.begin() + size_t(t + 1) * ng);
+                --occ[i];
+                ++occ[j];
+                for (int u = 0; u < S.ntype; ++u)
+                    if (std::equal(occ.begin(), occ.end(), S.tocc.begin() + size_t(u) * ng)) out.push_back(u);
+            }
+        return out;
+    };
+    auto allowed = [&](int ta, int tb) { return c->lay.boff[size_t(ta) * B.ntype + tb] >= 0; };
+    std::vector<int> start{0}, tiles;
+    std::vector<std::vector<int>> rb(B.ntype);
+    for (int u = 0; u < B.ntype; ++u) rb[u] = reach(B, u);
+    for (int ta = 0; ta < A.ntype; ++ta) {
+        const auto ra = reach(A, ta);
+        std::vector<char> act(B.ntype, 0);
+        for (int u = 0; u < B.ntype; ++u) {
+            bool out_ok = false, src_ok = false;
+            for (int t2 : ra) out_ok = out_ok || allowed(t2, u);
+            for (int u2 : rb[u]) src_ok = src_ok || allowed(ta, u2);
+            act[u] = out_ok && src_ok;
+        }
+        for (int t = 0; t < L.ntiles; ++t)
+            if (act[L.tile_u[t]]) tiles.push_back(t);
+        start.push_back(int(tiles.size()));
+        c->act_max = std::max(c->act_max, start.back() - start[start.size() - 2]);
+    }
+    if (tiles.empty()) tiles.push_back(0);
+    HIP_OR_FAIL(c, upload(&c->d_act_start, start), "init: active tiles");
+    HIP_OR_FAIL(c, upload(&c->d_act_tiles, tiles), "init: active tiles");
     return CISIGMA_OK;
 }
 
@@ -695,6 +743,7 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
         hipError_t e = cis::build_diag_tables(c);
         if (e != hipSuccess) rc = hip_fail(c, e, "init: diagonal tables");
     }
+    if (!rc) rc = build_active_tiles(c);
     if (!rc) rc = build_scatter_plan(c);
     if (rc) {
         std::fprintf(stderr, "cisigma_init: %s\n", c->err.c_str());

@@ -161,6 +161,11 @@ struct cisigma_ctx {
     cis::Workspace ws[2];          // per dtype (0 FP64, 1 FP32)
     cis::BlockTilesDev bt{};       // tiles of the caller-layout blocks
     cis::ScatterPlan plan;         // beta-side scatter plan of the owner-computes sigma_3 kernel
+    // general sigma_3 kernel: per alpha type, the 64-column beta tiles that can
+    // change sigma (CSR over alpha types; all tiles for one-block spaces)
+    int *d_act_start = nullptr;    // [ntype_a + 1]
+    int *d_act_tiles = nullptr;
+    int act_max = 0;
     hipStream_t stream = nullptr;  // own stream for synchronous calls
     // options
     int precision = CISIGMA_FP64;

@@ -18,6 +18,7 @@
 #include "internal.h"
 #include "mfma.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace cis {
@@ -37,10 +38,12 @@ struct AbArgs {
     const int64_t *seg;          // [nta][ntb]
     const int *ld;               // [ntb]
     const int *tile_u, *tile_c0; // 64-column tiles of the beta types
+    const int *act_start, *act_tiles;   // per alpha type: the tiles that can change sigma
     const T *gp;                 // [n*n][kp]
     int anexc, bnexc, ntb, ntiles;
     int n, kp, Na, Nb;
     int stage;                   // C row of Ja staged in LDS
+    int act_max;                 // longest active-tile list
 };
 
 __device__ __forceinline__ float neg_if(float v, uint32_t s) { return s ? -v : v; }
@@ -119,8 +122,9 @@ __global__ __launch_bounds__(256) void k_sigma_ab(AbArgs<T> p) {
     if (!p.stage && p.ntb == 1 && segrow[0] >= 0) crow_g_base = p.cp + segrow[0] + int64_t(ra) * p.ld[0];
 
     constexpr int HALVES = kTileCols / NT;   // a 64-column layout tile in NT-column pieces
-    for (int item = blockIdx.y; item < p.ntiles * HALVES; item += gridDim.y) {
-        const int tile = item / HALVES;
+    const int act0 = p.act_start[ta], nact = p.act_start[ta + 1] - act0;
+    for (int item = blockIdx.y; item < nact * HALVES; item += gridDim.y) {
+        const int tile = p.act_tiles[act0 + item / HALVES];
         const int u = p.tile_u[tile], c0 = p.tile_c0[tile] + (item % HALVES) * NT;
         const int b0 = p.bstart[u], cnt = p.bstart[u + 1] - b0;
         for (int i = tid; i < KP * DS; i += 256) D[i] = T(0);
@@ -265,7 +269,7 @@ hipError_t run_ab(const AbArgs<T> &a, hipStream_t s) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds_use));
     if (e != hipSuccess) return e;
     // enough workgroups to fill the chip when there are few alpha strings
-    const int items = a.ntiles * (kTileCols / NT);
+    const int items = std::max(a.act_max, 1) * (kTileCols / NT);
     int ysplit = 1;
     while (int64_t(a.Na) * ysplit < 2048 && ysplit < items) ysplit *= 2;
     if (ysplit > items) ysplit = items;
@@ -315,6 +319,9 @@ hipError_t sigma_ab_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStrea
     a.ld = L.d_ld;
     a.tile_u = L.d_tile_u;
     a.tile_c0 = L.d_tile_c0;
+    a.act_start = ctx->d_act_start;
+    a.act_tiles = ctx->d_act_tiles;
+    a.act_max = ctx->act_max;
     a.anexc = A.nexc;
     a.bnexc = B.nexc;
     a.ntb = B.ntype;

@@ -121,3 +121,21 @@ def test_gas20_sampled_rows(dtype):
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
     ctx.close()
     assert err <= TOL[dtype], err
+
+
+def test_cas18_sampled_rows_fp32():
+    """CAS(18,18), 2,363,904,400 determinants (9.5 GB per FP32 vector; element
+    offsets beyond 2^31): FP32 sigma at 1024 random rows plus the first and last."""
+    ctx, ref = workload("cas18")
+    c = si.ci_vector(ctx.ndet, 0)
+    rows = sample_rows(ctx.ndet, 1024, 23, [0, 1, ctx.ndet - 1])
+    C = torch.tensor(c, dtype=torch.float32, device="cuda")
+    S = torch.empty_like(C)
+    ctx.apply(C, S)
+    torch.cuda.synchronize()
+    got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
+    want = ref.sigma_rows(rows, c)
+    del C, S
+    ctx.close()
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert err <= TOL[torch.float32], err
