@@ -65,17 +65,31 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     const int K = blockIdx.x;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ int any_valid;
-    if (tid == 0) any_valid = 0;
+    __shared__ unsigned long long colmask;   // column types some row of this K is allowed with
+    if (tid == 0) {
+        any_valid = 0;
+        colmask = 0;
+    }
     __syncthreads();
     for (int q = tid; q < NE; q += 256) {
         uint32_t w = (q < p.npv) ? p.pairs[int64_t(K) * p.npv + q] : kPairNone;
         rowJ[q] = (w == kPairNone) ? -1 : int(w >> 11);
         pid[q] = int((w >> 1) & 1023u);
         neg[q] = int(w & 1u);
-        if (w != kPairNone) any_valid = 1;
+        if (w != kPairNone) {
+            any_valid = 1;
+            if (p.nto <= 64) {
+                const int t = p.stype[w >> 11];
+                unsigned long long m = 0;
+                for (int u = 0; u < p.nto; ++u)
+                    if (p.seg[int64_t(t) * p.nto + u] >= 0) m |= 1ull << u;
+                atomicOr(&colmask, m);
+            }
+        }
     }
     __syncthreads();
     if (!any_valid) return;
+    const unsigned long long cols = p.nto <= 64 ? colmask : ~0ull;
     for (int idx = tid; idx < MP * KP; idx += 256) {
         int P = idx / KP, Q = idx % KP;
         T val = 0;
@@ -100,6 +114,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
          item += 4 * gridDim.y) {
         const int tile = item / HALVES;
         const int u = p.tile_u[tile];
+        if (!((cols >> (u & 63)) & 1ull)) continue;   // no row of this K lives in column type u
         const int c0 = p.tile_c0[tile] + (item % HALVES) * TW;
         if (u != cur_u) {
             cur_u = u;
