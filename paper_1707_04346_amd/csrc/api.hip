@@ -9,6 +9,7 @@
 // cisigma_apply enqueues: C -> padded copies, sigma_3, sigma_2, sigma_1,
 // padded accumulators -> sigma (Eq. 8: sigma = sigma_1 + sigma_2 + sigma_3).
 #include <algorithm>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -103,6 +104,9 @@ void free_ctx(cisigma_ctx *c) {
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
     hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
     hipFree(c->d_act_start); hipFree(c->d_act_tiles);
+    hipFree(c->go.d_tile_u); hipFree(c->go.d_tile_c0); hipFree(c->go.d_slot); hipFree(c->go.d_act);
+    hipFree(c->go.d_act_start); hipFree(c->go.d_g32); hipFree(c->go.d_g64);
+    hipFree(c->go.plan.d_entries[0]); hipFree(c->go.plan.d_entries[1]);
     for (auto e : c->prof_events) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
@@ -314,36 +318,42 @@ int build_active_tiles(cisigma_ctx *c) {
 // A group may span at most four lanes (the kernel carries partial sums over
 // three).  One encoding per element size.  Without a plan (a shape no kernel
 // covers) the general kernel runs.
-int build_scatter_plan(cisigma_ctx *c) {
+// Where the contributions of one source tile come from and go to.
+struct PlanSpec {
+    int ntile = 0;                                 // 32-column source tiles
+    std::function<int(int, int)> source;           // (tile, column) -> beta string index, -1: none
+    std::function<int(int, int)> w_row;            // orbital pair (k >= l) -> W row
+    int nvirt = 0;                                 // sigma slots (targets < nvirt; discard slots nvirt + lane)
+    uint32_t unit[2] = {8, 4};                     // bytes per unit of the slot field: [FP64, FP32]
+    std::function<int(int)> width;                 // entries per lane the kernel compiles for `need`, 0: none
+};
+
+// Builds the two encodings of a scatter plan into P (P.ew = 0: no plan).
+int make_scatter_plan(cisigma_ctx *c, const PlanSpec &ps, cis::ScatterPlan &P) {
     constexpr int NT = 32, WS = 33;
+    (void)NT;
     const auto &B = c->sp[1];
-    const int ld = c->pl[0].ld[0];
-    const int mp = 16 * ((c->npair + 15) / 16);
-    // 16-bit fields: W byte offsets (FP64 the larger) and slot offsets (FP32 bytes, FP64 elements)
-    if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || size_t(mp) * WS * 8 >= 65536 ||
-        (size_t(ld) + 64) * 4 >= 65536)
-        return CISIGMA_OK;
     std::vector<uint32_t> exc(size_t(B.nstr) * B.nexc), str(B.nstr);
     HIP_OR_FAIL(c, hipMemcpy(exc.data(), B.d_exc, exc.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
     HIP_OR_FAIL(c, hipMemcpy(str.data(), B.d_str, str.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
     struct Item { uint32_t tgt, widx, neg, start, end; };
-    const int ntile = ld / NT;
+    const int ntile = ps.ntile;
     std::vector<std::vector<Item>> tiles(ntile);
     int need = 1;
     for (int t = 0; t < ntile; ++t) {
         auto &tile = tiles[t];
-        for (int col = 0; col < NT; ++col) {
-            const int Jb = t * NT + col;
-            if (Jb >= B.nstr) break;
+        for (int col = 0; col < 32; ++col) {
+            const int Jb = ps.source(t, col);
+            if (Jb < 0) continue;
             for (int e = 0; e < B.nexc; ++e) {
                 const uint32_t w = exc[size_t(Jb) * B.nexc + e];
                 if (w == cis::kExcNone) continue;
                 const int k = (w >> 6) & 31, l = (w >> 1) & 31;
-                tile.push_back({w >> 11, uint32_t(cis::pair_ge(k, l) * WS + col), w & 1u, 0u, 0u});
+                tile.push_back({w >> 11, uint32_t(ps.w_row(std::max(k, l), std::min(k, l)) * WS + col), w & 1u, 0u, 0u});
             }
             for (uint32_t b = str[Jb]; b; b &= b - 1) {
                 const int k = __builtin_ctz(b);
-                tile.push_back({uint32_t(Jb), uint32_t(cis::pair_ge(k, k) * WS + col), 0u, 0u, 0u});
+                tile.push_back({uint32_t(Jb), uint32_t(ps.w_row(k, k) * WS + col), 0u, 0u, 0u});
             }
         }
         std::stable_sort(tile.begin(), tile.end(), [](const Item &a, const Item &b) { return a.tgt < b.tgt; });
@@ -394,8 +404,8 @@ int build_scatter_plan(cisigma_ctx *c) {
         return i == tile.size();
     };
     int ew = 0;
-    for (int cand : {cis::sigma_ab_owner_width(c->sp[0].nexc, c->npair, need), 16}) {
-        if (cand < need || cis::sigma_ab_owner_width(c->sp[0].nexc, c->npair, cand) != cand) continue;
+    for (int cand : {ps.width(need), 16}) {
+        if (cand < need || ps.width(cand) != cand) continue;
         std::vector<std::pair<size_t, size_t>> rg;
         bool ok = true;
         for (int t = 0; t < ntile && ok; ++t) ok = ranges_of(tiles[t], cand, rg);
@@ -407,7 +417,7 @@ int build_scatter_plan(cisigma_ctx *c) {
     std::vector<std::pair<size_t, size_t>> rg;
     for (int es_i = 0; es_i < 2; ++es_i) {
         const uint32_t es = es_i == 0 ? 8 : 4;   // [0]: FP64, [1]: FP32
-        auto &P = plan[es_i];
+        auto &PL = plan[es_i];
         for (int t = 0; t < ntile; ++t) {
             const auto &tile = tiles[t];
             ranges_of(tile, ew, rg);
@@ -415,8 +425,8 @@ int build_scatter_plan(cisigma_ctx *c) {
                 const size_t base = (size_t(t) * 4 + wv) * per_wave;
                 const size_t i = wv < int(rg.size()) ? rg[wv].first : 0, j = wv < int(rg.size()) ? rg[wv].second : 0;
                 for (int lane = 0; lane < 64; ++lane) {
-                    const uint32_t spare = (uint32_t(ld) + lane) * es;          // discard slot, bytes
-                    const uint32_t unit = es == 4 ? 1 : 8;                       // slot field unit, bytes
+                    const uint32_t spare = (uint32_t(ps.nvirt) + lane) * es;    // discard slot, bytes
+                    const uint32_t unit = ps.unit[es_i];                         // slot field unit, bytes
                     uint32_t hdr = spare | 1u;
                     for (int q = 0; q < ew; ++q) {
                         const size_t e = i + size_t(lane) * ew + q;
@@ -432,18 +442,170 @@ int build_scatter_plan(cisigma_ctx *c) {
                                     if (tile[f].end) { hdr = tile[f].tgt * es; break; }
                             }
                         }
-                        P[base + size_t(q) * 64 + lane] = word;
+                        PL[base + size_t(q) * 64 + lane] = word;
                     }
-                    P[base + size_t(ew) * 64 + lane] = hdr;
+                    PL[base + size_t(ew) * 64 + lane] = hdr;
                 }
             }
         }
     }
-    cis::ScatterPlan &SP = c->plan;
-    HIP_OR_FAIL(c, upload(&SP.d_entries[0], plan[0]), "init: scatter plan");
-    HIP_OR_FAIL(c, upload(&SP.d_entries[1], plan[1]), "init: scatter plan");
-    SP.ntile = ntile;
-    SP.ew = ew;
+    HIP_OR_FAIL(c, upload(&P.d_entries[0], plan[0]), "init: scatter plan");
+    HIP_OR_FAIL(c, upload(&P.d_entries[1], plan[1]), "init: scatter plan");
+    P.ntile = ntile;
+    P.ew = ew;
+    return CISIGMA_OK;
+}
+
+int build_scatter_plan(cisigma_ctx *c) {
+    constexpr int WS = 33;
+    const auto &B = c->sp[1];
+    const int ld = c->pl[0].ld[0];
+    const int mp = 16 * ((c->npair + 15) / 16);
+    // 16-bit fields: W byte offsets (FP64 the larger) and slot offsets (FP32 bytes, FP64 elements)
+    if (!c->cas || c->n > 16 || B.nexc == 0 || c->na == 0 || size_t(mp) * WS * 8 >= 65536 ||
+        (size_t(ld) + 64) * 4 >= 65536)
+        return CISIGMA_OK;
+    PlanSpec ps;
+    ps.ntile = ld / 32;
+    ps.source = [&](int t, int col) { const int Jb = t * 32 + col; return Jb < B.nstr ? Jb : -1; };
+    ps.w_row = [](int k, int l) { return cis::pair_ge(k, l); };
+    ps.nvirt = ld;
+    ps.unit[0] = 8;
+    ps.unit[1] = 1;
+    const int anexc = c->sp[0].nexc, npair = c->npair;
+    ps.width = [=](int need) { return cis::sigma_ab_owner_width(anexc, npair, need); };
+    return make_scatter_plan(c, ps, c->plan);
+}
+
+
+// Tables of the owner-computes sigma_3 kernel for GAS spaces (see GasOwner):
+// W rows = orbital pairs k >= l ordered by the GAS spaces of k and l; the
+// gathered rows of an alpha string of type ta = its single excitations ordered
+// by source type (the source type of an excitation depends only on ta, since
+// spaces are contiguous orbital ranges), then the string itself; per alpha type
+// the 32-column source tiles (one beta type each) with the k steps whose
+// gathered rows have a block with that beta type and the row blocks whose
+// pairs move a source of that beta type into a block of ta.  Without a compiled
+// kernel for the shape (or when the tables do not fit) the general kernel runs.
+int build_gas_owner(cisigma_ctx *c) {
+    constexpr int WS = 33;
+    auto &G = c->go;
+    const auto &A = c->sp[0], &B = c->sp[1];
+    const int n = c->n, ng = c->gas.ngas;
+    if (c->cas || c->na == 0 || c->nb == 0 || A.nexc == 0 || B.nexc == 0) return CISIGMA_OK;
+    const int rb = (c->npair + 15) / 16, mp = 16 * rb;
+    const int ks = (A.nexc + 1 + 3) / 4, kp = 4 * ks;
+    if (ks > 32 || rb > 32 || B.ntype > 255 || size_t(mp) * WS * 8 >= 65536 || size_t(B.nstr) + 64 >= 65536)
+        return CISIGMA_OK;
+    if (cis::sigma_ab_gas_width(ks, rb, 1) == 0) return CISIGMA_OK;
+    std::vector<int> space(n, 0);
+    for (int g = 0; g < ng; ++g)
+        for (int o = 0; o < n; ++o)
+            if ((c->gas.mask[g] >> o) & 1u) space[o] = g;
+    std::vector<std::pair<int, int>> pairs;
+    for (int k = 0; k < n; ++k)
+        for (int l = 0; l <= k; ++l) pairs.push_back({k, l});
+    std::stable_sort(pairs.begin(), pairs.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+        return std::make_pair(space[x.first], space[x.second]) < std::make_pair(space[y.first], space[y.second]);
+    });
+    std::vector<int> row_of(c->npair);
+    for (int r = 0; r < c->npair; ++r) row_of[cis::pair_ge(pairs[r].first, pairs[r].second)] = r;
+    // type moved by one electron from space `from` to space `to` (-1: no such type)
+    auto moved = [&](const cis::SpinTables &S, int t, int from, int to) {
+        if (from == to) return t;
+        std::vector<int> occ(S.tocc.begin() + size_t(t) * ng, S.tocc.begin() + size_t(t + 1) * ng);
+        if (occ[from] == 0) return -1;
+        --occ[from];
+        ++occ[to];
+        for (int u = 0; u < S.ntype; ++u)
+            if (std::equal(occ.begin(), occ.end(), S.tocc.begin() + size_t(u) * ng)) return u;
+        return -1;
+    };
+    auto allowed = [&](int ta, int tb) { return ta >= 0 && tb >= 0 && c->lay.boff[size_t(ta) * B.ntype + tb] >= 0; };
+    std::vector<int> gsize(ng, 0);
+    for (int o = 0; o < n; ++o) ++gsize[space[o]];
+    // gathered-row slots of each alpha type
+    std::vector<int> slot(size_t(A.ntype) * kp, -1), slot_src(size_t(A.ntype) * kp, -1);
+    for (int ta = 0; ta < A.ntype; ++ta) {
+        std::vector<int> occ_space, vir_space;   // GAS space of the i-th occupied / virtual orbital
+        for (int g = 0; g < ng; ++g) {
+            const int occ = A.tocc[size_t(ta) * ng + g];
+            for (int q = 0; q < occ; ++q) occ_space.push_back(g);
+            for (int q = occ; q < gsize[g]; ++q) vir_space.push_back(g);
+        }
+        std::vector<std::pair<int, int>> es;   // (source type, excitation index)
+        for (int io = 0; io < c->na; ++io)
+            for (int iv = 0; iv < n - c->na; ++iv)
+                es.push_back({moved(A, ta, occ_space[io], vir_space[iv]), io * (n - c->na) + iv});
+        es.push_back({ta, -2});
+        std::stable_sort(es.begin(), es.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            return unsigned(x.first) < unsigned(y.first);   // no source type (-1) last
+        });
+        for (size_t q = 0; q < es.size(); ++q) {
+            slot[size_t(ta) * kp + q] = es[q].first >= 0 ? es[q].second : -1;
+            slot_src[size_t(ta) * kp + q] = es[q].first;
+        }
+    }
+    // source tiles and the active lists
+    std::vector<int> tu, tc;
+    for (int u = 0; u < B.ntype; ++u)
+        for (int c0 = 0; c0 < B.tcount[u]; c0 += 32) { tu.push_back(u); tc.push_back(c0); }
+    std::vector<uint32_t> act;
+    std::vector<int> astart{0};
+    for (int ta = 0; ta < A.ntype; ++ta) {
+        std::vector<uint32_t> kmask(B.ntype, 0), rmask(B.ntype, 0);
+        for (int u2 = 0; u2 < B.ntype; ++u2) {
+            for (int q = 0; q < kp; ++q)
+                if (allowed(slot_src[size_t(ta) * kp + q], u2)) kmask[u2] |= 1u << (q / 4);
+            for (int r = 0; r < c->npair; ++r) {
+                const int sk = space[pairs[r].first], sl = space[pairs[r].second];
+                // E_kl or E_lk on a source of type u2 moves one electron between the two spaces
+                if (allowed(ta, moved(B, u2, sl, sk)) || allowed(ta, moved(B, u2, sk, sl))) rmask[u2] |= 1u << (r / 16);
+            }
+        }
+        for (size_t t = 0; t < tu.size(); ++t)
+            if (kmask[tu[t]] && rmask[tu[t]]) {
+                act.push_back(uint32_t(t));
+                act.push_back(kmask[tu[t]]);
+                act.push_back(rmask[tu[t]]);
+                act.push_back(uint32_t(tu[t]) | (uint32_t(tc[t]) << 8));
+            }
+        astart.push_back(int(act.size() / 4));
+    }
+    if (act.empty()) act.assign(4, 0u);
+    // (ij|kl) with kl in the grouped row order
+    std::vector<double> g64(size_t(n) * n * mp, 0.0);
+    std::vector<float> g32(g64.size(), 0.0f);
+    for (int ij = 0; ij < n * n; ++ij)
+        for (int r = 0; r < c->npair; ++r) {
+            const double v = c->g[(size_t(ij) * n + pairs[r].first) * n + pairs[r].second];
+            g64[size_t(ij) * mp + r] = v;
+            g32[size_t(ij) * mp + r] = float(v);
+        }
+    PlanSpec ps;
+    ps.ntile = int(tu.size());
+    ps.source = [&](int t, int col) {
+        const int cc = tc[t] + col;
+        return cc < B.tcount[tu[t]] ? B.tstart[tu[t]] + cc : -1;
+    };
+    ps.w_row = [&](int k, int l) { return row_of[cis::pair_ge(k, l)]; };
+    ps.nvirt = B.nstr;
+    ps.unit[0] = 8;
+    ps.unit[1] = 4;
+    ps.width = [=](int need) { return cis::sigma_ab_gas_width(ks, rb, need); };
+    int rc = make_scatter_plan(c, ps, G.plan);
+    if (rc || G.plan.ew == 0) return rc;
+    HIP_OR_FAIL(c, upload(&G.d_tile_u, tu), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_tile_c0, tc), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_slot, slot), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_act, act), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_act_start, astart), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_g64, g64), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_g32, g32), "init: GAS owner tables");
+    G.nsrc = int(tu.size());
+    G.nvirt = B.nstr;
+    G.ks = ks;
+    G.rb = rb;
     return CISIGMA_OK;
 }
 
@@ -453,7 +615,8 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
     // one-block spaces: one extra zero row after each copy (rows the owner-computes
     // sigma_3 and the pair-product kernels read in place of missing ones)
-    const int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
+    int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
+    if (c->go.ks) for (int ld : c->pl[0].ld) zero_row = std::max<int64_t>(zero_row, ld);
     size_t na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
     size_t nb = size_t(std::max<int64_t>(c->pl[1].size + (c->cas ? c->pl[1].ld[0] : 0), 1)) * es;
     size_t fr = 0, tot = 0;
@@ -745,6 +908,7 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
     }
     if (!rc) rc = build_active_tiles(c);
     if (!rc) rc = build_scatter_plan(c);
+    if (!rc) rc = build_gas_owner(c);
     if (rc) {
         std::fprintf(stderr, "cisigma_init: %s\n", c->err.c_str());
         free_ctx(c);

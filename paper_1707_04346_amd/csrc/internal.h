@@ -125,6 +125,27 @@ struct ScatterPlan {
     int ew = 0;                                    // entries per lane and tile (0: no plan)
 };
 
+// Owner-computes sigma_3 for GAS spaces: W rows are the orbital pairs grouped
+// by the GAS spaces of their two orbitals, the gathered rows of an alpha string
+// are its single excitations grouped by source type, and every alpha type has
+// the list of 32-column source tiles (of one beta type each) that can change
+// its sigma, with the k steps and row blocks that can.
+struct GasOwner {
+    int ks = 0, rb = 0;                  // k steps (4 gathered rows each), 16-row blocks of W
+    int nsrc = 0;                        // source tiles over all beta types
+    int *d_tile_u = nullptr;             // [nsrc] beta type of each source tile
+    int *d_tile_c0 = nullptr;            // [nsrc] first column inside that type
+    int *d_slot = nullptr;               // [ntype_a][4*ks] excitation index of each gathered row,
+                                         //   -2: the string itself, -1: none
+    uint32_t *d_act = nullptr;           // [.][4] per alpha type: {tile, k-step mask, row-block mask,
+                                         //   beta type | first column << 8}
+    int *d_act_start = nullptr;          // [ntype_a + 1]
+    float *d_g32 = nullptr;              // [n*n][16*rb] (ij|kl), kl in the grouped row order
+    double *d_g64 = nullptr;
+    ScatterPlan plan;                    // beta-side plan over the source tiles (slots: elements)
+    int nvirt = 0;                       // beta strings (length of the LDS sigma row)
+};
+
 struct Workspace {
     void *cp = nullptr;    // C in the alpha-major padded layout
     void *sp = nullptr;    // sigma accumulator, alpha-major padded layout
@@ -166,6 +187,7 @@ struct cisigma_ctx {
     int *d_act_start = nullptr;    // [ntype_a + 1]
     int *d_act_tiles = nullptr;
     int act_max = 0;
+    cis::GasOwner go;              // owner-computes sigma_3 tables for GAS spaces (go.ks = 0: none)
     hipStream_t stream = nullptr;  // own stream for synchronous calls
     // options
     int precision = CISIGMA_FP64;
@@ -205,6 +227,11 @@ bool launch_sigma_ab_owner(const cisigma_ctx *ctx, const void *C, void *sigma, i
 // plan width (entries per lane and tile) the owner-computes kernel uses for a
 // shape that needs `need`; 0 when no compiled kernel covers it
 int sigma_ab_owner_width(int anexc, int npair, int need);
+// the same for the GAS owner-computes kernel with ks k steps and rb row blocks
+int sigma_ab_gas_width(int ks, int rb, int need);
+// owner-computes sigma_3 on a GAS space: false when no compiled kernel covers it
+bool launch_sigma_ab_gas(const cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s,
+                         hipError_t *err);
 // Ys == nullptr: scatter with atomics into Y (Y holds what to add to).
 // Ys != nullptr (one-type spins): materialise into Ys chunk by chunk (chunk
 // columns, a multiple of 64) and gather into Y, overwriting Y.

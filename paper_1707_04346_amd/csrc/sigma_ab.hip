@@ -334,9 +334,10 @@ hipError_t sigma_ab_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStrea
                                          : reinterpret_cast<const T *>(ctx->d_gp64);
     int ks = ks_for(ctx->kp);
     a.kp = ctx->kp;
-    if (ctx->cas && ctx->ab_mode != 1) {
+    if (ctx->ab_mode != 1) {
         hipError_t e = hipSuccess;
-        if (launch_sigma_ab_owner(ctx, cp, sp, sizeof(T) == 4 ? CISIGMA_FP32 : CISIGMA_FP64, s, &e)) {
+        const int dt = sizeof(T) == 4 ? CISIGMA_FP32 : CISIGMA_FP64;
+        if (ctx->cas ? launch_sigma_ab_owner(ctx, cp, sp, dt, s, &e) : launch_sigma_ab_gas(ctx, cp, sp, dt, s, &e)) {
             if (e == hipSuccess) const_cast<cisigma_ctx *>(ctx)->last_path[sizeof(T) == 4] |= CISIGMA_PATH_AB_OWNER;
             return e;
         }

@@ -204,10 +204,32 @@ def test_cas_takes_the_fast_paths(case, dtype):
     assert rel(s, ref.sigma(c)) <= tol
 
 
-def test_gas_takes_the_general_path():
+@pytest.mark.parametrize("case", [(7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])),
+                                  (8, 3, 4, ([3, 5], [5, 7], [6, 7])),
+                                  (6, 3, 3, ([2, 2, 2], [0, 0, 6], [6, 6, 6]))], ids=["gas7", "gas8", "gas6open"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_gas_takes_the_owner_path(case, dtype):
+    """GAS spaces run the owner-computes sigma_3 kernel with per-type source
+    tiles (same-spin parts on the general kernels), and stay exact."""
     cis = _cis()
-    ctx, ref = make(7, 3, 3, gas=([2, 3, 2], [3, 5, 6], [4, 6, 6]))
-    c = si.ci_vector(ctx.ndet, 15)
-    s = gpu_sigma(ctx, c, torch.float64)
-    assert ctx.last_path(cis.FP64) == 0
-    assert rel(s, ref.sigma(c)) <= TOL64
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, gas=gas, seed=16)
+    c = si.ci_vector(ctx.ndet, 17)
+    s = gpu_sigma(ctx, c, dtype)
+    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) == cis.PATH_AB_OWNER
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert rel(s, ref.sigma(c)) <= tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_gas_general_path_matches_oracle(dtype):
+    """The general (atomic) sigma_3 kernel on GAS spaces, forced."""
+    cis = _cis()
+    for norb, na, nb, gas in [(7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])), (8, 3, 4, ([3, 5], [5, 7], [6, 7]))]:
+        ctx, ref = make(norb, na, nb, gas=gas, seed=18)
+        ctx.set_option(cis.OPT_SIGMA_PATH, 1)
+        c = si.ci_vector(ctx.ndet, 19)
+        s = gpu_sigma(ctx, c, dtype)
+        assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) == 0
+        tol = TOL64 if dtype == torch.float64 else TOL32
+        assert rel(s, ref.sigma(c)) <= tol
