@@ -288,21 +288,26 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_x(AbxArgs<T> p) {
         *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
 }
 
-// ---- eight-wave form (FP32): four producing and four scattering waves ---------
+// ---- eight-wave form (FP32): six producing and two scattering waves ----------
 //
-// Waves 0-3 compute W of tile t+1 into one of two W buffers while waves 4-7
-// scatter tile t from the other; one barrier per tile.  The SIMDs interleave
-// the two kinds of work (matrix cores against vector ALU and LDS) and each role
-// keeps only its own registers.  LDS: two W tiles and the sigma row (~88 KB for
-// CAS(16,16)).
+// On gfx950 an FP32 MFMA keeps its SIMD from issuing vector instructions of
+// other waves, so a scatter wave that shares a SIMD with a producing wave waits
+// out every matrix instruction.  The roles are therefore split by SIMD: the
+// eight waves of a workgroup are placed on the four SIMDs in turn (wave w on
+// SIMD w mod 4), waves 3 and 7 scatter (the four plan ranges of a tile, two
+// each) and share one SIMD, and the other six multiply -- three 16-row-block
+// groups x two 16-column halves -- on the other three SIMDs.  Waves 0-2 and
+// 4-6 compute W of tile t+1 into one of two W buffers while waves 3 and 7
+// scatter tile t from the other; one barrier per tile.  LDS: two W tiles and
+// the sigma row (~88 KB for CAS(16,16)).
 template <typename T, int KS, int RB, int EW>
 __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
     using acc_t = typename Mfma<T>::acc_t;
     using vec_t = typename Mfma<T>::vec_t;
     constexpr int VEC = 16 / sizeof(T);
-    constexpr int RBW = (RB + 1) / 2;
+    constexpr int RBW = (RB + 2) / 3;
     constexpr int MP = 16 * RB;
-    constexpr int PW = (EW + 1) * 64;                      // plan words per wave and tile
+    constexpr int PW = (EW + 1) * 64;                      // plan words per range and tile
     constexpr int PT = 4 * PW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *W0 = reinterpret_cast<T *>(smem_raw);               // [2][MP][WS]
@@ -317,9 +322,10 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
     const int ntile = p.ld / kAbxNT;
     __syncthreads();                           // the sigma row is in LDS
-    if (wave < 4) {
-        const int cb = wave & 1, grp = wave >> 1;
-        const int rb0 = grp == 0 ? 0 : RBW, nrb = grp == 0 ? RBW : RB - RBW;
+    if ((wave & 3) != 3) {
+        const int m = (wave >> 2) * 3 + (wave & 3);        // 0..5
+        const int cb = m & 1, rb0 = (m >> 1) * RBW;
+        const int nrb = RB - rb0 < RBW ? RB - rb0 : RBW;   // may be <= 0 for small RB
         T A[RBW][KS];
         uint32_t boff[KS];
         abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
@@ -340,19 +346,29 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         }
     } else {
         const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
-        const uint32_t pl = uint32_t((wave - 4) * PW + lane) * 4u;
+        const int sw = wave >> 2;                          // plan ranges sw and sw + 2
+        const uint32_t pl0 = uint32_t(sw * PW + lane) * 4u, pl1 = uint32_t((sw + 2) * PW + lane) * 4u;
         const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
-        uint32_t pw_[EW], ph, nw_[EW], nh;
-        abx_plan_load<EW>(pr, pl, 0u, pw_, ph);
+        // two tiles per trip, plan words in alternating registers: the words of
+        // the next tile stay in flight for a whole tile, across the barrier
+        uint32_t pa0[EW], ha0, pa1[EW], ha1, pb0[EW], hb0, pb1[EW], hb1;
+        abx_plan_load<EW>(pr, pl0, 0u, pa0, ha0);
+        abx_plan_load<EW>(pr, pl1, 0u, pa1, ha1);
         __syncthreads();                       // W of tile 0 ready
-        for (int tile = 0; tile < ntile; ++tile) {
-            const int t1 = tile + 1 < ntile ? tile + 1 : tile;
-            abx_plan_load<EW>(pr, pl, uint32_t(t1) * (PT * 4u), nw_, nh);
-            abx_scatter<T, EW>(tile & 1 ? W1 : W0, sig, pw_, ph, spare);
-#pragma unroll
-            for (int q = 0; q < EW; ++q) pw_[q] = nw_[q];
-            ph = nh;
+        for (int tile = 0; tile < ntile; tile += 2) {
+            const int t1 = tile + 1 < ntile ? tile + 1 : tile, t2 = tile + 2 < ntile ? tile + 2 : t1;
+            abx_plan_load<EW>(pr, pl0, uint32_t(t1) * (PT * 4u), pb0, hb0);
+            abx_plan_load<EW>(pr, pl1, uint32_t(t1) * (PT * 4u), pb1, hb1);
+            abx_scatter<T, EW>(W0, sig, pa0, ha0, spare);
+            abx_scatter<T, EW>(W0, sig, pa1, ha1, spare);
             __syncthreads();                   // tile consumed; the next W is ready
+            if (tile + 1 < ntile) {
+                abx_plan_load<EW>(pr, pl0, uint32_t(t2) * (PT * 4u), pa0, ha0);
+                abx_plan_load<EW>(pr, pl1, uint32_t(t2) * (PT * 4u), pa1, ha1);
+                abx_scatter<T, EW>(W1, sig, pb0, hb0, spare);
+                abx_scatter<T, EW>(W1, sig, pb1, hb1, spare);
+                __syncthreads();
+            }
         }
     }
     for (int cc = tid * VEC; cc < p.ld; cc += 512 * VEC)
