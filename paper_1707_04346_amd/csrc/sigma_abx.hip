@@ -230,61 +230,85 @@ __device__ __forceinline__ void abx_plan_load(__amdgpu_buffer_rsrc_t pr, uint32_
     hdr = buffer_ld_u32(pr, pl + EW * 256u, soff);
 }
 
-// ---- four-wave form (FP64): every wave multiplies and scatters ----------------
+// ---- eight-wave form with one W buffer (FP64) ------------------------------------
 //
-// The four waves are 2 column halves x 2 groups of row blocks.  Per tile one
-// branch-free stretch holds the next tile's products and this tile's scatter,
-// then W is stored between two barriers.  LDS: the W tile and the sigma row.
+// The roles are split by SIMD as in the FP32 form below (waves 3 and 7 scatter,
+// the other six multiply), but the FP64 sigma row leaves room for one W tile
+// only: the producing waves compute the next tile's W in registers while the
+// scatter waves consume this tile's, and store it between two barriers.
 template <typename T, int KS, int RB, int EW>
-__global__ __launch_bounds__(256, 1) void k_sigma_ab_x(AbxArgs<T> p) {
+__global__ __launch_bounds__(512, 1) void k_sigma_ab_x(AbxArgs<T> p) {
     using acc_t = typename Mfma<T>::acc_t;
     using vec_t = typename Mfma<T>::vec_t;
     constexpr int VEC = 16 / sizeof(T);
-    constexpr int RBW = (RB + 1) / 2;
+    constexpr int RBW = (RB + 2) / 3;
     constexpr int MP = 16 * RB;
-    constexpr int PW = (EW + 1) * 64;                      // plan words per wave and tile
+    constexpr int PW = (EW + 1) * 64;                      // plan words per range and tile
     constexpr int PT = 4 * PW;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *W = reinterpret_cast<T *>(smem_raw);                // [MP][WS]
     T *sig = W + MP * kAbxWS;                              // [ld + 64]: slots ld.. take discarded writes
 
     const int Ia = blockIdx.x;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int cb = wave & 1, grp = wave >> 1;
-    const int rb0 = grp == 0 ? 0 : RBW, nrb = grp == 0 ? RBW : RB - RBW;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the roles branch per wave
     const int64_t rowoff = int64_t(Ia) * p.ld;
-    for (int c = tid * VEC; c < p.ld; c += 256 * VEC)
+    for (int c = tid * VEC; c < p.ld; c += 512 * VEC)
         *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
-    T A[RBW][KS];
-    uint32_t boff[KS];
-    abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
-
     const int ntile = p.ld / kAbxNT;
-    const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes), pr = buffer_of(p.plan, p.plan_bytes);
-    const uint32_t pl = uint32_t(wave * PW + lane) * 4u;   // this lane's plan byte offset in a tile
-    const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
-    T b[KS];
-    acc_t acc[RBW];
-    uint32_t pw_[EW], ph, nw_[EW], nh;
-    abx_load<T, KS>(cr, boff, 0, b);
-    abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
-    abx_plan_load<EW>(pr, pl, 0u, pw_, ph);
-    __syncthreads();                           // the sigma row is in LDS
-    abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
-    __syncthreads();
-    for (int tile = 0; tile < ntile; ++tile) {
-        const int t1 = tile + 1 < ntile ? tile + 1 : tile, t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
-        abx_plan_load<EW>(pr, pl, uint32_t(t1) * (PT * 4u), nw_, nh);
-        abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);   // next tile's W (after the last: discarded)
-        abx_scatter<T, EW>(W, sig, pw_, ph, spare);
-        __syncthreads();                       // W of this tile consumed
-        if (tile + 1 < ntile) abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < EW; ++q) pw_[q] = nw_[q];
-        ph = nh;
+    if ((wave & 3) != 3) {
+        const int m = (wave >> 2) * 3 + (wave & 3);        // 0..5
+        const int cb = m & 1, rb0 = (m >> 1) * RBW;
+        const int nrb = RB - rb0 < RBW ? RB - rb0 : RBW;   // may be <= 0 for small RB
+        T A[RBW][KS];
+        uint32_t boff[KS];
+        abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes);
+        T b[KS];
+        acc_t acc[RBW];
+        abx_load<T, KS>(cr, boff, 0, b);
+        abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
+        __syncthreads();                       // the sigma row is in LDS
+        abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
+        __syncthreads();                       // W of tile 0 ready
+        for (int tile = 0; tile < ntile; ++tile) {
+            if (tile + 1 < ntile) {
+                const int t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
+                abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);
+            }
+            __syncthreads();                   // W of this tile consumed
+            if (tile + 1 < ntile) abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
+            __syncthreads();                   // W of the next tile ready
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
+        const int sw = wave >> 2;                          // plan ranges sw and sw + 2
+        const uint32_t pl0 = uint32_t(sw * PW + lane) * 4u, pl1 = uint32_t((sw + 2) * PW + lane) * 4u;
+        const uint32_t spare = uint32_t(p.ld + lane) * uint32_t(sizeof(T));
+        uint32_t pa0[EW], ha0, pa1[EW], ha1, pb0[EW], hb0, pb1[EW], hb1;
+        abx_plan_load<EW>(pr, pl0, 0u, pa0, ha0);
+        abx_plan_load<EW>(pr, pl1, 0u, pa1, ha1);
+        __syncthreads();                       // the sigma row is in LDS
+        __syncthreads();                       // W of tile 0 ready
+        for (int tile = 0; tile < ntile; tile += 2) {
+            const int t1 = tile + 1 < ntile ? tile + 1 : tile, t2 = tile + 2 < ntile ? tile + 2 : t1;
+            abx_plan_load<EW>(pr, pl0, uint32_t(t1) * (PT * 4u), pb0, hb0);
+            abx_plan_load<EW>(pr, pl1, uint32_t(t1) * (PT * 4u), pb1, hb1);
+            abx_scatter<T, EW>(W, sig, pa0, ha0, spare);
+            abx_scatter<T, EW>(W, sig, pa1, ha1, spare);
+            __syncthreads();                   // W of this tile consumed
+            __syncthreads();                   // W of the next tile ready
+            if (tile + 1 < ntile) {
+                abx_plan_load<EW>(pr, pl0, uint32_t(t2) * (PT * 4u), pa0, ha0);
+                abx_plan_load<EW>(pr, pl1, uint32_t(t2) * (PT * 4u), pa1, ha1);
+                abx_scatter<T, EW>(W, sig, pb0, hb0, spare);
+                abx_scatter<T, EW>(W, sig, pb1, hb1, spare);
+                __syncthreads();
+                __syncthreads();
+            }
+        }
     }
-    for (int cc = tid * VEC; cc < p.ld; cc += 256 * VEC)
+    for (int cc = tid * VEC; cc < p.ld; cc += 512 * VEC)
         *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
 }
 
@@ -375,8 +399,6 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
 }
 
-// LDS bytes: the W tile (two for the eight-wave FP32 form) and the sigma row
-// with its 64 discard slots
 // ---- GAS spaces: owner-computes with per-type source tiles ---------------------
 //
 // One workgroup per output alpha string Ia of type ta; four waves as in the
@@ -653,6 +675,8 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     return false;
 }
 
+// LDS bytes: the W tile (two for the eight-wave FP32 form) and the sigma row
+// with its 64 discard slots
 template <typename T>
 size_t abx_lds(int ld, int rb) {
     const size_t nw = sizeof(T) == 4 ? 2 : 1;
@@ -672,7 +696,7 @@ hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RB, EW>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW>), dim3(a.Na), dim3(256), lds, s, a);
+        hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW>), dim3(a.Na), dim3(512), lds, s, a);
     }
     return hipGetLastError();
 }
