@@ -192,8 +192,9 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32"],
                 "traffic": stored_traffic("k_sigma_ab_ws" if owner else "k_sigma_ab") if args.workload == "cas16" else None,
-                "kernel": ("k_sigma_ab_ws (owner-computes sigma_3: gathered C rows -> FP32 MFMA on four waves, "
-                           "LDS scatter on four waves)" if owner else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
+                "kernel": ("k_sigma_ab_ws (owner-computes sigma_3: gathered C rows -> FP32 MFMA on six waves over "
+                           "three SIMDs, LDS scatter on two waves on the fourth)" if owner
+                           else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
                 "flops_per_launch": flops, "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
     if not args.no_fp64:
