@@ -13,10 +13,16 @@ library never loads it and shares no code with it.
   sigma and re-diagonalisation of the projected matrix), with numpy's ``eigh``
   for the small projected problem.
 
+* ``parity_basis`` / ``parity_spectrum``: the M_S = 0 sectors of Sec. 3.1 and
+  Sec. 3.3 (vectors symmetric or antisymmetric under alpha <-> beta string
+  exchange) and the dense spectrum of H inside them.
+
 Parity status: pinned (see ``tests/test_oracle.py``) against a brute-force
 second-quantised construction of Eq. 6, the two-site Hubbard closed form, the
 non-interacting closed form, spin and transposition symmetry, GAS = projected
-CAS, and dense ``eigh``.
+CAS, and dense ``eigh``; the sectors against the full spectrum, total spin
+(even S in the symmetric sector, odd S in the antisymmetric one) and the
+Hubbard closed form.
 """
 import ctypes
 import os
@@ -185,6 +191,39 @@ class Space:
         rc = _load().or_hmat(self._h, _ptr(out))
         assert rc == 0
         return out
+
+
+def parity_basis(nside, parity):
+    """Orthonormal basis (rows) of the M_S = 0 sector of a one-block space of
+    nside x nside determinants: vectors with C(Ib, Ia) = parity * C(Ia, Ib)
+    (Sec. 3.1, Sec. 3.3: for M_S = 0 the work is done on combinations of a
+    determinant and its alpha <-> beta exchanged partner).  The basis holds
+    (|Ia Ib> + parity |Ib Ia>)/sqrt(2) for Ia < Ib and, for parity = +1, the
+    diagonal determinants |Ia Ia>."""
+    rows = []
+    r2 = 1.0 / np.sqrt(2.0)
+    for a in range(nside):
+        for b in range(a, nside):
+            if a == b and parity < 0:
+                continue
+            v = np.zeros(nside * nside)
+            if a == b:
+                v[a * nside + a] = 1.0
+            else:
+                v[a * nside + b] = r2
+                v[b * nside + a] = parity * r2
+            rows.append(v)
+    return np.array(rows).reshape(len(rows), nside * nside)
+
+
+def parity_spectrum(space, parity):
+    """Eigenvalues (ascending) of H restricted to the M_S = 0 sector of
+    ``parity_basis``: dense eigh of Q H Q^T (tiny spaces only)."""
+    n = int(round(np.sqrt(space.ndet)))
+    if n * n != space.ndet:
+        raise ValueError("the sector needs a one-block space with n_alpha = n_beta")
+    Q = parity_basis(n, parity)
+    return np.linalg.eigvalsh(Q @ space.hmat() @ Q.T)
 
 
 def davidson(space, nroots=1, tol=1e-10, rtol=None, max_iter=200, max_space=None,

@@ -392,3 +392,54 @@ def test_davidson_cas8_vs_dense():
     w = np.linalg.eigvalsh(S.hmat())
     e, _, info = oracle.davidson(S, 2, tol=1e-10)
     assert np.allclose(e, w[:2], atol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# M_S = 0 sectors (Sec. 3.1, Sec. 3.3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("norb,ne,seed", [(5, 2, 3), (4, 2, 8), (6, 3, 1)])
+def test_parity_sectors_split_the_spectrum(norb, ne, seed):
+    """The two sectors are orthogonal complements invariant under H (which
+    commutes with alpha <-> beta exchange), so their spectra together are the
+    whole spectrum."""
+    h, g = si.integrals(norb, 2 * norb, seed)
+    S = oracle.Space(norb, ne, ne, h, g)
+    n = int(round(math.sqrt(S.ndet)))
+    Qe, Qo = oracle.parity_basis(n, 1), oracle.parity_basis(n, -1)
+    assert Qe.shape[0] == n * (n + 1) // 2 and Qo.shape[0] == n * (n - 1) // 2
+    Q = np.vstack([Qe, Qo])
+    assert np.abs(Q @ Q.T - np.eye(S.ndet)).max() < 1e-14
+    H = S.hmat()
+    assert np.abs(Qe @ H @ Qo.T).max() < 1e-12
+    both = np.sort(np.concatenate([oracle.parity_spectrum(S, 1), oracle.parity_spectrum(S, -1)]))
+    assert np.allclose(both, np.linalg.eigvalsh(H), atol=1e-11)
+
+
+@pytest.mark.parametrize("norb,ne", [(5, 2), (4, 2), (4, 1)])
+def test_parity_sector_total_spin(norb, ne):
+    """With the determinant order alpha string before beta string, the
+    symmetric sector holds exactly the even total spins S and the
+    antisymmetric one the odd S."""
+    h, g = si.integrals(norb, 2 * norb, 4)
+    S = oracle.Space(norb, ne, ne, h, g)
+    n = int(round(math.sqrt(S.ndet)))
+    S2 = _s2_matrix(S)
+    for parity in (1, -1):
+        Q = oracle.parity_basis(n, parity)
+        w = np.linalg.eigvalsh(Q @ S2 @ Q.T)
+        s = np.round((-1 + np.sqrt(1 + 4 * w)) / 2).astype(int)
+        assert np.allclose(s * (s + 1), w, atol=1e-9)
+        assert np.all(s % 2 == (0 if parity > 0 else 1)), (parity, sorted(set(s)))
+
+
+@pytest.mark.parametrize("t,U", [(1.0, 3.0), (1.3, 5.5)])
+def test_parity_two_site_hubbard(t, U):
+    """Two electrons on two sites: the three singlets (U -+ r)/2 and U are the
+    symmetric sector, the M_S = 0 triplet (energy 0) the antisymmetric one."""
+    h = np.array([[0.0, -t], [-t, 0.0]])
+    g = np.zeros((2, 2, 2, 2))
+    g[0, 0, 0, 0] = g[1, 1, 1, 1] = U
+    S = oracle.Space(2, 1, 1, h, g)
+    r = math.sqrt(U * U + 16 * t * t)
+    assert np.allclose(oracle.parity_spectrum(S, 1), sorted([(U - r) / 2, U, (U + r) / 2]), atol=1e-12)
+    assert np.allclose(oracle.parity_spectrum(S, -1), [0.0], atol=1e-12)
