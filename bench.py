@@ -11,10 +11,12 @@ Prints one JSON line with
   * cpu_baseline: the CPU oracle (plain Slater-Condon sigma) on a bounded
     random sample of output determinants of the same workload, scaled to
     sigma builds/s;
-  * extra: the FP64 sigma rate, per-pass times and the time to converge the
-    Davidson energies (3 roots) in FP64 and in mixed precision (FP32 sigma and
-    basis, FP64 projected problem and final refinement), with the largest
-    energy difference between the two.
+  * extra: the FP64 sigma rate, per-pass times, the FP32 sigma rate inside
+    the even M_S = 0 sector (Sec. 3.3: no beta-beta pass), and the time to
+    converge the Davidson energies (3 roots) in FP64 and in mixed precision
+    (FP32 sigma and basis, FP64 projected problem and final refinement), with
+    the largest energy difference between the two, plus mixed precision in the
+    even sector.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16]
 """
@@ -35,13 +37,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0):
+def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0, parity=0):
     tdt = torch.float32 if dtype == "fp32" else torch.float64
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1000 + seed)
     C = torch.randn(ctx.ndet, dtype=tdt, device="cuda", generator=gen)
+    if parity:
+        # a vector of the M_S = 0 sector: C(Ib, Ia) = parity * C(Ia, Ib)
+        n = int(round(ctx.ndet ** 0.5))
+        M = C.view(n, n)
+        C = (0.5 * (M + parity * M.t())).reshape(-1).contiguous()
     C /= torch.linalg.vector_norm(C)
     S = torch.empty_like(C)
+    ctx.set_option(cis.OPT_SPIN_PARITY, parity)
     for _ in range(warmup):
         ctx.apply(C, S)
     torch.cuda.synchronize()
@@ -54,6 +62,7 @@ def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0):
     dt = time.perf_counter() - t0
     passes, ncalls = ctx.pass_times()
     ctx.set_option(cis.OPT_PROFILE, 0)
+    ctx.set_option(cis.OPT_SPIN_PARITY, 0)
     assert ncalls == steps
     per_pass = {k: v / ncalls for k, v in passes.items()}
     return dt, per_pass, C
@@ -117,14 +126,20 @@ def stored_traffic(kernel_tag):
         return None
 
 
-def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose):
+def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector):
     out = {}
     ctx.set_option(cis.OPT_MAX_ITER, max_iter)
     ctx.set_option(cis.OPT_VERBOSE, 1 if verbose else 0)
-    for mode, prec in (("fp64", cis.FP64), ("mixed_fp32", cis.FP32)):
+    runs = [("fp64", cis.FP64, 0), ("mixed_fp32", cis.FP32, 0)]
+    if sector:
+        # lowest roots of the even-spin M_S = 0 sector (singlets first)
+        runs.append(("mixed_fp32_even_sector", cis.FP32, 1))
+    for mode, prec, parity in runs:
         ctx.set_option(cis.OPT_PRECISION, prec)
+        ctx.set_option(cis.OPT_SPIN_PARITY, parity)
         t0 = time.perf_counter()
         e, st, status = ctx.davidson(nroots, tol, allow_noconv=True)
+        ctx.set_option(cis.OPT_SPIN_PARITY, 0)
         out[mode] = {"seconds": time.perf_counter() - t0, "energies": [float(x) for x in e], "status": status,
                      "iterations": st["iterations"], "sigma_fp32": st["sigma_fp32"], "sigma_fp64": st["sigma_fp64"],
                      "refinements": st["refinements"], "residual": st["residual"]}
@@ -132,6 +147,8 @@ def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose):
     ctx.set_option(cis.OPT_PRECISION, cis.FP64)
     d = [abs(a - b) for a, b in zip(out["fp64"]["energies"], out["mixed_fp32"]["energies"])]
     out["max_abs_energy_diff_mixed_vs_fp64"] = max(d)
+    if sector:
+        out["even_sector_E0_minus_full_E0"] = out["mixed_fp32_even_sector"]["energies"][0] - out["fp64"]["energies"][0]
     return out
 
 
@@ -175,6 +192,13 @@ def main():
     extra = {"init_seconds": init_s, "fp32_pass_ms": pp32,
              "fp32_path": {"ab_owner_computes": bool(path32 & cis.PATH_AB_OWNER),
                            "same_spin_materialised": bool(path32 & cis.PATH_SS_MATERIALISED)}}
+    # M_S = 0 sector (n_alpha = n_beta, one block): the beta-beta pass is replaced by a transpose
+    sector = na == nb and spec["gas"] is None
+    if sector:
+        dtp, ppp, _ = time_sigma(ctx, cis, torch, "fp32", args.steps, 1, parity=1)
+        extra.update({"fp32_even_sector_sigma_per_s": args.steps / dtp,
+                      "fp32_even_sector_ms_per_step": 1e3 * dtp / args.steps, "fp32_even_sector_pass_ms": ppp})
+        log(f"fp32 sigma, even M_S=0 sector: {1e3 * dtp / args.steps:.2f} ms/step, passes {ppp}")
     if not args.no_fp64:
         dt64, pp64, _ = time_sigma(ctx, cis, torch, "fp64", max(2, args.steps // 2), 1)
         ms64 = 1e3 * dt64 / max(2, args.steps // 2)
@@ -204,7 +228,7 @@ def main():
         copy_calibration(torch, args.copy_calibration_mib)
 
     if not args.no_davidson:
-        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose)
+        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose, sector)
 
     cpu = None
     if not args.no_cpu:

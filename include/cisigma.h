@@ -77,6 +77,12 @@ extern "C" {
 #define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels */
 #define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products: at most this many columns per chunk
                                       (a positive multiple of 64); 0 (default): as many as fit in memory */
+#define CISIGMA_OPT_SPIN_PARITY 10 /* M_S = 0 spin symmetry (Sec. 3.1, Sec. 3.3): p = +1 or -1 restricts
+                                      cisigma_apply and cisigma_davidson to vectors with
+                                      C(Ib, Ia) = p C(Ia, Ib) (p = +1: even total spin S, singlets first;
+                                      p = -1: odd S), which drops the beta-beta pass; 0 (default): none.
+                                      Needs nalpha = nbeta (EINVAL otherwise) and a one-block (CAS)
+                                      space (EUNSUPPORTED for GAS spaces) */
 
 /* passes of one cisigma_apply, in order, as reported by cisigma_pass_times */
 #define CISIGMA_PASS_LAYOUT_IN 0   /* C -> padded alpha-major and beta-major copies */
@@ -178,6 +184,10 @@ int cisigma_set_option(cisigma_ctx *ctx, int key, double value);
  *              before the result is ready; synchronise the stream to read it.
  * FP32 computes in FP32 (MFMA with FP32 accumulation); FP64 in FP64.
  * The first call for a dtype allocates that dtype's workspace (synchronous).
+ * With CISIGMA_OPT_SPIN_PARITY p != 0 the caller guarantees
+ * C(Ib, Ia) = p C(Ia, Ib); the beta-beta part is then taken as p times the
+ * transpose of the alpha-alpha part (exact for such C; for any
+ * other C the result is sigma_aa(C) + sigma_ab(C) + sigma_bb(p C^T)).
  */
 int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream);
 
@@ -203,6 +213,11 @@ int cisigma_hdiag(cisigma_ctx *ctx, double *hdiag, void *stream);
  * (and every REFINE_EVERY iterations if that option is nonzero) the Ritz
  * vectors get an FP64 sigma, convergence is judged on their FP64 residuals,
  * and the returned energies are FP64 Rayleigh quotients <x|H x>/<x|x>.
+ * With CISIGMA_OPT_SPIN_PARITY p != 0 the roots are the lowest of the sector
+ * C(Ib, Ia) = p C(Ia, Ib): guesses are the combinations
+ * (|Ia Ib> + p |Ib Ia>)/sqrt(2) (or |Ia Ia> for p = +1) of the lowest
+ * diagonal elements, and every correction vector is projected onto the
+ * sector.
  */
 int cisigma_davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs,
                      cisigma_stats *stats);

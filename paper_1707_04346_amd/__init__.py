@@ -19,6 +19,7 @@ OPT_PRECISION, OPT_MAX_SPACE, OPT_MAX_ITER, OPT_REFINE_EVERY, OPT_RESID_TOL, OPT
 PASSES = ["layout_in", "clear", "sigma_aa", "sigma_ab", "sigma_bb", "layout_out"]
 OPT_SIGMA_PATH = 8
 OPT_SS_CHUNK = 9
+OPT_SPIN_PARITY = 10
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")

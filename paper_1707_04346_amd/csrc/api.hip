@@ -670,23 +670,37 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     }
     auto mark = [&](int pass) -> hipError_t { return prof ? hipEventRecord(ev[pass + 1], s) : hipSuccess; };
     c->last_path[dtype == CISIGMA_FP32] = mat ? CISIGMA_PATH_SS_MATERIALISED : 0;
-    HIP_OR_FAIL(c, launch_scatter_in(c, C, W.cp, W.ct, dtype, s), "apply: layout conversion");
+    // M_S = 0 sector (Sec. 3.3): for C(Ib, Ia) = p C(Ia, Ib) the beta-beta part
+    // is p times the transposed alpha-alpha part.  The alpha-alpha part then goes
+    // to the second accumulator (same shape when nalpha = nbeta), the alpha-beta
+    // part alone to the first, and the output gather forms sp + st + p st^T.
+    const int par = c->spin_parity;
+    HIP_OR_FAIL(c, launch_scatter_in(c, C, W.cp, par ? nullptr : W.ct, dtype, s), "apply: layout conversion");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_LAYOUT_IN), "apply: profiling events");
-    for (int spin = 0; spin < 2; ++spin) {
-        if (mat && c->sp[spin].nel >= 2) continue;   // overwritten by the gather
-        HIP_OR_FAIL(c, launch_fill(spin == 0 ? W.sp : W.st, c->pl[spin].size, dtype, s), "apply: fill");
+    if (par) {
+        HIP_OR_FAIL(c, launch_fill(W.sp, c->pl[0].size, dtype, s), "apply: fill");
+        if (!(mat && c->sp[0].nel >= 2)) HIP_OR_FAIL(c, launch_fill(W.st, c->pl[0].size, dtype, s), "apply: fill");
+    } else {
+        for (int spin = 0; spin < 2; ++spin) {
+            if (mat && c->sp[spin].nel >= 2) continue;   // overwritten by the gather
+            HIP_OR_FAIL(c, launch_fill(spin == 0 ? W.sp : W.st, c->pl[spin].size, dtype, s), "apply: fill");
+        }
     }
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_CLEAR), "apply: profiling events");
     const int chunk = c->ss_chunk > 0 ? std::min(c->ss_chunk, W.ys_chunk) : W.ys_chunk;
-    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, W.sp, dtype, s, mat ? W.ys : nullptr, chunk),
+    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, par ? W.st : W.sp, dtype, s, mat ? W.ys : nullptr, chunk),
                 "apply: sigma_2 (alpha-alpha)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AA), "apply: profiling events");
     HIP_OR_FAIL(c, launch_sigma_ab(c, W.cp, W.sp, dtype, s), "apply: sigma_3 (alpha-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AB), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s, mat ? W.ys : nullptr, chunk),
-                "apply: sigma_1 (beta-beta)");
+    if (!par)
+        HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s, mat ? W.ys : nullptr, chunk),
+                    "apply: sigma_1 (beta-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_BB), "apply: profiling events");
-    HIP_OR_FAIL(c, launch_gather_out(c, W.sp, W.st, sigma, dtype, s), "apply: layout conversion");
+    if (par)
+        HIP_OR_FAIL(c, launch_gather_parity(c, W.sp, W.st, sigma, par, dtype, s), "apply: layout conversion");
+    else
+        HIP_OR_FAIL(c, launch_gather_out(c, W.sp, W.st, sigma, dtype, s), "apply: layout conversion");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_LAYOUT_OUT), "apply: profiling events");
     if (prof) {
         for (auto e : ev) c->prof_events.push_back(e);
@@ -1007,6 +1021,15 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_SPIN_PARITY:
+            if (value != 0 && value != 1 && value != -1)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: spin parity must be -1, 0 or +1");
+            if (value != 0 && ctx->sp[0].nel != ctx->sp[1].nel)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: spin parity needs nalpha = nbeta");
+            if (value != 0 && !ctx->cas)
+                return cis_set_error(ctx, CISIGMA_EUNSUPPORTED, "set_option: spin parity is built for one-block spaces");
+            ctx->spin_parity = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_PROFILE:
             prof_reset(ctx);

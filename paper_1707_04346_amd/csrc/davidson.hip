@@ -173,15 +173,28 @@ __global__ void k_unit(T *x, int64_t N, int64_t idx) {
     for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) x[n] = T(n == idx ? 1 : 0);
 }
 
-// lexicographic (value, index) minimum strictly above (pv, pi)
+template <typename T>
+__global__ void k_unit2(T *x, int64_t N, int64_t i1, int64_t i2, T v) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride)
+        x[n] = n == i1 ? v : (n == i2 ? T(1) / T(1.4142135623730951) : T(0));
+}
+
+// lexicographic (value, index) minimum strictly above (pv, pi); with parity
+// p != 0 over the sector representatives (Ia, Ib), Ia <= Ib (Ia < Ib for p = -1)
+// of the one-block vector of side nside
 __global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, double pv, int64_t pi, double *ov,
-                                                int64_t *oi) {
+                                                int64_t *oi, int64_t nside, int parity) {
     __shared__ double sv[256];
     __shared__ int64_t si[256];
     double bv = INFINITY;
     int64_t bi = -1;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        if (parity != 0) {
+            const int64_t ra = n / nside, cb = n % nside;
+            if (ra > cb || (parity < 0 && ra == cb)) continue;
+        }
         double v = hd[n];
         bool above = (v > pv) || (v == pv && n > pi);
         if (!above) continue;
@@ -307,7 +320,13 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         }
     }
     max_space = std::max(max_space, 2 * nroots);
-    if (int64_t(max_space) > N) max_space = int(N);
+    // M_S = 0 sector (Sec. 3.1, Sec. 3.3): vectors with C(Ib, Ia) = par C(Ia, Ib)
+    const int par = ctx->spin_parity;
+    const int64_t nside = par ? int64_t(ctx->sp[0].nstr) : 0;
+    const int64_t dim = par ? (par > 0 ? nside * (nside + 1) / 2 : nside * (nside - 1) / 2) : N;
+    if (nroots > dim)
+        return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: nroots exceeds the dimension of the spin-parity sector");
+    if (int64_t(max_space) > dim) max_space = int(dim);
     if (max_space > 512) max_space = 512;
     double rtol = ctx->resid_tol > 0 ? ctx->resid_tol : std::sqrt(tol);
     if (mixed && ctx->resid_tol <= 0) rtol = std::max(rtol, 1e-5);
@@ -349,7 +368,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         std::vector<double> hv(g);
         std::vector<int64_t> hi(g);
         for (int r = 0; r < nroots; ++r) {
-            hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx);
+            hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx, nside, par);
             DV_TRY(hipMemcpyAsync(hv.data(), d.dvec, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
             DV_TRY(hipMemcpyAsync(hi.data(), d.pidx, g * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
             DV_TRY(hipStreamSynchronize(d.s));
@@ -357,7 +376,13 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             int64_t bi = -1;
             for (int b = 0; b < g; ++b)
                 if (hi[b] >= 0 && (bi < 0 || hv[b] < bv || (hv[b] == bv && hi[b] < bi))) { bv = hv[b]; bi = hi[b]; }
-            hipLaunchKernelGGL(k_unit<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, bi);
+            if (bi < 0) return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: fewer determinants than roots");
+            const int64_t ra = par ? bi / nside : 0, cb = par ? bi % nside : 0;
+            if (par == 0 || ra == cb)
+                hipLaunchKernelGGL(k_unit<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, bi);
+            else   // (|Ia Ib> + p |Ib Ia>) / sqrt(2)
+                hipLaunchKernelGGL(k_unit2<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, cb * nside + ra, bi,
+                                   T(par) / T(1.4142135623730951));
             pv = bv;
             pi = bi;
         }
@@ -367,7 +392,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     std::vector<double> erq(nroots, 0.0), r64(nroots, INFINITY);
     std::vector<double> w, Y, col(max_space + 8);
     int m = 0, nnew = nroots, iter = 0, nsig32 = 0, nsig64 = 0, nref = 0;
-    bool converged = false, have_rq = false;
+    bool converged = false, have_rq = false, stalled = false;
     int since_ref = 0;
     int rc = CISIGMA_OK;
     auto sigma_of = [&](const void *x, void *y, int dtype) -> int {
@@ -515,6 +540,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             if (any_open && !refined_now && rnorm[r] <= rtol) continue;
             T *t = B + int64_t(m + nnew) * N;
             DV_TRY(hipMemcpyAsync(t, TB + int64_t(r) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+            if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
             for (int pass = 0; pass < 2; ++pass) {
                 DV_TRY(dots(d, B, N, m + nnew, t, N, col.data()));
                 DV_TRY(hipMemcpyAsync(d.dvec, col.data(), (m + nnew) * sizeof(double), hipMemcpyHostToDevice, d.s));
@@ -528,7 +554,17 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             ++nnew;
             if (m + nnew >= max_space) break;
         }
-        if (nnew == 0) break;
+        if (nnew == 0) {
+            // every correction vanished: the residuals lie in the basis (a basis
+            // spanning the whole space or sector, or roots already at their
+            // residual threshold); one more pass settles the convergence test
+            bool small = true;
+            for (int r = 0; r < nroots; ++r) small = small && rnorm[r] <= rtol;
+            if (stalled || !(small || m >= dim)) break;
+            stalled = true;
+        } else {
+            stalled = false;
+        }
     }
     DV_TRY(hipStreamSynchronize(d.s));
     for (int r = 0; r < nroots; ++r) energies[r] = (mixed && have_rq) ? erq[r] : theta[r];

@@ -200,6 +200,7 @@ struct cisigma_ctx {
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
     int ab_mode = 0;
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)
+    int spin_parity = 0;   // M_S = 0 sector: C(Ib, Ia) = p C(Ia, Ib) assumed (0: none)
     // per-pass event timing of apply (CISIGMA_OPT_PROFILE)
     bool profile = false;
     std::vector<hipEvent_t> prof_events;   // pending pairs, (CISIGMA_NPASS + 1) events per call
@@ -243,6 +244,11 @@ hipError_t launch_scatter_in(const cisigma_ctx *ctx, const void *C, void *cp, vo
 hipError_t launch_gather_out(const cisigma_ctx *ctx, const void *sp, const void *st, void *sigma, int dtype,
                              hipStream_t s);
 hipError_t launch_hdiag(const cisigma_ctx *ctx, double *out, hipStream_t s);
+// sigma = sp + st + p st^T on the one-block layout (st: the alpha-alpha part, alpha-major)
+hipError_t launch_gather_parity(const cisigma_ctx *ctx, const void *sp, const void *st, void *sigma, int parity,
+                                int dtype, hipStream_t s);
+// x <- (x + p x^T) / 2 for the caller's one-block vector x[n][n]
+hipError_t launch_symmetrize(void *x, int n, int parity, int dtype, hipStream_t s);
 inline BlockTilesDev block_tiles(const cisigma_ctx *ctx) { return ctx->bt; }
 
 // Davidson driver (davidson.hip)

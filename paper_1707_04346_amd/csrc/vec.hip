@@ -40,11 +40,72 @@ __global__ __launch_bounds__(256) void k_scatter_in(const T *__restrict__ C, T *
         }
         tile[4 * i + ty][tx] = v;
     }
+    if (ct == nullptr) return;                 // the beta-major copy is not wanted (uniform)
     __syncthreads();
 #pragma unroll 4
     for (int i = 0; i < 16; ++i) {
         int rb = c0 + 4 * i + ty, ca = r0 + tx;   // beta row, alpha column
         if (rb < B.nb && ca < B.na) ct[B.segb + int64_t(rb) * B.ldb + ca] = tile[tx][4 * i + ty];
+    }
+}
+
+// M_S = 0 sector (one block, nalpha = nbeta, so both spins share the alpha
+// layout): sigma = sp + st + p st^T, with st the alpha-alpha part and sp the
+// alpha-beta part (Sec. 3.3: the beta-beta part of such a vector is the
+// transposed alpha-alpha part).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_parity(const T *__restrict__ sp, const T *__restrict__ st,
+                                                      T *__restrict__ sig, const BlockDev *__restrict__ blk,
+                                                      const int *__restrict__ tr, const int *__restrict__ tc,
+                                                      T p) {
+    __shared__ T tile[64][65];
+    const int t = blockIdx.x;
+    const BlockDev B = blk[0];
+    const int r0 = tr[t], c0 = tc[t];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int rr = c0 + 4 * i + ty, cc = r0 + tx;   // element (c, r) of the output tile
+        T v = 0;
+        if (rr < B.na && cc < B.nb) v = st[B.sega + int64_t(rr) * B.lda + cc];
+        tile[tx][4 * i + ty] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int r = r0 + 4 * i + ty, c = c0 + tx;
+        if (r < B.na && c < B.nb) {
+            const int64_t a = B.sega + int64_t(r) * B.lda + c;
+            sig[B.off + int64_t(r) * B.nb + c] = sp[a] + st[a] + p * tile[4 * i + ty][tx];
+        }
+    }
+}
+
+// x <- (x + p x^T) / 2 on x[n][n] row-major, in place: block (bi, bj) with
+// bi <= bj owns the 32x32 tile pair (bi, bj) / (bj, bi); blocks below the
+// diagonal return at once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_symmetrize(T *x, int n, int nt, T p) {
+    __shared__ T a[32][33], b[32][33];
+    const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
+    if (bi > bj) return;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 8 rows per pass
+    const int r0 = bi * 32, c0 = bj * 32;
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        a[i][tx] = (r < n && c < n) ? x[int64_t(r) * n + c] : T(0);
+        const int r2 = c0 + i, c2 = r0 + tx;
+        b[i][tx] = (r2 < n && c2 < n) ? x[int64_t(r2) * n + c2] : T(0);
+    }
+    __syncthreads();
+    // a[i][j] = x(r0+i, c0+j), b[j][i] = x(c0+j, r0+i)
+    for (int i = ty; i < 32; i += 8) {
+        const int r = r0 + i, c = c0 + tx;
+        const T v = T(0.5) * (a[i][tx] + p * b[tx][i]);
+        if (r < n && c < n) x[int64_t(r) * n + c] = v;
+        // the mirrored element x(c0+i, r0+tx) = p * new x(r0+tx, c0+i)
+        const int r2 = c0 + i, c2 = r0 + tx;
+        if (r2 < n && c2 < n && bi != bj) x[int64_t(r2) * n + c2] = p * T(0.5) * (a[tx][i] + p * b[i][tx]);
     }
 }
 
@@ -133,6 +194,35 @@ hipError_t launch_gather_out(const cisigma_ctx *ctx, const void *sp, const void 
         hipLaunchKernelGGL(k_gather_out<double>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const double *>(sp),
                            static_cast<const double *>(st), static_cast<double *>(sigma), bt.blk, bt.tb, bt.tr,
                            bt.tc);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_parity(const cisigma_ctx *ctx, const void *sp, const void *st, void *sigma, int parity,
+                                int dtype, hipStream_t s) {
+    BlockTilesDev bt = block_tiles(ctx);
+    if (bt.ntiles == 0) return hipSuccess;
+    if (dtype == CISIGMA_FP32)
+        hipLaunchKernelGGL(k_gather_parity<float>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const float *>(sp),
+                           static_cast<const float *>(st), static_cast<float *>(sigma), bt.blk, bt.tr, bt.tc,
+                           float(parity));
+    else
+        hipLaunchKernelGGL(k_gather_parity<double>, dim3(bt.ntiles), dim3(256), 0, s,
+                           static_cast<const double *>(sp), static_cast<const double *>(st),
+                           static_cast<double *>(sigma), bt.blk, bt.tr, bt.tc, double(parity));
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(void *x, int n, int parity, int dtype, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nt = (n + 31) / 32;
+    const int64_t blocks = int64_t(nt) * nt;
+    if (blocks > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
+    if (dtype == CISIGMA_FP32)
+        hipLaunchKernelGGL(k_symmetrize<float>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<float *>(x), n, nt,
+                           float(parity));
+    else
+        hipLaunchKernelGGL(k_symmetrize<double>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<double *>(x), n,
+                           nt, double(parity));
     return hipGetLastError();
 }
 
