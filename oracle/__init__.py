@@ -13,6 +13,8 @@ library never loads it and shares no code with it.
   sigma and re-diagonalisation of the projected matrix), with numpy's ``eigh``
   for the small projected problem.
 
+* ``Space.rdm``: one- and two-particle density matrices by applying every
+  creation/annihilation operator to every determinant (the plain definition).
 * ``parity_basis`` / ``parity_spectrum``: the M_S = 0 sectors of Sec. 3.1 and
   Sec. 3.3 (vectors symmetric or antisymmetric under alpha <-> beta string
   exchange) and the dense spectrum of H inside them.
@@ -22,7 +24,8 @@ second-quantised construction of Eq. 6, the two-site Hubbard closed form, the
 non-interacting closed form, spin and transposition symmetry, GAS = projected
 CAS, and dense ``eigh``; the sectors against the full spectrum, total spin
 (even S in the symmetric sector, odd S in the antisymmetric one) and the
-Hubbard closed form.
+Hubbard closed form; the density matrices against the energy from sigma, traces,
+index symmetries and the single-determinant closed form.
 """
 import ctypes
 import os
@@ -78,6 +81,8 @@ def _load():
     lib.or_hmat.restype = i32
     lib.or_hmat.argtypes = [vp, vp]
     lib.or_set_threads.argtypes = [i32]
+    lib.or_rdm.restype = i32
+    lib.or_rdm.argtypes = [vp, vp, vp, vp]
     lib.or_max_threads.restype = i32
     _lib = lib
     return lib
@@ -178,6 +183,22 @@ class Space:
         out = np.empty(rows.size, dtype=np.float64)
         _load().or_sigma_rows(self._h, rows.size, _ptr(rows), _ptr(C), _ptr(out))
         return out
+
+    def rdm(self, C):
+        """Spin-summed one- and two-particle density matrices of C, normalised
+        by <C|C>: gamma[p,q] = sum_s <a+_ps a_qs>, Gamma[p,q,r,s] =
+        sum_(s,t) <a+_ps a+_rt a_st a_qs> (chemists' order: the energy is
+        sum h gamma + 1/2 sum (pq|rs) Gamma).  Every operator is applied to
+        every determinant of the space (plain definition; small spaces)."""
+        C = np.ascontiguousarray(C, dtype=np.float64).reshape(-1)
+        assert C.size == self.ndet
+        n = self.norb
+        g1 = np.empty((n, n), dtype=np.float64)
+        g2 = np.empty((n, n, n, n), dtype=np.float64)
+        rc = _load().or_rdm(self._h, _ptr(C), _ptr(g1), _ptr(g2))
+        if rc != 0:
+            raise ValueError("oracle: zero vector")
+        return g1, g2
 
     def hdiag(self):
         out = np.empty(self.ndet, dtype=np.float64)

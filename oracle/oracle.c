@@ -25,6 +25,12 @@
  *     operators of Eq. 7, real orbitals, chemists' notation (ij|kl).
  *     No blocking, no splitting into sigma_1/2/3, no reuse between elements.
  *
+ *   * One- and two-particle density matrices of a vector (the densities that
+ *     Sec. 2.2 and Sec. 3.4 feed to the orbital step): the definitions
+ *       gamma_pq   = sum_s <C|a+_ps a_qs|C> / <C|C>,
+ *       Gamma_pqrs = sum_st <C|a+_ps a+_rt a_st a_qs|C> / <C|C>,
+ *     applied operator by operator to every determinant (below).
+ *
  * Sign convention: a determinant is alpha-hat(I_alpha) beta-hat(I_beta)|vac>
  * where each string operator is the product of creation operators in
  * ascending orbital order (Eq. 2).  The sign of a^+_p a_q acting on a string
@@ -496,5 +502,107 @@ int or_hmat(const or_space *S, double *out) {
             out[i * N + j] = h_elem(S, ia, ib, ja, jb);
         }
     }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Density matrices by direct operator application.
+ *
+ * A determinant is held as one 64-bit word of spin orbitals: alpha orbital p
+ * is bit p, beta orbital p is bit norb + p, so that the ascending creation
+ * order of Eq. 2 (alpha string left of beta string) is ascending bit order.
+ * a_k and a+_k act with the sign (-1)^(occupied spin orbitals below k).
+ * ------------------------------------------------------------------------- */
+
+/* a_k on d: 0 when k is empty, else the new word and the sign */
+static int op_ann(uint64_t d, int k, uint64_t *out, int *sign) {
+    uint64_t b = (uint64_t)1 << k;
+    if (!(d & b)) return 0;
+    *sign *= (__builtin_popcountll(d & (b - 1)) & 1) ? -1 : 1;
+    *out = d & ~b;
+    return 1;
+}
+
+/* a+_k on d: 0 when k is occupied */
+static int op_cre(uint64_t d, int k, uint64_t *out, int *sign) {
+    uint64_t b = (uint64_t)1 << k;
+    if (d & b) return 0;
+    *sign *= (__builtin_popcountll(d & (b - 1)) & 1) ? -1 : 1;
+    *out = d | b;
+    return 1;
+}
+
+static int64_t index_of_word(const or_space *S, uint64_t d) {
+    uint32_t ia = (uint32_t)(d & ((S->norb >= 32) ? 0xffffffffu : ((1u << S->norb) - 1u)));
+    uint32_t ib = (uint32_t)(d >> S->norb);
+    if (popc(ia) != S->nel[0] || popc(ib) != S->nel[1]) return -1;
+    return or_address(S, ia, ib);
+}
+
+/* rdm1[n*n], rdm2[n^4] (index ((p*n+q)*n+r)*n+s), both normalised by <C|C>;
+ * returns 0, or -1 for a zero vector */
+int or_rdm(const or_space *S, const double *C, double *rdm1, double *rdm2) {
+    const int n = S->norb, n2 = 2 * n;
+    const int64_t N = S->ndet;
+    const size_t n4 = (size_t)n * n * n * n;
+    double cc = 0;
+    for (int64_t j = 0; j < N; ++j) cc += C[j] * C[j];
+    if (!(cc > 0)) return -1;
+    memset(rdm1, 0, sizeof(double) * n * n);
+    memset(rdm2, 0, sizeof(double) * n4);
+    #pragma omp parallel
+    {
+        double *g1 = calloc((size_t)n * n, sizeof(double));
+        double *g2 = calloc(n4, sizeof(double));
+        #pragma omp for schedule(dynamic, 16)
+        for (int64_t j = 0; j < N; ++j) {
+            if (C[j] == 0) continue;
+            uint32_t ja, jb;
+            det_of(S, j, &ja, &jb);
+            const uint64_t d0 = (uint64_t)ja | ((uint64_t)jb << n);
+            /* one-body: a+_P a_Q with P, Q spin orbitals of one spin */
+            for (int Q = 0; Q < n2; ++Q) {
+                uint64_t d1; int s1 = 1;
+                if (!op_ann(d0, Q, &d1, &s1)) continue;
+                const int sp = Q / n, q = Q % n;
+                for (int p = 0; p < n; ++p) {
+                    uint64_t d2; int s2 = s1;
+                    if (!op_cre(d1, sp * n + p, &d2, &s2)) continue;
+                    int64_t i = index_of_word(S, d2);
+                    if (i >= 0) g1[(size_t)p * n + q] += C[i] * s2 * C[j];
+                }
+            }
+            /* two-body: a+_P a+_R a_T a_Q, P and Q of spin s, R and T of spin t */
+            for (int Q = 0; Q < n2; ++Q) {
+                uint64_t d1; int s1 = 1;
+                if (!op_ann(d0, Q, &d1, &s1)) continue;
+                const int sq = Q / n, q = Q % n;
+                for (int T = 0; T < n2; ++T) {
+                    uint64_t d2; int s2 = s1;
+                    if (!op_ann(d1, T, &d2, &s2)) continue;
+                    const int st = T / n, t = T % n;
+                    for (int r = 0; r < n; ++r) {
+                        uint64_t d3; int s3 = s2;
+                        if (!op_cre(d2, st * n + r, &d3, &s3)) continue;
+                        for (int p = 0; p < n; ++p) {
+                            uint64_t d4; int s4 = s3;
+                            if (!op_cre(d3, sq * n + p, &d4, &s4)) continue;
+                            int64_t i = index_of_word(S, d4);
+                            if (i >= 0) g2[(((size_t)p * n + q) * n + r) * n + t] += C[i] * s4 * C[j];
+                        }
+                    }
+                }
+            }
+        }
+        #pragma omp critical
+        {
+            for (size_t k = 0; k < (size_t)n * n; ++k) rdm1[k] += g1[k];
+            for (size_t k = 0; k < n4; ++k) rdm2[k] += g2[k];
+        }
+        free(g1);
+        free(g2);
+    }
+    for (size_t k = 0; k < (size_t)n * n; ++k) rdm1[k] /= cc;
+    for (size_t k = 0; k < n4; ++k) rdm2[k] /= cc;
     return 0;
 }

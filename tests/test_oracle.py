@@ -443,3 +443,53 @@ def test_parity_two_site_hubbard(t, U):
     r = math.sqrt(U * U + 16 * t * t)
     assert np.allclose(oracle.parity_spectrum(S, 1), sorted([(U - r) / 2, U, (U + r) / 2]), atol=1e-12)
     assert np.allclose(oracle.parity_spectrum(S, -1), [0.0], atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# density matrices (plain operator application)
+# ---------------------------------------------------------------------------
+RDM_CASES = [(5, 2, 2, None), (6, 3, 2, None), (5, 1, 3, None), (7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6]))]
+
+
+@pytest.mark.parametrize("case", RDM_CASES, ids=[f"n{c[0]}a{c[1]}b{c[2]}" + ("gas" if c[3] else "") for c in RDM_CASES])
+def test_rdm_energy_traces_and_symmetries(case):
+    """sum h gamma + 1/2 sum (pq|rs) Gamma = <C|H|C>/<C|C> with H C from the
+    Slater-Condon sigma (independent code); traces N and N(N-1); partial trace
+    (N-1) gamma; Gamma_pqrs = Gamma_rspq = Gamma_qpsr."""
+    norb, na, nb, gas = case
+    h, g = si.integrals(norb, 2 * norb, 13)
+    S = oracle.Space(norb, na, nb, h, g, gas=gas)
+    C = si.ci_vector(S.ndet, 5)
+    g1, g2 = S.rdm(C)
+    N = na + nb
+    e_rdm = np.einsum("pq,pq", h, g1) + 0.5 * np.einsum("pqrs,pqrs", g, g2)
+    e_sig = C @ S.sigma(C) / (C @ C)
+    assert abs(e_rdm - e_sig) < 1e-12 * max(1.0, abs(e_sig))
+    assert abs(np.trace(g1) - N) < 1e-12
+    assert abs(np.einsum("pprr", g2) - N * (N - 1)) < 1e-11
+    assert np.abs(np.einsum("pqrr->pq", g2) - (N - 1) * g1).max() < 1e-12
+    assert np.abs(g1 - g1.T).max() < 1e-13
+    assert np.abs(g2 - g2.transpose(2, 3, 0, 1)).max() < 1e-13
+    assert np.abs(g2 - g2.transpose(1, 0, 3, 2)).max() < 1e-13
+
+
+def test_rdm_single_determinant_closed_form():
+    """One determinant: gamma = diag(n_a + n_b) and
+    Gamma_pqrs = d_pq d_rs (N_p N_r - d_pr N_p) - d_ps d_qr (sum_s n_ps n_qs - d_pq N_p)."""
+    norb, na, nb = 5, 3, 2
+    h, g = si.integrals(norb, 10, 2)
+    S = oracle.Space(norb, na, nb, h, g)
+    i = 7
+    C = np.zeros(S.ndet)
+    C[i] = -2.0
+    ia, ib = S.det(i)
+    na_ = np.array([(ia >> p) & 1 for p in range(norb)], float)
+    nb_ = np.array([(ib >> p) & 1 for p in range(norb)], float)
+    Np = na_ + nb_
+    d = np.eye(norb)
+    same = np.outer(na_, na_) + np.outer(nb_, nb_)
+    want2 = (np.einsum("pq,rs,p,r->pqrs", d, d, Np, Np) - np.einsum("pq,rs,pr,p->pqrs", d, d, d, Np)
+             - np.einsum("ps,qr,pq->pqrs", d, d, same) + np.einsum("ps,qr,pq,p->pqrs", d, d, d, Np))
+    g1, g2 = S.rdm(C)
+    assert np.abs(g1 - np.diag(Np)).max() < 1e-14
+    assert np.abs(g2 - want2).max() < 1e-14
