@@ -223,6 +223,25 @@ int cisigma_davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies,
                      cisigma_stats *stats);
 
 /*
+ * cisigma_rdm -- spin-summed one- and two-particle density matrices of C (the
+ * densities of the orbital step, Sec. 2.2 and Sec. 3.4), normalised by <C|C>:
+ *     rdm1[p*n + q]               = sum_s <C|a+_ps a_qs|C> / <C|C>
+ *     rdm2[((p*n + q)*n + r)*n + s] = sum_(s,t) <C|a+_ps a+_rt a_st a_qs|C> / <C|C>
+ * (chemists' order: the energy is sum h_pq rdm1_pq + 1/2 sum (pq|rs) rdm2_pqrs).
+ *   C          device vector of ndet elements of dtype (CISIGMA_FP64 or
+ *              CISIGMA_FP32; FP32 multiplies in FP32 and sums the per-workgroup
+ *              partials in FP64), caller-owned, in the vector order above.
+ *   rdm1, rdm2 caller-owned device FP64 arrays of n^2 and n^4 elements,
+ *              overwritten.  A zero vector gives NaN.
+ *   stream     hipStream_t or NULL; asynchronous like cisigma_apply.
+ * Built for one-block (CAS) spaces with norb <= 16 whose alpha-major row fits
+ * the 160 KB LDS with the product tile (EUNSUPPORTED otherwise).  The first
+ * call allocates a partial-sum buffer (~80 MB at norb = 16) and the dtype's
+ * sigma workspace.
+ */
+int cisigma_rdm(cisigma_ctx *ctx, const void *C, int dtype, double *rdm1, double *rdm2, void *stream);
+
+/*
  * cisigma_pass_times -- with CISIGMA_OPT_PROFILE set, every cisigma_apply
  * records a HIP event pair around each pass on the stream it runs on.  This
  * call synchronises those events and writes the summed milliseconds of each

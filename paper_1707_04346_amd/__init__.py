@@ -69,6 +69,8 @@ _lib.cisigma_hdiag.restype = _i32
 _lib.cisigma_hdiag.argtypes = [_vp, _vp, _vp]
 _lib.cisigma_davidson.restype = _i32
 _lib.cisigma_davidson.argtypes = [_vp, _i32, _f64, _vp, _vp, ctypes.POINTER(Stats)]
+_lib.cisigma_rdm.restype = _i32
+_lib.cisigma_rdm.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
 _lib.cisigma_last_path.restype = _i32
 _lib.cisigma_last_path.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
 _lib.cisigma_pass_times.restype = _i32
@@ -80,7 +82,7 @@ _lib.cisigma_strerror.argtypes = [_i32]
 
 EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "cisigma_address", "cisigma_strings",
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
-           "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror"]
+           "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -211,6 +213,19 @@ class Context:
         if status != OK and not (allow_noconv and status == ENOCONV):
             self._check(status)
         return e, st.as_dict(), status
+
+    def rdm(self, C, rdm1, rdm2, stream=None):
+        """Spin-summed density matrices of C into device FP64 tensors rdm1 (n*n) and
+        rdm2 (n**4), asynchronous on stream."""
+        dt = FP32 if str(C.dtype).endswith("float32") else FP64
+        n = self.norb
+        if C.numel() != self.ndet or not C.is_contiguous():
+            raise CisigmaError(EINVAL, "C must be a contiguous device tensor of ndet elements")
+        if rdm1.numel() != n * n or rdm2.numel() != n ** 4 or not str(rdm1.dtype).endswith("float64") \
+                or not str(rdm2.dtype).endswith("float64") or not (rdm1.is_contiguous() and rdm2.is_contiguous()):
+            raise CisigmaError(EINVAL, "rdm1 and rdm2 must be contiguous float64 device tensors of n^2 and n^4 elements")
+        self._check(_lib.cisigma_rdm(self._h, _ptr(C), dt, _ptr(rdm1), _ptr(rdm2), _stream_ptr(stream)))
+        return rdm1, rdm2
 
     def pass_times(self):
         """Summed milliseconds per apply pass since profiling was enabled, and the call count."""

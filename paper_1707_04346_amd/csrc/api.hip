@@ -100,6 +100,7 @@ void free_ctx(cisigma_ctx *c) {
         auto &W = c->ws[s];
         hipFree(W.cp); hipFree(W.sp); hipFree(W.ct); hipFree(W.st); hipFree(W.ys);
     }
+    hipFree(c->d_rdm);
     hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
     hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
@@ -1048,6 +1049,31 @@ CIS_API int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtyp
     const char *a = static_cast<const char *>(C), *b = static_cast<const char *>(sigma);
     if (a < b + bytes && b < a + bytes) return cis_set_error(ctx, CISIGMA_EINVAL, "apply: C and sigma overlap");
     return cis::apply_sigma(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
+}
+
+CIS_API int cisigma_rdm(cisigma_ctx *ctx, const void *C, int dtype, double *rdm1, double *rdm2, void *stream) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if (!C || !rdm1 || !rdm2) return cis_set_error(ctx, CISIGMA_EINVAL, "rdm: NULL pointer");
+    if (dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64) return cis_set_error(ctx, CISIGMA_EINVAL, "rdm: bad dtype");
+    if (!ctx->cas || ctx->n > 16)
+        return cis_set_error(ctx, CISIGMA_EUNSUPPORTED, "rdm: built for one-block spaces of at most 16 orbitals");
+    if (cis::rdm_lds_bytes(ctx, dtype) > 160 * 1024)
+        return cis_set_error(ctx, CISIGMA_EUNSUPPORTED, "rdm: the alpha-major row does not fit the LDS");
+    int rc = ensure_workspace(ctx, dtype);
+    if (rc) return rc;
+    const size_t need = cis::rdm_part_elems(ctx);
+    if (ctx->rdm_elems < need) {
+        hipFree(ctx->d_rdm);
+        ctx->d_rdm = nullptr;
+        ctx->rdm_elems = 0;
+        HIP_OR_FAIL(ctx, hipMalloc(&ctx->d_rdm, need * sizeof(double)), "rdm: partial-sum buffer");
+        ctx->rdm_elems = need;
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    auto &W = ctx->ws[dtype == CISIGMA_FP32 ? 1 : 0];
+    HIP_OR_FAIL(ctx, cis::launch_scatter_in(ctx, C, W.cp, nullptr, dtype, s), "rdm: layout conversion");
+    HIP_OR_FAIL(ctx, cis::launch_rdm(ctx, W.cp, dtype, ctx->d_rdm, rdm1, rdm2, s), "rdm: density kernels");
+    return CISIGMA_OK;
 }
 
 CIS_API int cisigma_hdiag(cisigma_ctx *ctx, double *hdiag, void *stream) {

@@ -201,6 +201,8 @@ struct cisigma_ctx {
     int ab_mode = 0;
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)
     int spin_parity = 0;   // M_S = 0 sector: C(Ib, Ia) = p C(Ia, Ib) assumed (0: none)
+    double *d_rdm = nullptr;   // density-matrix partial sums (allocated on first use)
+    size_t rdm_elems = 0;
     // per-pass event timing of apply (CISIGMA_OPT_PROFILE)
     bool profile = false;
     std::vector<hipEvent_t> prof_events;   // pending pairs, (CISIGMA_NPASS + 1) events per call
@@ -250,6 +252,13 @@ hipError_t launch_gather_parity(const cisigma_ctx *ctx, const void *sp, const vo
 // x <- (x + p x^T) / 2 for the caller's one-block vector x[n][n]
 hipError_t launch_symmetrize(void *x, int n, int parity, int dtype, hipStream_t s);
 inline BlockTilesDev block_tiles(const cisigma_ctx *ctx) { return ctx->bt; }
+
+// density matrices (rdm.hip): one-block spaces, n <= 16
+int rdm_blocks(int n);
+size_t rdm_lds_bytes(const cisigma_ctx *ctx, int dtype);
+size_t rdm_part_elems(const cisigma_ctx *ctx);
+hipError_t launch_rdm(const cisigma_ctx *ctx, const void *cp, int dtype, double *part, double *rdm1, double *rdm2,
+                      hipStream_t s);
 
 // Davidson driver (davidson.hip)
 int davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats);
