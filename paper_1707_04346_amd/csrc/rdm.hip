@@ -46,7 +46,14 @@ template <typename T, int NT>
 __global__ __launch_bounds__(512, 1) void k_rdm(RdmArgs<T> p) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
-    constexpr int DS = NT + 1;                             // D row stride (elements)
+    // D is stored with the columns of a tile permuted so that the k steps a lane
+    // feeds to the matrix cores are contiguous: column c sits at
+    // (c % 4) * KT + c / 4, and one lane's operand for all KT k steps is KT
+    // consecutive elements (16-byte loads).  Rows are padded by 16 bytes.
+    constexpr int KT = NT / 4;                             // k steps per tile
+    constexpr int VE = 16 / int(sizeof(T));                // elements per 16-byte load
+    constexpr int DS = NT + VE;                            // D row stride (elements)
+    using V = typename M::vec_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *D = reinterpret_cast<T *>(smem_raw);                // [16 nb][DS]
     T *row = D + 16 * p.nb * DS;                           // [ld]: C(K_a, .)
@@ -57,12 +64,18 @@ __global__ __launch_bounds__(512, 1) void k_rdm(RdmArgs<T> p) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int n = p.n, n2 = n * n, MR = 16 * p.nb;
+    constexpr int RG = 512 / NT;                           // threads per tile column
+    constexpr int KA = (64 + RG - 1) / RG;                 // single excitations per string <= 8 * 8 (n <= 16)
+    constexpr int KB = KA;
+    const int c = tid % NT, rg = tid / NT;
+    const int cperm = (c % 4) * KT + c / 4;                // where column c is stored
+    const int lfrag = (lane & 15) * DS + (lane >> 4) * KT; // this lane's operand inside a 16-row block
 
     // this wave's block pairs (bi <= bj), a contiguous run of the row-major
     // enumeration of the upper triangle, and their LDS fragment offsets
     const int per = (p.npb + 7) / 8;
     const int s0 = wave * per;
-    uint32_t off[kRdmSlots];                               // A offset | B offset << 16 (elements)
+    int sbi[kRdmSlots], sbj[kRdmSlots];                    // block rows / columns of the slots
     int nslot = 0;
     {
         int bi = 0, bj = 0, q = 0;
@@ -73,9 +86,8 @@ __global__ __launch_bounds__(512, 1) void k_rdm(RdmArgs<T> p) {
 #pragma unroll
         for (int s = 0; s < kRdmSlots; ++s) {
             const bool ok = s < per && s0 + s < p.npb;
-            const uint32_t oa = uint32_t((16 * bi + (lane & 15)) * DS + (lane >> 4));
-            const uint32_t ob = uint32_t((16 * bj + (lane & 15)) * DS + (lane >> 4));
-            off[s] = ok ? (oa | (ob << 16)) : 0u;
+            sbi[s] = ok ? bi : 0;
+            sbj[s] = ok ? bj : 0;
             nslot += ok ? 1 : 0;
             if (ok && ++bj == p.nb) { ++bi; bj = bi; }
         }
@@ -108,53 +120,111 @@ __global__ __launch_bounds__(512, 1) void k_rdm(RdmArgs<T> p) {
             rowJ[k * n + l] = int(w >> 11);
             rowS[k * n + l] = (w & 1) ? -1 : 1;
         }
+        // this thread's column c of every tile, its alpha entries a = rg + RG i
+        // (source offset, target row, sign) and beta entries e = rg + RG i
+        uint32_t asrc[KA];
+        int adst[KA];
+        T asgn[KA];
+#pragma unroll
+        for (int i = 0; i < KA; ++i) {
+            const int a = rg + RG * i;
+            const uint32_t w = a < p.anexc ? p.aexc[int64_t(Ka) * p.anexc + a] : kExcNone;
+            adst[i] = w == kExcNone ? -1 : int(((w >> 6) & 31) * n + ((w >> 1) & 31));
+            asrc[i] = w == kExcNone ? 0u : (w >> 11) * uint32_t(p.ld) + uint32_t(c);
+            asgn[i] = (w & 1) ? T(-1) : T(1);
+        }
+        // operands of tile c0 in registers, those of the next tile in flight
+        T aval[KA], anext[KA];
+        uint32_t bw[KB], bnext[KB], bs, bsnext;
+        auto fetch = [&](int t0, T (&av)[KA], uint32_t (&bv)[KB], uint32_t &bsv) {
+            const int Kb = t0 + c;
+#pragma unroll
+            for (int i = 0; i < KA; ++i) av[i] = adst[i] >= 0 ? p.cp[asrc[i] + uint32_t(t0)] : T(0);
+            const bool in = Kb < p.Nb;
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+                const int e = rg + RG * i;
+                bv[i] = in && e < p.bnexc ? p.bexc[int64_t(Kb) * p.bnexc + e] : kExcNone;
+            }
+            bsv = in ? p.bstr[Kb] : 0u;
+        };
+        fetch(0, aval, bw, bs);
         __syncthreads();
         for (int c0 = 0; c0 < p.ld; c0 += NT) {
-            // alpha part, diagonal and the C row; every cell of the tile is written
-            for (int idx = tid; idx < MR * NT; idx += 512) {
-                const int r = idx / NT, c = idx % NT, Kb = c0 + c;
+            if (c0 + NT < p.ld) fetch(c0 + NT, anext, bnext, bsnext);
+            const int Kb = c0 + c;
+            // zero rows, diagonal rows and the C row (alpha rows are written below)
+            for (int r = rg; r < MR; r += RG) {
+                const int J = rowJ[r];
+                if (J >= 0) continue;
                 T v = 0;
-                if (Kb < p.Nb) {
-                    const int J = rowJ[r];
-                    if (J >= 0) {
-                        v = T(rowS[r]) * p.cp[int64_t(J) * p.ld + Kb];
-                    } else if (J == -2) {
-                        v = row[Kb];
-                    } else if (J == -3) {
-                        const int k = rowS[r] & 255;
-                        const int occ = (rowS[r] >> 8) + int((p.bstr[Kb] >> k) & 1u);
-                        v = T(occ) * row[Kb];
-                    }
+                if (J == -2) {
+                    v = row[Kb];
+                } else if (J == -3) {
+                    const int k = rowS[r] & 255;
+                    v = T((rowS[r] >> 8) + int((bs >> k) & 1u)) * row[Kb];
                 }
-                D[r * DS + c] = v;
+                D[r * DS + cperm] = v;
             }
+            // alpha rows (padding columns of C are zero)
+#pragma unroll
+            for (int i = 0; i < KA; ++i)
+                if (adst[i] >= 0) D[adst[i] * DS + cperm] = asgn[i] * aval[i];
             __syncthreads();
             // beta part: within a column the excitations have distinct (k, l),
             // so no two threads add to one cell
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+                const uint32_t w = bw[i];
+                if (w == kExcNone) continue;
+                const int k = (w >> 6) & 31, l = (w >> 1) & 31;
+                const T u = row[w >> 11];
+                D[(k * n + l) * DS + cperm] += (w & 1) ? -u : u;
+            }
+            __syncthreads();
+            // M += D D^T over the tile's columns: per slot one operand of each
+            // block (all KT k steps), the row operand reloaded only when the
+            // block row changes, the next slot's column operand in flight
             {
-                constexpr int TPC = 512 / NT;                  // threads per column
-                const int c = tid / TPC, Kb = c0 + c;
-                if (Kb < p.Nb) {
-                    const uint32_t *bx = p.bexc + int64_t(Kb) * p.bnexc;
-                    for (int e = tid % TPC; e < p.bnexc; e += TPC) {
-                        const uint32_t w = bx[e];
-                        if (w == kExcNone) continue;
-                        const int k = (w >> 6) & 31, l = (w >> 1) & 31;
-                        const T u = row[w >> 11];
-                        D[(k * n + l) * DS + c] += (w & 1) ? -u : u;
+                auto frag = [&](int blk, T (&f)[KT]) {
+                    const V *src = reinterpret_cast<const V *>(D + 16 * blk * DS + lfrag);
+#pragma unroll
+                    for (int v = 0; v < KT / VE; ++v) {
+                        const V x = src[v];
+#pragma unroll
+                        for (int e = 0; e < VE; ++e) f[v * VE + e] = x[e];
                     }
+                };
+                // slots in groups of SG: SG independent accumulation chains per k step
+                constexpr int SG = sizeof(T) == 4 ? 2 : 1;
+#pragma unroll
+                for (int g0 = 0; g0 < kRdmSlots; g0 += SG) {
+                    if (g0 < nslot) {
+                        T fa[SG][KT], fb[SG][KT];
+#pragma unroll
+                        for (int q = 0; q < SG; ++q) {
+                            const int sl = g0 + q < kRdmSlots ? g0 + q : kRdmSlots - 1;
+                            if (g0 + q < nslot) {
+                                frag(sbi[sl], fa[q]);
+                                frag(sbj[sl], fb[q]);
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < KT; ++t)
+#pragma unroll
+                            for (int q = 0; q < SG; ++q)
+                                if (g0 + q < kRdmSlots && g0 + q < nslot)
+                                    acc[g0 + q] = M::op(fa[q][t], fb[q][t], acc[g0 + q]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);         // one group's operands in registers at a time
                 }
             }
             __syncthreads();
-            // M += D D^T over the tile's columns
 #pragma unroll
-            for (int t = 0; t < NT / 4; ++t) {
+            for (int i = 0; i < KA; ++i) aval[i] = anext[i];
 #pragma unroll
-                for (int s = 0; s < kRdmSlots; ++s)
-                    if (s < nslot) acc[s] = M::op(D[(off[s] & 0xffffu) + 4 * t], D[(off[s] >> 16) + 4 * t], acc[s]);
-                __builtin_amdgcn_sched_barrier(0);             // bound the operand registers in flight
-            }
-            __syncthreads();
+            for (int i = 0; i < KB; ++i) bw[i] = bnext[i];
+            bs = bsnext;
         }
         // one alpha string's products are summed in the accumulators' precision,
         // the strings of a workgroup in FP64 (each element has one owning lane)
@@ -214,7 +284,7 @@ int rdm_blocks(int n) { return (n * n + 1 + 15) / 16; }
 size_t rdm_lds_bytes(const cisigma_ctx *ctx, int dtype) {
     const int es = dtype == CISIGMA_FP32 ? 4 : 8;
     const int nt = dtype == CISIGMA_FP32 ? rdm_nt<float>() : rdm_nt<double>();
-    return size_t(16 * rdm_blocks(ctx->n) * (nt + 1) + ctx->pl[0].ld[0]) * es + size_t(2 * 16 * rdm_blocks(ctx->n)) * 4;
+    return size_t(16 * rdm_blocks(ctx->n) * (nt + 16 / es) + ctx->pl[0].ld[0]) * es + size_t(2 * 16 * rdm_blocks(ctx->n)) * 4;
 }
 
 int rdm_grid(const cisigma_ctx *ctx) { return std::min(ctx->sp[0].nstr, 256); }
@@ -228,7 +298,8 @@ size_t rdm_part_elems(const cisigma_ctx *ctx) {
 hipError_t launch_rdm(const cisigma_ctx *ctx, const void *cp, int dtype, double *part, double *rdm1, double *rdm2,
                       hipStream_t s) {
     const int nb = rdm_blocks(ctx->n);
-    if (nb > kRdmMaxBlocks) return hipErrorInvalidValue;
+    // the kernel holds at most 64 single excitations per string (n <= 16) and 17 row blocks
+    if (nb > kRdmMaxBlocks || ctx->sp[0].nexc > 64 || ctx->sp[1].nexc > 64) return hipErrorInvalidValue;
     const int npb = nb * (nb + 1) / 2;
     const int G = rdm_grid(ctx);
     const size_t lds = rdm_lds_bytes(ctx, dtype);
