@@ -149,21 +149,29 @@ __global__ __launch_bounds__(512, 1) void k_rdm(RdmArgs<T> p) {
             bsv = in ? p.bstr[Kb] : 0u;
         };
         fetch(0, aval, bw, bs);
+        // D starts at zero for this K_a; afterwards each tile rewrites the alpha,
+        // diagonal and C rows and clears the cells of zero rows that the previous
+        // tile's beta part wrote
+        for (int i = tid; i < MR * DS; i += 512) D[i] = T(0);
+        uint32_t bprev[KB];
+#pragma unroll
+        for (int i = 0; i < KB; ++i) bprev[i] = kExcNone;
         __syncthreads();
         for (int c0 = 0; c0 < p.ld; c0 += NT) {
             if (c0 + NT < p.ld) fetch(c0 + NT, anext, bnext, bsnext);
             const int Kb = c0 + c;
-            // zero rows, diagonal rows and the C row (alpha rows are written below)
-            for (int r = rg; r < MR; r += RG) {
-                const int J = rowJ[r];
-                if (J >= 0) continue;
-                T v = 0;
-                if (J == -2) {
-                    v = row[Kb];
-                } else if (J == -3) {
-                    const int k = rowS[r] & 255;
-                    v = T((rowS[r] >> 8) + int((bs >> k) & 1u)) * row[Kb];
-                }
+#pragma unroll
+            for (int i = 0; i < KB; ++i) {
+                const uint32_t w = bprev[i];
+                if (w == kExcNone) continue;
+                const int r = int(((w >> 6) & 31) * n + ((w >> 1) & 31));
+                if (rowJ[r] == -1) D[r * DS + cperm] = T(0);
+            }
+            // diagonal rows (k, k) for orbitals k = rg, rg + RG, ... and the C row (k = n)
+            for (int k = rg; k <= n; k += RG) {
+                const int r = k < n ? k * n + k : n2;
+                T v = row[Kb];
+                if (k < n) v *= T((rowS[r] >> 8) + int((bs >> k) & 1u));
                 D[r * DS + cperm] = v;
             }
             // alpha rows (padding columns of C are zero)
@@ -223,7 +231,10 @@ __global__ __launch_bounds__(512, 1) void k_rdm(RdmArgs<T> p) {
 #pragma unroll
             for (int i = 0; i < KA; ++i) aval[i] = anext[i];
 #pragma unroll
-            for (int i = 0; i < KB; ++i) bw[i] = bnext[i];
+            for (int i = 0; i < KB; ++i) {
+                bprev[i] = bw[i];
+                bw[i] = bnext[i];
+            }
             bs = bsnext;
         }
         // one alpha string's products are summed in the accumulators' precision,
