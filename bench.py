@@ -126,6 +126,36 @@ def stored_traffic(kernel_tag):
         return None
 
 
+def time_rdm(ctx, torch, n, na, nb, ndet):
+    """Density matrices of a random vector, FP32 and FP64: milliseconds per call
+    (HIP events, 3 calls after one warm-up) and the matrix-core rate of the
+    products issued (upper triangle of 16x16 blocks of the (n^2+1)-row M)."""
+    out = {}
+    nbk = (n * n + 1 + 15) // 16
+    npb = nbk * (nbk + 1) // 2
+    lay = ctx.layout()
+    nstr_a = int(lay["nalpha_str"][0])
+    lda = -(-int(lay["nbeta_str"][0]) // 64) * 64          # beta columns, padded to 64
+    for name, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        C = torch.randn(ndet, dtype=dt, device="cuda")
+        g1 = torch.empty(n * n, dtype=torch.float64, device="cuda")
+        g2 = torch.empty(n ** 4, dtype=torch.float64, device="cuda")
+        ctx.rdm(C, g1, g2)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            ctx.rdm(C, g1, g2)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        flops = 2.0 * 16 * 16 * npb * lda * nstr_a
+        out[name] = {"ms": ms, "issued_tflops": flops / (ms / 1e3) / 1e12, "trace_rdm1": float(g1.view(n, n).trace())}
+        del C, g1, g2
+    out["note"] = "spin-summed rdm1 + rdm2 of a random vector, device FP64 outputs"
+    return out
+
+
 def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector):
     out = {}
     ctx.set_option(cis.OPT_MAX_ITER, max_iter)
@@ -162,6 +192,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-davidson", action="store_true", help="skip timing Davidson to convergence (FP64 vs mixed)")
+    ap.add_argument("--no-rdm", action="store_true", help="skip timing the density matrices")
     ap.add_argument("--nroots", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=300)
@@ -223,6 +254,11 @@ def main():
     extra["sigma_ab_tflops_fp32"] = achieved
     if not args.no_fp64:
         extra["sigma_ab_tflops_fp64"] = flops / (pp64["sigma_ab"] / 1e3) / 1e12
+
+    # NEXT: spin-summed 1- and 2-particle density matrices (one-block spaces, n <= 16)
+    if spec["gas"] is None and n <= 16 and not args.no_rdm:
+        extra["rdm"] = time_rdm(ctx, torch, n, na, nb, ctx.ndet)
+        log(f"rdm: {extra['rdm']}")
 
     if args.copy_calibration_mib > 0:
         copy_calibration(torch, args.copy_calibration_mib)
