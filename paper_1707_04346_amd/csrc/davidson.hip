@@ -35,6 +35,7 @@ namespace {
 constexpr int kRedBlocks = 1024;
 constexpr int kRitzRoots = 4;     // roots per pass of the batched Ritz kernel
 constexpr int kGroup = 8;
+constexpr int kMultiY = 4;        // vectors per pass of the blocked dot / update kernels
 
 template <typename T>
 __device__ __forceinline__ double ld(const T *p, int64_t i) { return double(p[i]); }
@@ -73,6 +74,74 @@ __global__ __launch_bounds__(256) void k_dots(const TX *X, int64_t sx, int nx, c
             double s = block_sum(acc[j], sh);
             if (threadIdx.x == 0) partial[int64_t(blockIdx.x) * nx + i0 + j] = s;
         }
+    }
+}
+
+// partial[b][j * nx + i] = sum over block b's slice of X_i . Y_j, for j < ny <= kMultiY:
+// X is read once for all Y
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_dots_multi(const TX *X, int64_t sx, int nx, const TY *Y, int64_t sy, int ny,
+                                                    int64_t N, double *partial) {
+    constexpr int GX = 4;
+    __shared__ double sh[4][GX * kMultiY];
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    for (int i0 = 0; i0 < nx; i0 += GX) {
+        double acc[GX][kMultiY];
+#pragma unroll
+        for (int a = 0; a < GX; ++a)
+#pragma unroll
+            for (int j = 0; j < kMultiY; ++j) acc[a][j] = 0;
+        for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+            double yv[kMultiY];
+#pragma unroll
+            for (int j = 0; j < kMultiY; ++j) yv[j] = j < ny ? double(Y[j * sy + n]) : 0.0;
+#pragma unroll
+            for (int a = 0; a < GX; ++a) {
+                if (i0 + a >= nx) break;
+                const double xv = double(X[(i0 + a) * sx + n]);
+#pragma unroll
+                for (int j = 0; j < kMultiY; ++j) acc[a][j] += xv * yv[j];
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < GX; ++a)
+#pragma unroll
+            for (int j = 0; j < kMultiY; ++j) {
+                double v = acc[a][j];
+                for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+                if (l == 0) sh[w][a * kMultiY + j] = v;
+            }
+        __syncthreads();
+        if (threadIdx.x < GX * kMultiY) {
+            const int a = threadIdx.x / kMultiY, j = threadIdx.x % kMultiY;
+            const double v = sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+            if (i0 + a < nx && j < ny) partial[int64_t(blockIdx.x) * nx * ny + j * nx + i0 + a] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// T_j -= sum_i c[j * nx + i] X_i for j < ny <= kMultiY: X is read once for all T_j
+template <typename T>
+__global__ __launch_bounds__(256) void k_subtract_multi(const T *X, int64_t sx, int nx, const double *c, int ny,
+                                                        T *Tv, int64_t st, int64_t N) {
+    __shared__ double cs[kMultiY * 512];
+    for (int i = threadIdx.x; i < ny * nx; i += blockDim.x) cs[i] = c[i];
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double v[kMultiY];
+#pragma unroll
+        for (int j = 0; j < kMultiY; ++j) v[j] = j < ny ? double(Tv[j * st + n]) : 0.0;
+        for (int i = 0; i < nx; ++i) {
+            const double xv = double(X[i * sx + n]);
+#pragma unroll
+            for (int j = 0; j < kMultiY; ++j) v[j] -= cs[j * nx + i] * xv;
+        }
+#pragma unroll
+        for (int j = 0; j < kMultiY; ++j)
+            if (j < ny) Tv[j * st + n] = T(v[j]);
     }
 }
 
@@ -299,6 +368,42 @@ hipError_t dots(Dev &d, const TX *X, int64_t sx, int nx, const TY *y, int64_t N,
     return hipStreamSynchronize(d.s);
 }
 
+// out[j * nx + i] = X_i . Y_j for j < ny (blocks of kMultiY), on the host
+template <typename TX, typename TY>
+hipError_t dots_multi(Dev &d, const TX *X, int64_t sx, int nx, const TY *Y, int64_t sy, int ny, int64_t N,
+                      double *host_out) {
+    if (nx == 0 || ny == 0) return hipSuccess;
+    const int g = d.grid(N);
+    for (int j0 = 0; j0 < ny; j0 += kMultiY) {
+        const int nyc = std::min(kMultiY, ny - j0);
+        hipLaunchKernelGGL((k_dots_multi<TX, TY>), dim3(g), dim3(256), 0, d.s, X, sx, nx, Y + int64_t(j0) * sy, sy,
+                           nyc, N, d.partial);
+        hipLaunchKernelGGL(k_reduce_partials, dim3((nx * nyc + 63) / 64), dim3(64), 0, d.s, d.partial, g, nx * nyc,
+                           d.dvec);
+        hipError_t e = hipMemcpyAsync(host_out + size_t(j0) * nx, d.dvec, size_t(nx) * nyc * sizeof(double),
+                                      hipMemcpyDeviceToHost, d.s);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(d.s);
+}
+
+// T_j -= sum_i c[j * nx + i] X_i for j < ny (host coefficients)
+template <typename T>
+hipError_t subtract_multi(Dev &d, const T *X, int64_t sx, int nx, const double *host_c, int ny, T *Tv, int64_t st,
+                          int64_t N) {
+    if (nx == 0 || ny == 0) return hipSuccess;
+    const int g = d.grid(N);
+    for (int j0 = 0; j0 < ny; j0 += kMultiY) {
+        const int nyc = std::min(kMultiY, ny - j0);
+        hipError_t e = hipMemcpyAsync(d.dvec, host_c + size_t(j0) * nx, size_t(nx) * nyc * sizeof(double),
+                                      hipMemcpyHostToDevice, d.s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_subtract_multi<T>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, nyc,
+                           Tv + int64_t(j0) * st, st, N);
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats) {
     auto t0 = std::chrono::steady_clock::now();
@@ -353,9 +458,9 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     DV_TRY(hipMalloc(&X64, size_t(nroots) * N * 8));
     DV_TRY(hipMalloc(&hd, size_t(N) * 8));
     if (mixed) DV_TRY(hipMalloc(&sig64, size_t(N) * 8));
-    DV_TRY(hipMalloc(&d.partial, size_t(kRedBlocks) * 512 * sizeof(double)));
-    // per-block (argmin) or per-vector (dots, <= 512) results
-    DV_TRY(hipMalloc(&d.dvec, size_t(std::max(kRedBlocks, 512)) * sizeof(double)));
+    DV_TRY(hipMalloc(&d.partial, size_t(kRedBlocks) * 512 * kMultiY * sizeof(double)));
+    // per-block (argmin) or per-vector (dots: <= 512 x kMultiY) results and coefficients
+    DV_TRY(hipMalloc(&d.dvec, size_t(std::max(kRedBlocks, 512 * kMultiY)) * sizeof(double)));
     DV_TRY(hipMalloc(&d.pidx, kRedBlocks * sizeof(int64_t)));
     DV_TRY(hipMalloc(&d.ybuf, size_t(kRitzRoots) * (512 + 1) * sizeof(double)));
     DV_TRY(launch_hdiag(ctx, hd, d.s));
@@ -429,12 +534,20 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         return hipGetLastError();
     };
     while (true) {
-        // (4) sigma of the new vectors and the new columns of G
+        // (4) sigma of the new vectors and the new columns of G (one pass over the
+        // basis for all new columns)
         for (int k = m; k < m + nnew; ++k) {
             rc = sigma_of(B + int64_t(k) * N, S + int64_t(k) * N, dt);
             if (rc) return rc;
-            DV_TRY(dots(d, B, N, k + 1, S + int64_t(k) * N, N, col.data()));
-            for (int i = 0; i <= k; ++i) G[size_t(i) * max_space + k] = G[size_t(k) * max_space + i] = col[i];
+        }
+        if (nnew > 0) {
+            std::vector<double> gc(size_t(m + nnew) * nnew);
+            DV_TRY(dots_multi(d, B, N, m + nnew, S + int64_t(m) * N, N, nnew, N, gc.data()));
+            for (int j = 0; j < nnew; ++j) {
+                const int k = m + j;
+                for (int i = 0; i <= k; ++i)
+                    G[size_t(i) * max_space + k] = G[size_t(k) * max_space + i] = gc[size_t(j) * (m + nnew) + i];
+            }
         }
         m += nnew;
         std::vector<double> Gm(size_t(m) * m);
@@ -531,28 +644,44 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int r = 0; r < nroots; ++r) G[size_t(r) * max_space + r] = theta[r];
             m = nroots;
         }
-        // (3) corrections, orthogonalised against the basis (CGS2) and each other
+        // (3) corrections, orthogonalised against the basis (CGS2, all corrections
+        // in one pass over the basis) and then against each other
         nnew = 0;
         bool any_open = false;
         for (int r = 0; r < nroots; ++r) any_open = any_open || refined_now || rnorm[r] > rtol;
-        for (int r = 0; r < nroots; ++r) {
+        std::vector<int> cand;
+        for (int r = 0; r < nroots && m + int(cand.size()) < max_space; ++r) {
             // roots whose residual already meets the threshold get no new direction
             if (any_open && !refined_now && rnorm[r] <= rtol) continue;
-            T *t = B + int64_t(m + nnew) * N;
-            DV_TRY(hipMemcpyAsync(t, TB + int64_t(r) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+            cand.push_back(r);
+        }
+        const int nc = int(cand.size());
+        for (int j = 0; j < nc; ++j) {
+            T *t = B + int64_t(m + j) * N;
+            DV_TRY(hipMemcpyAsync(t, TB + int64_t(cand[j]) * N, N * es, hipMemcpyDeviceToDevice, d.s));
             if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
+        }
+        if (nc > 0 && m > 0) {
+            std::vector<double> cc(size_t(m) * nc);
             for (int pass = 0; pass < 2; ++pass) {
-                DV_TRY(dots(d, B, N, m + nnew, t, N, col.data()));
-                DV_TRY(hipMemcpyAsync(d.dvec, col.data(), (m + nnew) * sizeof(double), hipMemcpyHostToDevice, d.s));
-                hipLaunchKernelGGL((k_subtract<T>), dim3(g), dim3(256), 0, d.s, B, N, m + nnew, d.dvec, t, N);
+                DV_TRY(dots_multi(d, B, N, m, B + int64_t(m) * N, N, nc, N, cc.data()));
+                DV_TRY(subtract_multi(d, B, N, m, cc.data(), nc, B + int64_t(m) * N, N, N));
+            }
+        }
+        for (int j = 0; j < nc; ++j) {
+            T *t = B + int64_t(m + j) * N;
+            for (int pass = 0; pass < 2 && nnew > 0; ++pass) {
+                DV_TRY(dots(d, B + int64_t(m) * N, N, nnew, t, N, col.data()));
+                DV_TRY(hipMemcpyAsync(d.dvec, col.data(), nnew * sizeof(double), hipMemcpyHostToDevice, d.s));
+                hipLaunchKernelGGL((k_subtract<T>), dim3(g), dim3(256), 0, d.s, B + int64_t(m) * N, N, nnew, d.dvec, t, N);
             }
             double tt;
             DV_TRY(dots(d, t, N, 1, t, N, &tt));
-            double nt = std::sqrt(tt);
+            const double nt = std::sqrt(tt);
             if (!(nt > 1e-12)) continue;
-            hipLaunchKernelGGL((k_scale_copy<T, T>), dim3(g), dim3(256), 0, d.s, t, t, 1.0 / nt, N);
+            T *dst = B + int64_t(m + nnew) * N;
+            hipLaunchKernelGGL((k_scale_copy<T, T>), dim3(g), dim3(256), 0, d.s, t, dst, 1.0 / nt, N);
             ++nnew;
-            if (m + nnew >= max_space) break;
         }
         if (nnew == 0) {
             // every correction vanished: the residuals lie in the basis (a basis
