@@ -634,12 +634,14 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     // of what is free, else column chunks (multiples of 64)
     if (c->cas) {
         size_t rows = 0, cols = 0;
+        bool shapes_ok = true;
         for (int s = 0; s < 2; ++s)
             if (c->sp[s].nel >= 2) {
                 rows = std::max(rows, size_t(c->sp[s].nK) * c->sp[s].npv);
                 cols = std::max(cols, size_t(c->pl[s].ld[0]));
+                shapes_ok = shapes_ok && cis::same_spin_materialisable(c->sp[s].npv);
             }
-        if (rows > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        if (rows > 0 && shapes_ok && hipMemGetInfo(&fr, &tot) == hipSuccess) {
             size_t budget = fr / 2;
             size_t chunk = std::min(cols, budget / (rows * es) / cis::kTileCols * cis::kTileCols);
             if (chunk >= size_t(cis::kTileCols) && hipMalloc(&W.ys, rows * chunk * es) == hipSuccess)
@@ -892,15 +894,6 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
         }
     }
     c->cas = (c->sp[0].ntype == 1 && c->sp[1].ntype == 1);
-    // the same-spin kernel is built for up to 14 empty orbitals + 2 per K
-    for (int s = 0; s < 2; ++s) {
-        int N = c->sp[s].nel;
-        if (N >= 2 && norb - N + 2 > 14) {
-            cis_set_error(c, CISIGMA_EUNSUPPORTED, "init: more than 12 empty orbitals of one spin");
-            free_ctx(c);
-            return CISIGMA_EUNSUPPORTED;
-        }
-    }
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);

@@ -240,6 +240,9 @@ bool launch_sigma_ab_gas(const cisigma_ctx *ctx, const void *C, void *sigma, int
 // columns, a multiple of 64) and gather into Y, overwriting Y.
 hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *X, void *Y, int dtype,
                                   hipStream_t s, void *Ys = nullptr, int chunk = 0);
+// whether the same-spin pair count npv has compiled MFMA kernels (else a plain
+// atomic kernel serves it and the materialised form is not used)
+bool same_spin_materialisable(int npv);
 // caller vector -> alpha-major and beta-major padded copies
 hipError_t launch_scatter_in(const cisigma_ctx *ctx, const void *C, void *cp, void *ct, int dtype, hipStream_t s);
 // sigma = alpha-major accumulator + transpose of the beta-major accumulator

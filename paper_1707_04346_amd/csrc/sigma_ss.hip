@@ -356,6 +356,40 @@ __global__ __launch_bounds__(256) void k_one_electron(const T *X, T *Y, const ui
     }
 }
 
+// Same-spin part for pair counts beyond the compiled MFMA shapes (many empty
+// orbitals, few electrons: e.g. 32 orbitals): per K and column, the plain
+// double loop Y(K+P) += e(K,P) sum_Q V(P,Q) e(K,Q) X(K+Q), accumulated with
+// atomics.  O(nK npv^2) per column; such spaces are small.
+template <typename T>
+__global__ __launch_bounds__(kTileCols) void k_sigma_ss_direct(SsArgs<T> p) {
+    const int K = blockIdx.x;
+    const uint32_t *pr = p.pairs + int64_t(K) * p.npv;
+    for (int tile = blockIdx.y; tile < p.ntiles; tile += gridDim.y) {
+        const int u = p.tile_u[tile];
+        const int col = p.tile_c0[tile] + int(threadIdx.x);
+        for (int ep = 0; ep < p.npv; ++ep) {
+            const uint32_t wp = pr[ep];
+            if (wp == kPairNone) continue;
+            const int Jp = int(wp >> 11), tp = p.stype[Jp];
+            const int64_t sp = p.seg[int64_t(tp) * p.nto + u];
+            if (sp < 0) continue;
+            const T *vrow = p.V + int64_t((wp >> 1) & 1023u) * p.nps;
+            T acc = 0;
+            for (int eq = 0; eq < p.npv; ++eq) {
+                const uint32_t wq = pr[eq];
+                if (wq == kPairNone) continue;
+                const int Jq = int(wq >> 11), tq = p.stype[Jq];
+                const int64_t sq = p.seg[int64_t(tq) * p.nto + u];
+                if (sq < 0) continue;
+                const T v = vrow[(wq >> 1) & 1023u];
+                const T x = p.X[sq + int64_t(Jq - p.sstart[tq]) * p.ld[u] + col];
+                acc += ((wp ^ wq) & 1u) ? -v * x : v * x;
+            }
+            atomicAdd(&p.Y[sp + int64_t(Jp - p.sstart[tp]) * p.ld[u] + col], acc);
+        }
+    }
+}
+
 template <typename T, int KS, int MBL, bool STORE>
 hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
     constexpr int KP = 4 * KS, MP = 16 * MBL;
@@ -394,6 +428,14 @@ hipError_t dispatch_ssy(const SsyArgs<T> &a, hipStream_t s) {
     CIS_SSY(34, 9) CIS_SSY(39, 10) CIS_SSY(43, 11)
 #undef CIS_SSY
     return hipErrorInvalidValue;
+}
+
+// pair counts served by the MFMA kernels: npv = C(m, 2) for m = 2..14 (m =
+// empty orbitals + 2; larger m leaves the V block too big for the LDS)
+bool ss_shape_compiled(int npv) {
+    for (int m = 2; m <= 14; ++m)
+        if (npv == m * (m - 1) / 2) return true;
+    return npv <= 0;
 }
 
 template <typename T, bool STORE>
@@ -444,7 +486,13 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
     a.nps = ctx->nps;
     a.nto = ctx->sp[other].ntype;
     a.ntiles = L.ntiles;
-    if (!Ys) return dispatch_ss<T, false>(a, s);
+    if (!Ys) {
+        if (ss_shape_compiled(S.npv)) return dispatch_ss<T, false>(a, s);
+        int ysplit = 1;
+        while (int64_t(S.nK) * ysplit < 2048 && ysplit < L.ntiles) ysplit *= 2;
+        hipLaunchKernelGGL((k_sigma_ss_direct<T>), dim3(S.nK, ysplit), dim3(kTileCols), 0, s, a);
+        return hipGetLastError();
+    }
     // materialised form, one column chunk at a time: store rows K*npv+P, then gather per string
     const int per = S.nel * (S.nel - 1) / 2;
     const int64_t ld = L.ld[0];
@@ -492,5 +540,7 @@ hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *
     return dtype == CISIGMA_FP32 ? same_spin_t<float>(ctx, spin, X, Y, Ys, chunk, s)
                                  : same_spin_t<double>(ctx, spin, X, Y, Ys, chunk, s);
 }
+
+bool same_spin_materialisable(int npv) { return ss_shape_compiled(npv); }
 
 }  // namespace cis
