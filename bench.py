@@ -65,29 +65,43 @@ def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0, parity=0):
     ctx.set_option(cis.OPT_SPIN_PARITY, 0)
     assert ncalls == steps
     per_pass = {k: v / ncalls for k, v in passes.items()}
-    return dt, per_pass, C
+    return dt, per_pass, C, S
 
 
-def cpu_baseline(spec, h, g, C_dev, target_s):
+def cpu_baseline(spec, h, g, C_dev, target_s, gpu_sigmas):
+    """The oracle's row-sampled sigma of the benchmark vector, timed; the same
+    rows also give the GPU sigma errors against the oracle (gpu_sigmas: name ->
+    device sigma of the same vector), returned as a second value."""
     import numpy as np
     import oracle
     sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
     c = C_dev.double().cpu().numpy()
     rng = np.random.default_rng(7)
     nrows, done, t_used = 64, 0, 0.0
+    all_rows, all_ref = [], []
     while t_used < target_s:
         rows = rng.integers(0, sp.ndet, nrows)
         t0 = time.perf_counter()
-        sp.sigma_rows(rows, c)
+        ref = sp.sigma_rows(rows, c)
         t_used += time.perf_counter() - t0
+        all_rows.append(rows)
+        all_ref.append(ref)
         done += nrows
         nrows = min(nrows * 2, 1 << 16)
     rows_per_s = done / t_used
+    rows = np.concatenate(all_rows)
+    ref = np.concatenate(all_ref)
+    import torch
+    idx = torch.tensor(rows, device=C_dev.device)
+    errs = {"rows": int(rows.size)}
+    for name, S in gpu_sigmas.items():
+        got = S[idx].double().cpu().numpy()
+        errs[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
     return {"value": rows_per_s / sp.ndet, "unit": "sigma builds/s", "cores": oracle.max_threads(),
             "kind": "oracle",
             "sample": f"{done} random output determinants of the same CAS vector through the oracle's "
                       f"row-sampled Slater-Condon sigma ({t_used:.1f} s, {rows_per_s:.0f} rows/s), scaled to "
-                      f"the {sp.ndet} rows of one sigma build"}
+                      f"the {sp.ndet} rows of one sigma build"}, errs
 
 
 def copy_calibration(torch, mib):
@@ -216,7 +230,7 @@ def main():
     init_s = time.perf_counter() - t0
     log(f"init {args.workload}: ndet={ctx.ndet} in {init_s:.2f} s")
 
-    dt32, pp32, C32 = time_sigma(ctx, cis, torch, "fp32", args.steps, args.warmup)
+    dt32, pp32, C32, S32 = time_sigma(ctx, cis, torch, "fp32", args.steps, args.warmup)
     ms32 = 1e3 * dt32 / args.steps
     path32 = ctx.last_path(cis.FP32)
     log(f"fp32 sigma: {ms32:.2f} ms/step, passes {pp32}, path flags {path32}")
@@ -226,12 +240,12 @@ def main():
     # M_S = 0 sector (n_alpha = n_beta, one block): the beta-beta pass is replaced by a transpose
     sector = na == nb and spec["gas"] is None
     if sector:
-        dtp, ppp, _ = time_sigma(ctx, cis, torch, "fp32", args.steps, 1, parity=1)
+        dtp, ppp, _, _ = time_sigma(ctx, cis, torch, "fp32", args.steps, 1, parity=1)
         extra.update({"fp32_even_sector_sigma_per_s": args.steps / dtp,
                       "fp32_even_sector_ms_per_step": 1e3 * dtp / args.steps, "fp32_even_sector_pass_ms": ppp})
         log(f"fp32 sigma, even M_S=0 sector: {1e3 * dtp / args.steps:.2f} ms/step, passes {ppp}")
     if not args.no_fp64:
-        dt64, pp64, _ = time_sigma(ctx, cis, torch, "fp64", max(2, args.steps // 2), 1)
+        dt64, pp64, _, _ = time_sigma(ctx, cis, torch, "fp64", max(2, args.steps // 2), 1)
         ms64 = 1e3 * dt64 / max(2, args.steps // 2)
         extra.update({"fp64_sigma_per_s": 1e3 / ms64, "fp64_ms_per_step": ms64, "fp64_pass_ms": pp64,
                       "speedup_fp32_vs_fp64": ms64 / ms32})
@@ -268,8 +282,17 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(spec, h, g, C32, args.cpu_seconds)
-        log(f"cpu baseline: {cpu}")
+        # sigma of the benchmark vector in both precisions, checked against the oracle on its sampled rows
+        sig = {"fp32": S32}
+        if not args.no_fp64:
+            C64 = C32.double()
+            S64 = torch.empty_like(C64)
+            ctx.apply(C64, S64)
+            torch.cuda.synchronize()
+            sig["fp64"] = S64
+        cpu, errs = cpu_baseline(spec, h, g, C32, args.cpu_seconds, sig)
+        extra["sigma_rel_error_vs_oracle_sampled_rows"] = errs
+        log(f"cpu baseline: {cpu}; sigma errors vs oracle: {errs}")
 
     cfg = {"workload": f"{args.workload}: {n} orbitals, {na} alpha + {nb} beta electrons"
                        + (f", GAS {spec['gas']}" if spec["gas"] else " (CAS)")

@@ -77,6 +77,13 @@ extern "C" {
 #define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels */
 #define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products: at most this many columns per chunk
                                       (a positive multiple of 64); 0 (default): as many as fit in memory */
+#define CISIGMA_OPT_GRAPH 11       /* nonzero: cisigma_apply on a non-NULL stream runs its kernels eagerly
+                                      at the first call with a given (C, sigma, dtype, stream) and captures
+                                      them into a HIP graph that later calls with the same arguments replay
+                                      (for callers applying sigma to the same buffers many times, where
+                                      launch overhead matters: small spaces).  NULL stream, profiling on:
+                                      eager.  Changing the spin-parity, sigma-path or chunk options drops
+                                      the captured graphs.  Default 0 */
 #define CISIGMA_OPT_SPIN_PARITY 10 /* M_S = 0 spin symmetry (Sec. 3.1, Sec. 3.3): p = +1 or -1 restricts
                                       cisigma_apply and cisigma_davidson to vectors with
                                       C(Ib, Ia) = p C(Ia, Ib) (p = +1: even total spin S, singlets first;

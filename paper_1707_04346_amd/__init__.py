@@ -20,6 +20,7 @@ PASSES = ["layout_in", "clear", "sigma_aa", "sigma_ab", "sigma_bb", "layout_out"
 OPT_SIGMA_PATH = 8
 OPT_SS_CHUNK = 9
 OPT_SPIN_PARITY = 10
+OPT_GRAPH = 11
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")

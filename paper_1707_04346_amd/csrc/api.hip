@@ -101,6 +101,7 @@ void free_ctx(cisigma_ctx *c) {
         hipFree(W.cp); hipFree(W.sp); hipFree(W.ct); hipFree(W.st); hipFree(W.ys);
     }
     hipFree(c->d_rdm);
+    cis::drop_graphs(c);
     hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
     hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
@@ -712,6 +713,45 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     return CISIGMA_OK;
 }
 
+void drop_graphs(cisigma_ctx *c) {
+    for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
+}
+
+int apply_sigma_graph(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s) {
+    for (auto &g : c->graphs)
+        if (g.C == C && g.sigma == sigma && g.dtype == dtype && g.stream == s) {
+            HIP_OR_FAIL(c, hipGraphLaunch(g.exec, s), "apply: graph launch");
+            c->last_path[dtype == CISIGMA_FP32] = g.path;
+            return CISIGMA_OK;
+        }
+    // first call with these arguments: run eagerly (this call's result; it also
+    // allocates the workspace and sets every kernel attribute), then capture the
+    // same launches for the next calls
+    int rc = apply_sigma(c, C, sigma, dtype, s);
+    if (rc) return rc;
+    const int path = c->last_path[dtype == CISIGMA_FP32];
+    HIP_OR_FAIL(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "apply: graph capture");
+    rc = apply_sigma(c, C, sigma, dtype, s);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (rc || e != hipSuccess || !graph) {
+        if (graph) hipGraphDestroy(graph);
+        if (rc) return rc;
+        return hip_fail(c, e != hipSuccess ? e : hipErrorUnknown, "apply: graph capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    HIP_OR_FAIL(c, e, "apply: graph instantiation");
+    if (c->graphs.size() >= 16) {
+        hipGraphExecDestroy(c->graphs.front().exec);
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({C, sigma, dtype, s, exec, path});
+    return CISIGMA_OK;
+}
+
 }  // namespace cis
 
 static void prof_reset(cisigma_ctx *c) {
@@ -1008,15 +1048,22 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             ctx->verbose = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_SIGMA_PATH:
+            cis::drop_graphs(ctx);
             if (value != 0 && value != 1) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0 or 1");
             ctx->ab_mode = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_SS_CHUNK:
+            cis::drop_graphs(ctx);
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
             return CISIGMA_OK;
+        case CISIGMA_OPT_GRAPH:
+            cis::drop_graphs(ctx);
+            ctx->graph_mode = value != 0;
+            return CISIGMA_OK;
         case CISIGMA_OPT_SPIN_PARITY:
+            cis::drop_graphs(ctx);
             if (value != 0 && value != 1 && value != -1)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: spin parity must be -1, 0 or +1");
             if (value != 0 && ctx->sp[0].nel != ctx->sp[1].nel)
@@ -1041,6 +1088,8 @@ CIS_API int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtyp
     const size_t bytes = size_t(ctx->lay.ndet) * (dtype == CISIGMA_FP32 ? 4 : 8);
     const char *a = static_cast<const char *>(C), *b = static_cast<const char *>(sigma);
     if (a < b + bytes && b < a + bytes) return cis_set_error(ctx, CISIGMA_EINVAL, "apply: C and sigma overlap");
+    if (ctx->graph_mode && stream && !ctx->profile)
+        return cis::apply_sigma_graph(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
     return cis::apply_sigma(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
 }
 

@@ -201,6 +201,17 @@ struct cisigma_ctx {
     int ab_mode = 0;
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)
     int spin_parity = 0;   // M_S = 0 sector: C(Ib, Ia) = p C(Ia, Ib) assumed (0: none)
+    // captured apply graphs (CISIGMA_OPT_GRAPH)
+    struct ApplyGraph {
+        const void *C;
+        void *sigma;
+        int dtype;
+        hipStream_t stream;
+        hipGraphExec_t exec;
+        int path;
+    };
+    int graph_mode = 0;
+    std::vector<ApplyGraph> graphs;
     double *d_rdm = nullptr;   // density-matrix partial sums (allocated on first use)
     size_t rdm_elems = 0;
     // per-pass event timing of apply (CISIGMA_OPT_PROFILE)
@@ -267,6 +278,9 @@ hipError_t launch_rdm(const cisigma_ctx *ctx, const void *cp, int dtype, double 
 int davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats);
 // sigma of one device vector on the given stream (api.hip)
 int apply_sigma(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+// the same through a captured graph (CISIGMA_OPT_GRAPH; non-NULL stream)
+int apply_sigma_graph(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+void drop_graphs(cisigma_ctx *ctx);
 
 }  // namespace cis
 
