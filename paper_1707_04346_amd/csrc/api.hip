@@ -9,6 +9,7 @@
 // cisigma_apply enqueues: C -> padded copies, sigma_3, sigma_2, sigma_1,
 // padded accumulators -> sigma (Eq. 8: sigma = sigma_1 + sigma_2 + sigma_3).
 #include <algorithm>
+#include <array>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -106,9 +107,13 @@ void free_ctx(cisigma_ctx *c) {
     hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
     hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
     hipFree(c->d_act_start); hipFree(c->d_act_tiles);
-    hipFree(c->go.d_tile_u); hipFree(c->go.d_tile_c0); hipFree(c->go.d_slot); hipFree(c->go.d_act);
-    hipFree(c->go.d_act_start); hipFree(c->go.d_g32); hipFree(c->go.d_g64);
-    hipFree(c->go.plan.d_entries[0]); hipFree(c->go.plan.d_entries[1]);
+    hipFree(c->go.d_slot); hipFree(c->go.d_coff); hipFree(c->go.d_g32); hipFree(c->go.d_g64);
+    for (int d = 0; d < 2; ++d) {
+        hipFree(c->go.d_act[d]);
+        hipFree(c->go.d_units[d]);
+        hipFree(c->go.plan[d].d_entries[0]);
+        hipFree(c->go.plan[d].d_entries[1]);
+    }
     for (auto e : c->prof_events) hipEventDestroy(e);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
@@ -325,40 +330,48 @@ struct PlanSpec {
     int ntile = 0;                                 // 32-column source tiles
     std::function<int(int, int)> source;           // (tile, column) -> beta string index, -1: none
     std::function<int(int, int)> w_row;            // orbital pair (k >= l) -> W row
+    std::function<int(int)> target;                // beta string -> sigma slot, -1: outside (dropped); none: identity
     int nvirt = 0;                                 // sigma slots (targets < nvirt; discard slots nvirt + lane)
     uint32_t unit[2] = {8, 4};                     // bytes per unit of the slot field: [FP64, FP32]
     std::function<int(int)> width;                 // entries per lane the kernel compiles for `need`, 0: none
 };
 
-// Builds the two encodings of a scatter plan into P (P.ew = 0: no plan).
-int make_scatter_plan(cisigma_ctx *c, const PlanSpec &ps, cis::ScatterPlan &P) {
-    constexpr int NT = 32, WS = 33;
-    (void)NT;
-    const auto &B = c->sp[1];
-    std::vector<uint32_t> exc(size_t(B.nstr) * B.nexc), str(B.nstr);
-    HIP_OR_FAIL(c, hipMemcpy(exc.data(), B.d_exc, exc.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
-    HIP_OR_FAIL(c, hipMemcpy(str.data(), B.d_str, str.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
-    struct Item { uint32_t tgt, widx, neg, start, end; };
-    const int ntile = ps.ntile;
-    std::vector<std::vector<Item>> tiles(ntile);
+// The contributions of every source tile (target slot, W element, sign),
+// sorted by target, with group starts and ends marked, and the smallest entry
+// count per lane whose four wave ranges hold every tile.
+struct PlanItem { uint32_t tgt, widx, neg, start, end; };
+struct PlanTiles {
+    std::vector<std::vector<PlanItem>> tiles;
     int need = 1;
-    for (int t = 0; t < ntile; ++t) {
-        auto &tile = tiles[t];
+};
+
+int plan_items(cisigma_ctx *c, const PlanSpec &ps, const std::vector<uint32_t> &exc, const std::vector<uint32_t> &str,
+               PlanTiles &out) {
+    constexpr int WS = 33;
+    const auto &B = c->sp[1];
+    out.tiles.assign(ps.ntile, {});
+    out.need = 1;
+    for (int t = 0; t < ps.ntile; ++t) {
+        auto &tile = out.tiles[t];
         for (int col = 0; col < 32; ++col) {
             const int Jb = ps.source(t, col);
             if (Jb < 0) continue;
+            auto push = [&](int Ib, int k, int l, uint32_t neg) {
+                const int slot = ps.target ? ps.target(Ib) : Ib;
+                if (slot < 0) return;
+                tile.push_back({uint32_t(slot), uint32_t(ps.w_row(std::max(k, l), std::min(k, l)) * WS + col), neg, 0u, 0u});
+            };
             for (int e = 0; e < B.nexc; ++e) {
                 const uint32_t w = exc[size_t(Jb) * B.nexc + e];
                 if (w == cis::kExcNone) continue;
-                const int k = (w >> 6) & 31, l = (w >> 1) & 31;
-                tile.push_back({w >> 11, uint32_t(ps.w_row(std::max(k, l), std::min(k, l)) * WS + col), w & 1u, 0u, 0u});
+                push(int(w >> 11), (w >> 6) & 31, (w >> 1) & 31, w & 1u);
             }
             for (uint32_t b = str[Jb]; b; b &= b - 1) {
                 const int k = __builtin_ctz(b);
-                tile.push_back({uint32_t(Jb), uint32_t(ps.w_row(k, k) * WS + col), 0u, 0u, 0u});
+                push(Jb, k, k, 0u);
             }
         }
-        std::stable_sort(tile.begin(), tile.end(), [](const Item &a, const Item &b) { return a.tgt < b.tgt; });
+        std::stable_sort(tile.begin(), tile.end(), [](const PlanItem &a, const PlanItem &b) { return a.tgt < b.tgt; });
         for (size_t i = 0; i < tile.size(); ++i) {
             tile[i].start = (i == 0 || tile[i].tgt != tile[i - 1].tgt);
             tile[i].end = (i + 1 == tile.size() || tile[i].tgt != tile[i + 1].tgt);
@@ -378,53 +391,58 @@ int make_scatter_plan(cisigma_ctx *c, const PlanSpec &ps, cis::ScatterPlan &P) {
             }
             return ranges <= 4;
         };
-        while (!fits(size_t(64) * need)) ++need;
+        while (!fits(size_t(64) * out.need)) ++out.need;
     }
-    // wave ranges of a tile for entries-per-lane ew; false when a group would
-    // span more than four lanes
-    auto ranges_of = [&](const std::vector<Item> &tile, int ew, std::vector<std::pair<size_t, size_t>> &rg) {
-        rg.clear();
-        const size_t cap = size_t(64) * ew;
-        size_t i = 0;
-        for (int wv = 0; wv < 4 && i < tile.size(); ++wv) {
-            size_t j = i;
-            while (j < tile.size()) {
-                size_t g = j + 1;
-                while (g < tile.size() && !tile[g].start) ++g;
-                if (g - i > cap) break;
-                j = g;
-            }
-            for (size_t g0 = i; g0 < j;) {
-                size_t g1 = g0 + 1;
-                while (g1 < j && !tile[g1].start) ++g1;
-                if ((g1 - 1 - i) / ew - (g0 - i) / ew > 3) return false;
-                g0 = g1;
-            }
-            rg.push_back({i, j});
-            i = j;
+    return CISIGMA_OK;
+}
+
+// wave ranges of a tile for entries-per-lane ew; false when a group would
+// span more than four lanes
+bool plan_ranges(const std::vector<PlanItem> &tile, int ew, std::vector<std::pair<size_t, size_t>> &rg) {
+    rg.clear();
+    const size_t cap = size_t(64) * ew;
+    size_t i = 0;
+    for (int wv = 0; wv < 4 && i < tile.size(); ++wv) {
+        size_t j = i;
+        while (j < tile.size()) {
+            size_t g = j + 1;
+            while (g < tile.size() && !tile[g].start) ++g;
+            if (g - i > cap) break;
+            j = g;
         }
-        return i == tile.size();
-    };
-    int ew = 0;
-    for (int cand : {ps.width(need), 16}) {
-        if (cand < need || ps.width(cand) != cand) continue;
-        std::vector<std::pair<size_t, size_t>> rg;
-        bool ok = true;
-        for (int t = 0; t < ntile && ok; ++t) ok = ranges_of(tiles[t], cand, rg);
-        if (ok) { ew = cand; break; }
+        for (size_t g0 = i; g0 < j;) {
+            size_t g1 = g0 + 1;
+            while (g1 < j && !tile[g1].start) ++g1;
+            if ((g1 - 1 - i) / ew - (g0 - i) / ew > 3) return false;
+            g0 = g1;
+        }
+        rg.push_back({i, j});
+        i = j;
     }
-    if (ew == 0) return CISIGMA_OK;
+    return i == tile.size();
+}
+
+bool plan_fits(const PlanTiles &pt, int ew) {
+    std::vector<std::pair<size_t, size_t>> rg;
+    for (const auto &tile : pt.tiles)
+        if (!plan_ranges(tile, ew, rg)) return false;
+    return true;
+}
+
+// plan words of every tile for entry count ew, appended to out[FP64], out[FP32]
+void plan_emit(const PlanSpec &ps, const PlanTiles &pt, int ew, std::vector<uint32_t> (&out)[2]) {
     const size_t per_wave = size_t(ew + 1) * 64, per_tile = 4 * per_wave;
-    std::vector<uint32_t> plan[2] = {std::vector<uint32_t>(per_tile * ntile), std::vector<uint32_t>(per_tile * ntile)};
     std::vector<std::pair<size_t, size_t>> rg;
     for (int es_i = 0; es_i < 2; ++es_i) {
         const uint32_t es = es_i == 0 ? 8 : 4;   // [0]: FP64, [1]: FP32
-        auto &PL = plan[es_i];
-        for (int t = 0; t < ntile; ++t) {
-            const auto &tile = tiles[t];
-            ranges_of(tile, ew, rg);
+        auto &PL = out[es_i];
+        const size_t base0 = PL.size();
+        PL.resize(base0 + per_tile * pt.tiles.size());
+        for (size_t t = 0; t < pt.tiles.size(); ++t) {
+            const auto &tile = pt.tiles[t];
+            plan_ranges(tile, ew, rg);
             for (int wv = 0; wv < 4; ++wv) {
-                const size_t base = (size_t(t) * 4 + wv) * per_wave;
+                const size_t base = base0 + (t * 4 + wv) * per_wave;
                 const size_t i = wv < int(rg.size()) ? rg[wv].first : 0, j = wv < int(rg.size()) ? rg[wv].second : 0;
                 for (int lane = 0; lane < 64; ++lane) {
                     const uint32_t spare = (uint32_t(ps.nvirt) + lane) * es;    // discard slot, bytes
@@ -434,7 +452,7 @@ int make_scatter_plan(cisigma_ctx *c, const PlanSpec &ps, cis::ScatterPlan &P) {
                         const size_t e = i + size_t(lane) * ew + q;
                         uint32_t word = (spare / unit) << 16;                    // padding: W element 0, discard slot
                         if (e < j) {
-                            const Item &it = tile[e];
+                            const PlanItem &it = tile[e];
                             const uint32_t slot = it.end ? it.tgt * es : spare;
                             word = ((slot / unit) << 16) | (it.widx * es) | it.neg;
                             if (q == 0 && !it.start) {
@@ -451,9 +469,34 @@ int make_scatter_plan(cisigma_ctx *c, const PlanSpec &ps, cis::ScatterPlan &P) {
             }
         }
     }
+}
+
+int plan_tables(cisigma_ctx *c, std::vector<uint32_t> &exc, std::vector<uint32_t> &str) {
+    const auto &B = c->sp[1];
+    exc.resize(size_t(B.nstr) * B.nexc);
+    str.resize(B.nstr);
+    HIP_OR_FAIL(c, hipMemcpy(exc.data(), B.d_exc, exc.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
+    HIP_OR_FAIL(c, hipMemcpy(str.data(), B.d_str, str.size() * 4, hipMemcpyDeviceToHost), "init: scatter plan");
+    return CISIGMA_OK;
+}
+
+// Builds the two encodings of a scatter plan into P (P.ew = 0: no plan).
+int make_scatter_plan(cisigma_ctx *c, const PlanSpec &ps, cis::ScatterPlan &P) {
+    std::vector<uint32_t> exc, str;
+    int rc = plan_tables(c, exc, str);
+    if (rc) return rc;
+    PlanTiles pt;
+    rc = plan_items(c, ps, exc, str, pt);
+    if (rc) return rc;
+    int ew = 0;
+    for (int cand : {ps.width(pt.need), 16})
+        if (cand >= pt.need && ps.width(cand) == cand && plan_fits(pt, cand)) { ew = cand; break; }
+    if (ew == 0) return CISIGMA_OK;
+    std::vector<uint32_t> plan[2];
+    plan_emit(ps, pt, ew, plan);
     HIP_OR_FAIL(c, upload(&P.d_entries[0], plan[0]), "init: scatter plan");
     HIP_OR_FAIL(c, upload(&P.d_entries[1], plan[1]), "init: scatter plan");
-    P.ntile = ntile;
+    P.ntile = ps.ntile;
     P.ew = ew;
     return CISIGMA_OK;
 }
@@ -497,8 +540,7 @@ int build_gas_owner(cisigma_ctx *c) {
     if (c->cas || c->na == 0 || c->nb == 0 || A.nexc == 0 || B.nexc == 0) return CISIGMA_OK;
     const int rb = (c->npair + 15) / 16, mp = 16 * rb;
     const int ks = (A.nexc + 1 + 3) / 4, kp = 4 * ks;
-    if (ks > 32 || rb > 32 || B.ntype > 255 || size_t(mp) * WS * 8 >= 65536 || size_t(B.nstr) + 64 >= 65536)
-        return CISIGMA_OK;
+    if (ks > 32 || rb > 32 || B.ntype > 255 || size_t(mp) * WS * 8 >= 65536) return CISIGMA_OK;
     if (cis::sigma_ab_gas_width(ks, rb, 1) == 0) return CISIGMA_OK;
     std::vector<int> space(n, 0);
     for (int g = 0; g < ng; ++g)
@@ -548,12 +590,22 @@ int build_gas_owner(cisigma_ctx *c) {
             slot_src[size_t(ta) * kp + q] = es[q].first;
         }
     }
-    // source tiles and the active lists
+    // source tiles: 32 columns of one beta type
     std::vector<int> tu, tc;
     for (int u = 0; u < B.ntype; ++u)
         for (int c0 = 0; c0 < B.tcount[u]; c0 += 32) { tu.push_back(u); tc.push_back(c0); }
-    std::vector<uint32_t> act;
-    std::vector<int> astart{0};
+    // compact columns: the beta types allowed with each alpha type, concatenated
+    std::vector<int> coff(size_t(A.ntype) * B.ntype, -1), ncols(A.ntype, 0), btype(B.nstr);
+    for (int u = 0; u < B.ntype; ++u)
+        for (int i = B.tstart[u]; i < B.tstart[u + 1]; ++i) btype[i] = u;
+    for (int ta = 0; ta < A.ntype; ++ta)
+        for (int u = 0; u < B.ntype; ++u)
+            if (allowed(ta, u)) {
+                coff[size_t(ta) * B.ntype + u] = ncols[ta];
+                ncols[ta] += B.tcount[u];
+            }
+    // per alpha type, the source tiles that can change its sigma, with k-step and row-block masks
+    std::vector<std::vector<std::array<uint32_t, 4>>> tact(A.ntype);
     for (int ta = 0; ta < A.ntype; ++ta) {
         std::vector<uint32_t> kmask(B.ntype, 0), rmask(B.ntype, 0);
         for (int u2 = 0; u2 < B.ntype; ++u2) {
@@ -566,15 +618,9 @@ int build_gas_owner(cisigma_ctx *c) {
             }
         }
         for (size_t t = 0; t < tu.size(); ++t)
-            if (kmask[tu[t]] && rmask[tu[t]]) {
-                act.push_back(uint32_t(t));
-                act.push_back(kmask[tu[t]]);
-                act.push_back(rmask[tu[t]]);
-                act.push_back(uint32_t(tu[t]) | (uint32_t(tc[t]) << 8));
-            }
-        astart.push_back(int(act.size() / 4));
+            if (kmask[tu[t]] && rmask[tu[t]])
+                tact[ta].push_back({uint32_t(t), kmask[tu[t]], rmask[tu[t]], uint32_t(tu[t]) | (uint32_t(tc[t]) << 8)});
     }
-    if (act.empty()) act.assign(4, 0u);
     // (ij|kl) with kl in the grouped row order
     std::vector<double> g64(size_t(n) * n * mp, 0.0);
     std::vector<float> g32(g64.size(), 0.0f);
@@ -584,28 +630,132 @@ int build_gas_owner(cisigma_ctx *c) {
             g64[size_t(ij) * mp + r] = v;
             g32[size_t(ij) * mp + r] = float(v);
         }
-    PlanSpec ps;
-    ps.ntile = int(tu.size());
-    ps.source = [&](int t, int col) {
-        const int cc = tc[t] + col;
-        return cc < B.tcount[tu[t]] ? B.tstart[tu[t]] + cc : -1;
-    };
-    ps.w_row = [&](int k, int l) { return row_of[cis::pair_ge(k, l)]; };
-    ps.nvirt = B.nstr;
-    ps.unit[0] = 8;
-    ps.unit[1] = 4;
-    ps.width = [=](int need) { return cis::sigma_ab_gas_width(ks, rb, need); };
-    int rc = make_scatter_plan(c, ps, G.plan);
-    if (rc || G.plan.ew == 0) return rc;
-    HIP_OR_FAIL(c, upload(&G.d_tile_u, tu), "init: GAS owner tables");
-    HIP_OR_FAIL(c, upload(&G.d_tile_c0, tc), "init: GAS owner tables");
+    std::vector<uint32_t> exc, str;
+    int rc = plan_tables(c, exc, str);
+    if (rc) return rc;
+    // per precision: units (alpha type x compact column range that fits the LDS),
+    // their plans (targets outside the range dropped) and tile lists without
+    // the tiles that reach no column of the range
+    const int ntb = B.ntype;
+    for (int d = 0; d < 2; ++d) {
+        const size_t es = d == 0 ? 8 : 4;
+        const size_t fixed = (size_t(16) * rb * WS + 64) * es + size_t(4) * kp * ntb;
+        if (fixed >= 160 * 1024) continue;
+        const int cmax = int(std::min<size_t>((160 * 1024 - fixed) / es, 65536 - 64 - 1));
+        std::vector<cis::GasUnit> units;
+        std::vector<PlanSpec> specs;
+        std::vector<PlanTiles> pts;
+        std::vector<std::vector<std::array<uint32_t, 4>>> uact;
+        int need = 1;
+        for (int ta = 0; ta < A.ntype; ++ta) {
+            if (tact[ta].empty() || A.tcount[ta] == 0) continue;
+            for (int lo = 0; lo < ncols[ta]; lo += cmax) {
+                const int hi = std::min(ncols[ta], lo + cmax);
+                const auto &ta_tiles = tact[ta];
+                PlanSpec ps;
+                ps.ntile = int(ta_tiles.size());
+                ps.source = [&, ta](int t, int col) {
+                    const int u = int(ta_tiles[t][3] & 255u), cc = int(ta_tiles[t][3] >> 8) + col;
+                    return cc < B.tcount[u] ? B.tstart[u] + cc : -1;
+                };
+                ps.w_row = [&](int k, int l) { return row_of[cis::pair_ge(k, l)]; };
+                ps.target = [&, ta, lo, hi](int Ib) {
+                    const int u = btype[Ib], o = coff[size_t(ta) * ntb + u];
+                    if (o < 0) return -1;
+                    const int x = o + (Ib - B.tstart[u]);
+                    return x >= lo && x < hi ? x - lo : -1;
+                };
+                ps.nvirt = hi - lo;
+                ps.unit[0] = 8;
+                ps.unit[1] = 4;
+                PlanTiles pt;
+                rc = plan_items(c, ps, exc, str, pt);
+                if (rc) return rc;
+                // keep the tiles with at least one target in the range
+                std::vector<std::array<uint32_t, 4>> keep;
+                PlanTiles kept;
+                for (size_t t = 0; t < pt.tiles.size(); ++t)
+                    if (!pt.tiles[t].empty()) {
+                        keep.push_back(ta_tiles[t]);
+                        kept.tiles.push_back(std::move(pt.tiles[t]));
+                    }
+                if (keep.empty()) continue;
+                need = std::max(need, pt.need);
+                cis::GasUnit gu;
+                gu.ta = ta;
+                gu.lo = lo;
+                gu.hi = hi;
+                units.push_back(gu);
+                specs.push_back(ps);
+                pts.push_back(std::move(kept));
+                uact.push_back(std::move(keep));
+            }
+        }
+        if (units.empty()) continue;
+        // longest rows of work first (one launch covers every unit; the longest workgroups start first)
+        {
+            std::vector<size_t> ord(units.size());
+            for (size_t k = 0; k < ord.size(); ++k) ord[k] = k;
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return uact[x].size() > uact[y].size(); });
+            std::vector<cis::GasUnit> u2;
+            std::vector<PlanSpec> s2;
+            std::vector<PlanTiles> p2;
+            std::vector<std::vector<std::array<uint32_t, 4>>> a2;
+            for (size_t k : ord) {
+                u2.push_back(units[k]);
+                s2.push_back(specs[k]);
+                p2.push_back(std::move(pts[k]));
+                a2.push_back(std::move(uact[k]));
+            }
+            units.swap(u2);
+            specs.swap(s2);
+            pts.swap(p2);
+            uact.swap(a2);
+        }
+        int ew = 0;
+        for (int cand : {cis::sigma_ab_gas_width(ks, rb, need), 16}) {
+            if (cand < need || cis::sigma_ab_gas_width(ks, rb, cand) != cand) continue;
+            bool ok = true;
+            for (size_t k = 0; k < pts.size() && ok; ++k) ok = plan_fits(pts[k], cand);
+            if (ok) { ew = cand; break; }
+        }
+        if (ew == 0) continue;
+        std::vector<uint32_t> plan[2], act;
+        int tile0 = 0;
+        for (size_t k = 0; k < units.size(); ++k) {
+            plan_emit(specs[k], pts[k], ew, plan);
+            units[k].act0 = int(act.size() / 4);
+            units[k].nact = int(uact[k].size());
+            for (size_t t = 0; t < uact[k].size(); ++t) {
+                act.push_back(uint32_t(tile0 + int(t)));
+                act.push_back(uact[k][t][1]);
+                act.push_back(uact[k][t][2]);
+                act.push_back(uact[k][t][3]);
+            }
+            tile0 += int(uact[k].size());
+        }
+        if (size_t(tile0) * 4 * (ew + 1) * 64 * 4 >= (size_t(1) << 31)) continue;
+        std::vector<int> utab;
+        int nblk = 0, maxc = 0;
+        for (const auto &un : units) {
+            utab.insert(utab.end(), {un.ta, un.lo, un.hi, un.act0, un.nact, A.tstart[un.ta], nblk, 0});
+            nblk += A.tcount[un.ta];
+            maxc = std::max(maxc, un.hi - un.lo);
+        }
+        HIP_OR_FAIL(c, upload(&G.plan[d].d_entries[d], plan[d]), "init: GAS owner tables");
+        HIP_OR_FAIL(c, upload(&G.d_act[d], act), "init: GAS owner tables");
+        HIP_OR_FAIL(c, upload(&G.d_units[d], utab), "init: GAS owner tables");
+        G.nblocks[d] = nblk;
+        G.maxcols[d] = maxc;
+        G.plan[d].ntile = tile0;
+        G.plan[d].ew = ew;
+        G.units[d] = std::move(units);
+    }
+    if (G.units[0].empty() && G.units[1].empty()) return CISIGMA_OK;
     HIP_OR_FAIL(c, upload(&G.d_slot, slot), "init: GAS owner tables");
-    HIP_OR_FAIL(c, upload(&G.d_act, act), "init: GAS owner tables");
-    HIP_OR_FAIL(c, upload(&G.d_act_start, astart), "init: GAS owner tables");
+    HIP_OR_FAIL(c, upload(&G.d_coff, coff), "init: GAS owner tables");
     HIP_OR_FAIL(c, upload(&G.d_g64, g64), "init: GAS owner tables");
     HIP_OR_FAIL(c, upload(&G.d_g32, g32), "init: GAS owner tables");
-    G.nsrc = int(tu.size());
-    G.nvirt = B.nstr;
     G.ks = ks;
     G.rb = rb;
     return CISIGMA_OK;

@@ -130,20 +130,31 @@ struct ScatterPlan {
 // are its single excitations grouped by source type, and every alpha type has
 // the list of 32-column source tiles (of one beta type each) that can change
 // its sigma, with the k steps and row blocks that can.
+// Owner-computes sigma_3 on GAS spaces.  The sigma row of an alpha string
+// holds only the beta strings of the blocks allowed with its type (the types
+// concatenated: compact columns); a "unit" is one alpha type and a range of
+// its compact columns short enough for the LDS of the precision (units differ
+// per precision), with its own list of source tiles and its own scatter plan.
+struct GasUnit {
+    int ta = 0;                          // alpha type
+    int lo = 0, hi = 0;                  // compact column range owned
+    int act0 = 0, nact = 0;              // its source tiles in the act array
+};
 struct GasOwner {
     int ks = 0, rb = 0;                  // k steps (4 gathered rows each), 16-row blocks of W
-    int nsrc = 0;                        // source tiles over all beta types
-    int *d_tile_u = nullptr;             // [nsrc] beta type of each source tile
-    int *d_tile_c0 = nullptr;            // [nsrc] first column inside that type
     int *d_slot = nullptr;               // [ntype_a][4*ks] excitation index of each gathered row,
                                          //   -2: the string itself, -1: none
-    uint32_t *d_act = nullptr;           // [.][4] per alpha type: {tile, k-step mask, row-block mask,
-                                         //   beta type | first column << 8}
-    int *d_act_start = nullptr;          // [ntype_a + 1]
+    int *d_coff = nullptr;               // [ntype_a][ntype_b] first compact column of each allowed block, -1
     float *d_g32 = nullptr;              // [n*n][16*rb] (ij|kl), kl in the grouped row order
     double *d_g64 = nullptr;
-    ScatterPlan plan;                    // beta-side plan over the source tiles (slots: elements)
-    int nvirt = 0;                       // beta strings (length of the LDS sigma row)
+    // per precision ([0] FP64, [1] FP32)
+    std::vector<GasUnit> units[2];
+    uint32_t *d_act[2] = {nullptr, nullptr};   // [.][4]: {plan tile, k-step mask, row-block mask,
+                                               //   beta type | first column << 8}
+    int *d_units[2] = {nullptr, nullptr};      // [.][8]: ta, lo, hi, act0, nact, first alpha string, first block
+    int nblocks[2] = {0, 0};                   // workgroups of one launch over all units
+    int maxcols[2] = {0, 0};                   // longest unit row
+    ScatterPlan plan[2];                 // plan[d].d_entries[d]: tiles of all units (slots: elements)
 };
 
 struct Workspace {

@@ -401,15 +401,17 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
 
 // ---- GAS spaces: owner-computes with per-type source tiles ---------------------
 //
-// One workgroup per output alpha string Ia of type ta; four waves as in the
-// FP64 one-block form.  The LDS sigma row spans all beta strings (only the
-// blocks of ta are read and written back; other slots take the contributions
-// that land outside the space).  For each active source tile (32 columns of
-// one beta type u2) the gathered rows are the single excitations of Ia grouped
-// by source type, each read from its block with u2 (or the zero row); only the
-// k steps whose rows have a block with u2 and the W row blocks whose pairs lead
-// into a block of ta are multiplied.  W rows of skipped blocks are stale and
-// reach only slots outside the space.
+// Units: an alpha type ta and a range [lo, hi) of its compact columns (the
+// beta strings of the blocks allowed with ta, concatenated).  One launch covers
+// all units, one workgroup per (unit, alpha string of its type), four waves as
+// in the FP64 one-block form.
+// The LDS sigma row holds the unit's columns; the unit's plan drops every
+// contribution that lands outside them.  For each source tile of the unit (32
+// columns of one beta type u2) the gathered rows are the single excitations of
+// Ia grouped by source type, each read from its block with u2 (or the zero
+// row); only the k steps whose rows have a block with u2 and the W row blocks
+// whose pairs lead into a block of ta are multiplied.  W rows of skipped
+// blocks are stale and no plan entry reads them.
 template <typename T>
 struct AbgArgs {
     const T *cp;                 // C, alpha-major padded GAS layout, zero row at zero_off
@@ -421,12 +423,13 @@ struct AbgArgs {
     const int *bstart;           // [ntb + 1] first beta string of each type
     const T *g;                  // [n*n][mp] (ij|kl), kl in the grouped row order
     const int *slot;             // [nta][4*ks] excitation index of each gathered row (-2: Ia, -1: none)
-    const uint4 *act;            // {tile, k-step mask, row-block mask, beta type | first column << 8}
-    const int *act_start;        // [nta + 1]
-    const int *tile_u, *tile_c0;
+    const uint4 *act;            // tiles of all units: {plan tile, k-step mask, row-block mask, beta type | first column << 8}
+    const int *coff;             // [nta][ntb] first compact column of each allowed block (-1: not allowed)
+    const int *units;            // [nunits][8]: ta, lo, hi, act0, nact, first alpha string, first workgroup
     const uint32_t *plan;
     uint32_t cp_bytes, plan_bytes, zero_off;
-    int anexc, n, npair, mp, ntb, nvirt;
+    int anexc, n, npair, mp, ntb, nunits;
+    int nvirt;                   // the longest unit row (LDS layout)
 };
 
 template <typename T, int KS, int RB, int EW>
@@ -444,18 +447,25 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     T *sig = W + MP * kAbxWS;                              // [nvirt + 64]
     uint32_t *rowoff = reinterpret_cast<uint32_t *>(sig + p.nvirt + 64);   // [ntb][KP] byte offsets
 
-    const int Ia = blockIdx.x;
+    int ui = 0;                                            // this workgroup's unit (uniform)
+    while (ui + 1 < p.nunits && int(blockIdx.x) >= p.units[8 * (ui + 1) + 6]) ++ui;
+    const int *U = p.units + 8 * ui;
+    const int ulo = U[1], uhi = U[2], ncol = uhi - ulo;
+    const int Ia = U[5] + (int(blockIdx.x) - U[6]);
     const int ta = p.atype[Ia], ra = Ia - p.astart[ta];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cb = wave & 1, grp = wave >> 1;
     const int rb0 = grp == 0 ? 0 : RBW, nrb = grp == 0 ? RBW : RB - RBW;
     const int64_t *segrow = p.seg + int64_t(ta) * p.ntb;
+    const int *coff = p.coff + int64_t(ta) * p.ntb;
+    // the unit's compact columns [lo, hi): the parts of the allowed blocks of ta inside them
     for (int u = 0; u < p.ntb; ++u) {
-        const int64_t s = segrow[u];
-        if (s < 0) continue;
-        const T *src = p.sp + s + int64_t(ra) * p.ld[u];
-        const int b0 = p.bstart[u], cnt = p.bstart[u + 1] - b0;
-        for (int i = tid; i < cnt; i += 256) sig[b0 + i] = src[i];
+        const int o = coff[u];
+        if (o < 0) continue;
+        const int cnt = p.bstart[u + 1] - p.bstart[u];
+        const int x0 = o > ulo ? o : ulo, x1 = o + cnt < uhi ? o + cnt : uhi;
+        const T *src = p.sp + segrow[u] + int64_t(ra) * p.ld[u] - o;
+        for (int x = x0 + tid; x < x1; x += 256) sig[x - ulo] = src[x];
     }
     const int *sl = p.slot + int64_t(ta) * KP;
     for (int idx = tid; idx < KP * p.ntb; idx += 256) {
@@ -511,13 +521,13 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     }
     __syncthreads();
 
-    const int a0 = p.act_start[ta], nact = p.act_start[ta + 1] - a0;
+    const int nact = U[4];
     if (nact > 0) {
         const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes), pr = buffer_of(p.plan, p.plan_bytes);
         const uint32_t colb = uint32_t(cb * 16 + (lane & 15)) * uint32_t(sizeof(T));
         const uint32_t pl = uint32_t(wave * PW + lane) * 4u;
-        const uint32_t spare = uint32_t(p.nvirt + lane) * uint32_t(sizeof(T));
-        const uint4 *act = p.act + a0;
+        const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
+        const uint4 *act = p.act + U[3];
         T bc[KS], bn[KS];
         acc_t acc[RBW], acc2[RBW];
         // k steps in four chunks; a chunk is multiplied when one of its k steps is active
@@ -593,11 +603,12 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         }
     }
     for (int u = 0; u < p.ntb; ++u) {
-        const int64_t s = segrow[u];
-        if (s < 0) continue;
-        T *dst = p.sp + s + int64_t(ra) * p.ld[u];
-        const int b0 = p.bstart[u], cnt = p.bstart[u + 1] - b0;
-        for (int i = tid; i < cnt; i += 256) dst[i] = sig[b0 + i];
+        const int o = coff[u];
+        if (o < 0) continue;
+        const int cnt = p.bstart[u + 1] - p.bstart[u];
+        const int x0 = o > ulo ? o : ulo, x1 = o + cnt < uhi ? o + cnt : uhi;
+        T *dst = p.sp + segrow[u] + int64_t(ra) * p.ld[u] - o;
+        for (int x = x0 + tid; x < x1; x += 256) dst[x] = sig[x - ulo];
     }
 }
 
@@ -632,16 +643,21 @@ int gas_width_for(int ks, int rb, int need) {
 template <typename T>
 bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipError_t *err) {
     const GasOwner &G = ctx->go;
-    const uint32_t *plan = G.plan.d_entries[sizeof(T) == 4 ? 1 : 0];
-    if (G.ks == 0 || !plan || G.plan.ew == 0) return false;
+    const int d = sizeof(T) == 4 ? 1 : 0;
+    const uint32_t *plan = G.plan[d].d_entries[d];
+    if (G.ks == 0 || !plan || G.plan[d].ew == 0 || G.units[d].empty()) return false;
     const auto &A = ctx->sp[0];
     const auto &L = ctx->pl[0];
-    if (abg_lds<T>(G.nvirt, G.rb, G.ks, ctx->sp[1].ntype) > 160 * 1024) return false;
     int64_t ldmax = 0;
     for (int v : L.ld) ldmax = std::max<int64_t>(ldmax, v);
     const uint64_t cpb = (uint64_t(L.size) + uint64_t(ldmax)) * sizeof(T);
-    const uint64_t plb = uint64_t(G.plan.ntile) * 4 * (G.plan.ew + 1) * 64 * sizeof(uint32_t);
+    const uint64_t plb = uint64_t(G.plan[d].ntile) * 4 * (G.plan[d].ew + 1) * 64 * sizeof(uint32_t);
     if (cpb >= (uint64_t(1) << 31) || plb >= (uint64_t(1) << 31)) return false;
+    bool shape = false;
+#define CIS_HAS(K, R, E) shape = shape || (G.ks == K && G.rb == R && G.plan[d].ew == E);
+    CIS_ABG_SHAPES(CIS_HAS)
+#undef CIS_HAS
+    if (!shape) return false;
     AbgArgs<T> a{};
     a.cp = static_cast<const T *>(cp);
     a.sp = static_cast<T *>(sp);
@@ -654,10 +670,7 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.bstart = ctx->d_tstart[1];
     a.g = std::is_same<T, float>::value ? reinterpret_cast<const T *>(G.d_g32) : reinterpret_cast<const T *>(G.d_g64);
     a.slot = G.d_slot;
-    a.act = reinterpret_cast<const uint4 *>(G.d_act);
-    a.act_start = G.d_act_start;
-    a.tile_u = G.d_tile_u;
-    a.tile_c0 = G.d_tile_c0;
+    a.coff = G.d_coff;
     a.plan = plan;
     a.cp_bytes = uint32_t(cpb);
     a.plan_bytes = uint32_t(plb);
@@ -667,12 +680,15 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.npair = ctx->npair;
     a.mp = 16 * G.rb;
     a.ntb = ctx->sp[1].ntype;
-    a.nvirt = G.nvirt;
+    a.act = reinterpret_cast<const uint4 *>(G.d_act[d]);
+    a.units = G.d_units[d];
+    a.nunits = int(G.units[d].size());
+    a.nvirt = G.maxcols[d];
 #define CIS_RUN(K, R, E) \
-    if (G.ks == K && G.rb == R && G.plan.ew == E) { *err = run_abg<T, K, R, E>(a, A.nstr, s); return true; }
+    if (G.ks == K && G.rb == R && G.plan[d].ew == E) *err = run_abg<T, K, R, E>(a, G.nblocks[d], s);
     CIS_ABG_SHAPES(CIS_RUN)
 #undef CIS_RUN
-    return false;
+    return true;
 }
 
 // LDS bytes: the W tile (two for the eight-wave FP32 form) and the sigma row

@@ -116,9 +116,8 @@ def test_gas20_sampled_rows(dtype):
     S = torch.empty_like(C)
     ctx.apply(C, S)
     torch.cuda.synchronize()
-    # FP32: the owner-computes GAS kernel; FP64: its LDS sigma row does not fit, the general kernel
-    assert ctx.last_path(_cis().FP32 if dtype == torch.float32 else _cis().FP64) == \
-        (_cis().PATH_AB_OWNER if dtype == torch.float32 else 0)
+    # the owner-computes GAS kernel in both precisions (FP64: long sigma rows split over several units)
+    assert ctx.last_path(_cis().FP32 if dtype == torch.float32 else _cis().FP64) == _cis().PATH_AB_OWNER
     got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
     want = ref.sigma_rows(rows, c)
     err = np.linalg.norm(got - want) / np.linalg.norm(want)
