@@ -122,11 +122,12 @@ def stored_traffic(kernel_tag):
     summary, or None when the kernel source changed after the counters were
     taken (the summary records the source's SHA-256)."""
     import hashlib
-    src = os.path.join(ROOT, "paper_1707_04346_amd", "csrc", "sigma_abx.hip" if kernel_tag == "k_sigma_ab_ws" else "sigma_ab.hip")
+    csrc = os.path.join(ROOT, "paper_1707_04346_amd", "csrc")
+    srcs = [os.path.join(csrc, f) for f in (("sigma_abx.hip", "abx.h") if kernel_tag == "k_sigma_ab_ws" else ("sigma_ab.hip",))]
     prof = os.path.join(ROOT, "profiles", f"{kernel_tag}_cas16_fp32_traffic.txt")
-    if not (os.path.exists(src) and os.path.exists(prof)):
+    if not (all(os.path.exists(f) for f in srcs) and os.path.exists(prof)):
         return None
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    sha = hashlib.sha256(b"".join(open(f, "rb").read() for f in srcs)).hexdigest()
     fields = {}
     for ln in open(prof):
         if ":" in ln:

@@ -537,7 +537,9 @@ int build_gas_owner(cisigma_ctx *c) {
     auto &G = c->go;
     const auto &A = c->sp[0], &B = c->sp[1];
     const int n = c->n, ng = c->gas.ngas;
-    if (c->cas || c->na == 0 || c->nb == 0 || A.nexc == 0 || B.nexc == 0) return CISIGMA_OK;
+    // one-block spaces come here only when the one-block owner kernel has no plan
+    // (more than 16 orbitals, or a sigma row longer than its LDS)
+    if ((c->cas && c->plan.ew > 0) || c->na == 0 || c->nb == 0 || A.nexc == 0 || B.nexc == 0) return CISIGMA_OK;
     const int rb = (c->npair + 15) / 16, mp = 16 * rb;
     const int ks = (A.nexc + 1 + 3) / 4, kp = 4 * ks;
     if (ks > 32 || rb > 32 || B.ntype > 255 || size_t(mp) * WS * 8 >= 65536) return CISIGMA_OK;
@@ -637,8 +639,12 @@ int build_gas_owner(cisigma_ctx *c) {
     // their plans (targets outside the range dropped) and tile lists without
     // the tiles that reach no column of the range
     const int ntb = B.ntype;
+    int64_t ldmax = 0;
+    for (int v : c->pl[0].ld) ldmax = std::max<int64_t>(ldmax, v);
     for (int d = 0; d < 2; ++d) {
         const size_t es = d == 0 ? 8 : 4;
+        // the kernel addresses C with 32-bit byte offsets (its zero row included)
+        if ((uint64_t(c->pl[0].size) + uint64_t(ldmax)) * es >= (uint64_t(1) << 31)) continue;
         const size_t fixed = (size_t(16) * rb * WS + 64) * es + size_t(4) * kp * ntb;
         if (fixed >= 160 * 1024) continue;
         const int cmax = int(std::min<size_t>((160 * 1024 - fixed) / es, 65536 - 64 - 1));
@@ -692,6 +698,15 @@ int build_gas_owner(cisigma_ctx *c) {
             }
         }
         if (units.empty()) continue;
+        // splitting rows repeats the products of every tile that reaches several
+        // units: give the precision to the general kernel when that more than
+        // doubles them
+        {
+            double split = 0, whole = 0;
+            for (size_t k = 0; k < units.size(); ++k) split += double(uact[k].size()) * A.tcount[units[k].ta];
+            for (int ta = 0; ta < A.ntype; ++ta) whole += double(tact[ta].size()) * A.tcount[ta];
+            if (split > 2.0 * whole) continue;
+        }
         // longest rows of work first (one launch covers every unit; the longest workgroups start first)
         {
             std::vector<size_t> ord(units.size());
