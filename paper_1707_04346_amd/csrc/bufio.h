@@ -37,5 +37,12 @@ __device__ __forceinline__ void buffer_st(const bf_floatx4 &x, __amdgpu_buffer_r
 __device__ __forceinline__ void buffer_st(const bf_double2 &x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, int(voff), int(soff), 0);
 }
+// streaming stores (non-temporal hint: data read once, much later)
+__device__ __forceinline__ void buffer_st_nt(const bf_floatx4 &x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, int(voff), int(soff), 2);
+}
+__device__ __forceinline__ void buffer_st_nt(const bf_double2 &x, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, int(voff), int(soff), 2);
+}
 
 }  // namespace cis

@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256, 2) void k_sigma_ss_y(SsyArgs<T> p) {
                 vec_t o;
 #pragma unroll
                 for (int v = 0; v < VEC; ++v) o[v] = acc[rb][v][i];
-                buffer_st(o, yr, yoff[rb][i], soff);
+                buffer_st_nt(o, yr, yoff[rb][i], soff);   // each row of Y is read once, by the gather
             }
     };
     if (wave >= nitems) return;
@@ -315,9 +315,20 @@ __global__ __launch_bounds__(256) void k_pair_gather(const T *__restrict__ Ys, i
     for (int q = threadIdx.x; q < per; q += blockDim.x) rows[q] = inv[int64_t(I) * per + q];
     __syncthreads();
     for (int c = col_begin + int(threadIdx.x) * VEC; c < col_end; c += int(blockDim.x) * VEC) {
-        vec_t acc = vec_t{};
-        for (int q = 0; q < per; ++q) acc += *reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q]) * ldy + (c - col_begin));
-        *reinterpret_cast<vec_t *>(out + int64_t(I) * ld + c) = acc;
+        // every row of Y is read once (streaming loads); four rows in flight per step
+        vec_t acc = vec_t{}, acc2 = vec_t{};
+        int q = 0;
+        for (; q + 4 <= per; q += 4) {
+            const vec_t a0 = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q]) * ldy + (c - col_begin)));
+            const vec_t a1 = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q + 1]) * ldy + (c - col_begin)));
+            const vec_t a2 = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q + 2]) * ldy + (c - col_begin)));
+            const vec_t a3 = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q + 3]) * ldy + (c - col_begin)));
+            acc += a0 + a1;
+            acc2 += a2 + a3;
+        }
+        for (; q < per; ++q)
+            acc += __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + int64_t(rows[q]) * ldy + (c - col_begin)));
+        *reinterpret_cast<vec_t *>(out + int64_t(I) * ld + c) = acc + acc2;
     }
 }
 
