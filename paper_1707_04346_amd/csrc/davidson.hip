@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void k_dots(const TX *X, int64_t sx, int nx, c
 template <typename TX, typename TY>
 __global__ __launch_bounds__(256) void k_dots_multi(const TX *X, int64_t sx, int nx, const TY *Y, int64_t sy, int ny,
                                                     int64_t N, double *partial) {
-    constexpr int GX = 4;
+    constexpr int GX = 8;                                  // X vectors per pass over Y
     __shared__ double sh[4][GX * kMultiY];
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -134,6 +134,7 @@ __global__ __launch_bounds__(256) void k_subtract_multi(const T *X, int64_t sx, 
         double v[kMultiY];
 #pragma unroll
         for (int j = 0; j < kMultiY; ++j) v[j] = j < ny ? double(Tv[j * st + n]) : 0.0;
+#pragma unroll 8
         for (int i = 0; i < nx; ++i) {
             const double xv = double(X[i * sx + n]);
 #pragma unroll
@@ -145,12 +146,14 @@ __global__ __launch_bounds__(256) void k_subtract_multi(const T *X, int64_t sx, 
     }
 }
 
-__global__ void k_reduce_partials(const double *partial, int nb, int nx, double *out) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+// out[i] = sum over the nb blocks of partial[b][i]: one wave per output
+__global__ __launch_bounds__(64) void k_reduce_partials(const double *partial, int nb, int nx, double *out) {
+    const int i = blockIdx.x;
     if (i >= nx) return;
     double s = 0;
-    for (int b = 0; b < nb; ++b) s += partial[int64_t(b) * nx + i];
-    out[i] = s;
+    for (int b = int(threadIdx.x); b < nb; b += 64) s += partial[int64_t(b) * nx + i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) out[i] = s;
 }
 
 // Ritz vectors, their sigma, residual-norm partials and preconditioned
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
         double x[R], s[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) x[r] = s[r] = 0;
+#pragma unroll 4
         for (int i = 0; i < m; ++i) {
             const double b = double(B[i * sv + n]), c = double(S[i * sv + n]);
 #pragma unroll
@@ -362,7 +366,7 @@ template <typename TX, typename TY>
 hipError_t dots(Dev &d, const TX *X, int64_t sx, int nx, const TY *y, int64_t N, double *host_out) {
     int g = d.grid(N);
     hipLaunchKernelGGL((k_dots<TX, TY>), dim3(g), dim3(256), 0, d.s, X, sx, nx, y, N, d.partial);
-    hipLaunchKernelGGL(k_reduce_partials, dim3((nx + 63) / 64), dim3(64), 0, d.s, d.partial, g, nx, d.dvec);
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nx), dim3(64), 0, d.s, d.partial, g, nx, d.dvec);
     hipError_t e = hipMemcpyAsync(host_out, d.dvec, size_t(nx) * sizeof(double), hipMemcpyDeviceToHost, d.s);
     if (e != hipSuccess) return e;
     return hipStreamSynchronize(d.s);
@@ -378,7 +382,7 @@ hipError_t dots_multi(Dev &d, const TX *X, int64_t sx, int nx, const TY *Y, int6
         const int nyc = std::min(kMultiY, ny - j0);
         hipLaunchKernelGGL((k_dots_multi<TX, TY>), dim3(g), dim3(256), 0, d.s, X, sx, nx, Y + int64_t(j0) * sy, sy,
                            nyc, N, d.partial);
-        hipLaunchKernelGGL(k_reduce_partials, dim3((nx * nyc + 63) / 64), dim3(64), 0, d.s, d.partial, g, nx * nyc,
+        hipLaunchKernelGGL(k_reduce_partials, dim3(nx * nyc), dim3(64), 0, d.s, d.partial, g, nx * nyc,
                            d.dvec);
         hipError_t e = hipMemcpyAsync(host_out + size_t(j0) * nx, d.dvec, size_t(nx) * nyc * sizeof(double),
                                       hipMemcpyDeviceToHost, d.s);
