@@ -92,30 +92,32 @@ void free_ctx(cisigma_ctx *c) {
     if (!c) return;
     for (int s = 0; s < 2; ++s) {
         auto &T = c->sp[s];
-        hipFree(T.d_str); hipFree(T.d_stype); hipFree(T.d_exc); hipFree(T.d_pairs);
-        hipFree(T.d_tkey); hipFree(T.d_tstart); hipFree(T.d_radix); hipFree(T.d_adiag); hipFree(T.d_pair_inv);
+        (void)hipFree(T.d_str); (void)hipFree(T.d_stype); (void)hipFree(T.d_exc); (void)hipFree(T.d_pairs);
+        (void)hipFree(T.d_tkey); (void)hipFree(T.d_tstart); (void)hipFree(T.d_radix); (void)hipFree(T.d_adiag);
+        (void)hipFree(T.d_pair_inv);
         auto &L = c->pl[s];
-        hipFree(L.d_seg); hipFree(L.d_ld); hipFree(L.d_tile_u); hipFree(L.d_tile_c0);
-        hipFree(c->d_tstart[s]);
-        hipFree(c->d_v64[s]); hipFree(c->d_v32[s]);
+        (void)hipFree(L.d_seg); (void)hipFree(L.d_ld); (void)hipFree(L.d_tile_u); (void)hipFree(L.d_tile_c0);
+        (void)hipFree(c->d_tstart[s]);
+        (void)hipFree(c->d_v64[s]); (void)hipFree(c->d_v32[s]);
         auto &W = c->ws[s];
-        hipFree(W.cp); hipFree(W.sp); hipFree(W.ct); hipFree(W.st); hipFree(W.ys);
+        (void)hipFree(W.cp); (void)hipFree(W.sp); (void)hipFree(W.ct); (void)hipFree(W.st); (void)hipFree(W.ys);
     }
-    hipFree(c->d_rdm);
+    (void)hipFree(c->d_rdm);
     cis::drop_graphs(c);
-    hipFree(c->d_gp64); hipFree(c->d_gp32); hipFree(c->d_h64); hipFree(c->d_h32); hipFree(c->d_jpq);
-    hipFree(c->bt.blk); hipFree(c->bt.tb); hipFree(c->bt.tr); hipFree(c->bt.tc);
-    hipFree(c->plan.d_entries[0]); hipFree(c->plan.d_entries[1]);
-    hipFree(c->d_act_start); hipFree(c->d_act_tiles);
-    hipFree(c->go.d_slot); hipFree(c->go.d_coff); hipFree(c->go.d_g32); hipFree(c->go.d_g64);
+    (void)hipFree(c->d_gp64); (void)hipFree(c->d_gp32); (void)hipFree(c->d_h64); (void)hipFree(c->d_h32);
+    (void)hipFree(c->d_jpq);
+    (void)hipFree(c->bt.blk); (void)hipFree(c->bt.tb); (void)hipFree(c->bt.tr); (void)hipFree(c->bt.tc);
+    (void)hipFree(c->plan.d_entries[0]); (void)hipFree(c->plan.d_entries[1]);
+    (void)hipFree(c->d_act_start); (void)hipFree(c->d_act_tiles);
+    (void)hipFree(c->go.d_slot); (void)hipFree(c->go.d_coff); (void)hipFree(c->go.d_g32); (void)hipFree(c->go.d_g64);
     for (int d = 0; d < 2; ++d) {
-        hipFree(c->go.d_act[d]);
-        hipFree(c->go.d_units[d]);
-        hipFree(c->go.plan[d].d_entries[0]);
-        hipFree(c->go.plan[d].d_entries[1]);
+        (void)hipFree(c->go.d_act[d]);
+        (void)hipFree(c->go.d_units[d]);
+        (void)hipFree(c->go.plan[d].d_entries[0]);
+        (void)hipFree(c->go.plan[d].d_entries[1]);
     }
-    for (auto e : c->prof_events) hipEventDestroy(e);
-    if (c->stream) hipStreamDestroy(c->stream);
+    for (auto e : c->prof_events) (void)hipEventDestroy(e);
+    if (c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
 
@@ -879,7 +881,7 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
 }
 
 void drop_graphs(cisigma_ctx *c) {
-    for (auto &g : c->graphs) hipGraphExecDestroy(g.exec);
+    for (auto &g : c->graphs) (void)hipGraphExecDestroy(g.exec);
     c->graphs.clear();
 }
 
@@ -901,16 +903,16 @@ int apply_sigma_graph(cisigma_ctx *c, const void *C, void *sigma, int dtype, hip
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(s, &graph);
     if (rc || e != hipSuccess || !graph) {
-        if (graph) hipGraphDestroy(graph);
+        if (graph) (void)hipGraphDestroy(graph);
         if (rc) return rc;
         return hip_fail(c, e != hipSuccess ? e : hipErrorUnknown, "apply: graph capture");
     }
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     HIP_OR_FAIL(c, e, "apply: graph instantiation");
     if (c->graphs.size() >= 16) {
-        hipGraphExecDestroy(c->graphs.front().exec);
+        (void)hipGraphExecDestroy(c->graphs.front().exec);
         c->graphs.erase(c->graphs.begin());
     }
     c->graphs.push_back({C, sigma, dtype, s, exec, path});
@@ -920,7 +922,7 @@ int apply_sigma_graph(cisigma_ctx *c, const void *C, void *sigma, int dtype, hip
 }  // namespace cis
 
 static void prof_reset(cisigma_ctx *c) {
-    for (auto e : c->prof_events) hipEventDestroy(e);
+    for (auto e : c->prof_events) (void)hipEventDestroy(e);
     c->prof_events.clear();
     c->prof_pending.clear();
     for (double &v : c->prof_ms) v = 0;
@@ -941,7 +943,7 @@ CIS_API int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls) {
         }
         ctx->prof_calls += 1;
     }
-    for (auto e : ctx->prof_events) hipEventDestroy(e);
+    for (auto e : ctx->prof_events) (void)hipEventDestroy(e);
     ctx->prof_events.clear();
     ctx->prof_pending.clear();
     for (int p = 0; p < CISIGMA_NPASS; ++p) ms[p] = ctx->prof_ms[p];
@@ -1270,7 +1272,7 @@ CIS_API int cisigma_rdm(cisigma_ctx *ctx, const void *C, int dtype, double *rdm1
     if (rc) return rc;
     const size_t need = cis::rdm_part_elems(ctx);
     if (ctx->rdm_elems < need) {
-        hipFree(ctx->d_rdm);
+        (void)hipFree(ctx->d_rdm);
         ctx->d_rdm = nullptr;
         ctx->rdm_elems = 0;
         HIP_OR_FAIL(ctx, hipMalloc(&ctx->d_rdm, need * sizeof(double)), "rdm: partial-sum buffer");

@@ -451,8 +451,9 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             return cis_set_error(ctx, CISIGMA_ENOMEM, "davidson: not enough device memory for the subspace");
     }
     auto cleanup = [&]() {
-        hipFree(B); hipFree(S); hipFree(SX); hipFree(TB); hipFree(X64); hipFree(hd); hipFree(sig64);
-        hipFree(d.partial); hipFree(d.dvec); hipFree(d.pidx); hipFree(d.ybuf);
+        (void)hipFree(B); (void)hipFree(S); (void)hipFree(SX); (void)hipFree(TB); (void)hipFree(X64);
+        (void)hipFree(hd); (void)hipFree(sig64);
+        (void)hipFree(d.partial); (void)hipFree(d.dvec); (void)hipFree(d.pidx); (void)hipFree(d.ybuf);
     };
     struct Guard { std::function<void()> f; ~Guard() { f(); } } guard{cleanup};
     DV_TRY(hipMalloc(&B, size_t(max_space) * N * es));
