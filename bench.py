@@ -171,6 +171,29 @@ def time_rdm(ctx, torch, n, na, nb, ndet):
     return out
 
 
+def stored_same_spin_bytes():
+    """HBM bytes of one same-spin pass (pair products + gather) from the committed
+    counter summary, or None when those kernels changed after the counters
+    were taken."""
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1707_04346_amd", "csrc")
+    prof = os.path.join(ROOT, "profiles", "k_sigma_ab_ws_cas16_fp32_traffic.txt")
+    if not os.path.exists(prof):
+        return None
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sigma_ss.hip", "bufio.h"))).hexdigest()
+    fields = {}
+    for ln in open(prof):
+        if ":" in ln:
+            k, v = ln.split(":", 1)
+            fields[k.strip()] = v.strip()
+    if fields.get("same_spin_source_sha256") != sha:
+        return None
+    try:
+        return float(fields["same_spin_hbm_bytes_per_pass"])
+    except (KeyError, ValueError):
+        return None
+
+
 def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector):
     out = {}
     ctx.set_option(cis.OPT_MAX_ITER, max_iter)
@@ -267,6 +290,13 @@ def main():
                            else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
                 "flops_per_launch": flops, "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
+    if args.workload == "cas16":
+        ssb = stored_same_spin_bytes()
+        if ssb is not None:
+            # HBM-bound passes: counted bytes over the pass time, against the 8 TB/s peak
+            rate = ssb / (pp32["sigma_aa"] / 1e3) / 1e9
+            extra["same_spin_pass_hbm"] = {"bytes_per_pass": ssb, "achieved_GBps": rate, "peak_GBps": HBM_PEAK,
+                                           "frac": rate / HBM_PEAK}
     if not args.no_fp64:
         extra["sigma_ab_tflops_fp64"] = flops / (pp64["sigma_ab"] / 1e3) / 1e12
 
