@@ -21,6 +21,7 @@ OPT_SIGMA_PATH = 8
 OPT_SS_CHUNK = 9
 OPT_SPIN_PARITY = 10
 OPT_GRAPH = 11
+OPT_OVERLAP = 12
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")

@@ -118,6 +118,9 @@ void free_ctx(cisigma_ctx *c) {
     }
     for (auto e : c->prof_events) (void)hipEventDestroy(e);
     if (c->stream) (void)hipStreamDestroy(c->stream);
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     delete c;
 }
 
@@ -818,6 +821,11 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
                 W.ys = nullptr;
         }
     }
+    if (!c->side) {
+        HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "apply: side stream");
+        HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "apply: side stream");
+        HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming), "apply: side stream");
+    }
     HIP_OR_FAIL(c, hipDeviceSynchronize(), "apply: workspace");
     W.ready = true;
     return CISIGMA_OK;
@@ -862,9 +870,23 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     HIP_OR_FAIL(c, launch_sigma_same_spin(c, 0, W.cp, par ? W.st : W.sp, dtype, s, mat ? W.ys : nullptr, chunk),
                 "apply: sigma_2 (alpha-alpha)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AA), "apply: profiling events");
+    // the beta-beta pass (memory-bound) overlaps the alpha-beta pass (matrix-core
+    // bound) on the side stream: they read different copies of C and write
+    // different accumulators; it reuses the materialised rows only after the
+    // alpha-alpha pass, which precedes the fork.  Profiling keeps the passes in order.
+    const bool fork = !par && c->overlap && !prof && c->side;
+    if (fork) {
+        HIP_OR_FAIL(c, hipEventRecord(c->ev_fork, s), "apply: fork");
+        HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "apply: fork");
+        HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, c->side, mat ? W.ys : nullptr, chunk),
+                    "apply: sigma_1 (beta-beta)");
+        HIP_OR_FAIL(c, hipEventRecord(c->ev_join, c->side), "apply: join");
+    }
     HIP_OR_FAIL(c, launch_sigma_ab(c, W.cp, W.sp, dtype, s), "apply: sigma_3 (alpha-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AB), "apply: profiling events");
-    if (!par)
+    if (fork)
+        HIP_OR_FAIL(c, hipStreamWaitEvent(s, c->ev_join, 0), "apply: join");
+    else if (!par)
         HIP_OR_FAIL(c, launch_sigma_same_spin(c, 1, W.ct, W.st, dtype, s, mat ? W.ys : nullptr, chunk),
                     "apply: sigma_1 (beta-beta)");
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_BB), "apply: profiling events");
@@ -1224,6 +1246,10 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_OVERLAP:
+            cis::drop_graphs(ctx);
+            ctx->overlap = value != 0;
             return CISIGMA_OK;
         case CISIGMA_OPT_GRAPH:
             cis::drop_graphs(ctx);

@@ -200,6 +200,11 @@ struct cisigma_ctx {
     int act_max = 0;
     cis::GasOwner go;              // owner-computes sigma_3 tables for GAS spaces (go.ks = 0: none)
     hipStream_t stream = nullptr;  // own stream for synchronous calls
+    // beta-beta pass of apply on a second stream, overlapping the alpha-beta pass
+    // (CISIGMA_OPT_OVERLAP); created with the workspace, default priority
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    int overlap = 1;
     // options
     int precision = CISIGMA_FP64;
     int max_space = 0;
