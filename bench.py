@@ -53,22 +53,17 @@ def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0, parity=0):
     for _ in range(warmup):
         ctx.apply(C, S)
     torch.cuda.synchronize()
+    ctx.set_option(cis.OPT_PROFILE, 1)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         ctx.apply(C, S)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # per-pass times from separate calls with HIP events around every pass (the
-    # passes then run in order on one stream)
-    ctx.set_option(cis.OPT_PROFILE, 1)
-    nprof = max(2, min(steps, 5))
-    for _ in range(nprof):
-        ctx.apply(C, S)
-    torch.cuda.synchronize()
     passes, ncalls = ctx.pass_times()
     ctx.set_option(cis.OPT_PROFILE, 0)
     ctx.set_option(cis.OPT_SPIN_PARITY, 0)
-    assert ncalls == nprof
+    assert ncalls == steps
     per_pass = {k: v / ncalls for k, v in passes.items()}
     return dt, per_pass, C, S
 

@@ -80,7 +80,9 @@ extern "C" {
 #define CISIGMA_OPT_OVERLAP 12     /* nonzero (default): cisigma_apply runs the beta-beta pass on a second
                                       stream of the context, overlapping the alpha-beta pass, and joins
                                       before the output gather (the call stays ordered on `stream`);
-                                      0: one stream.  Passes are always in order while profiling */
+                                      0: one stream.  With profiling on, the beta-beta entry of
+                                      cisigma_pass_times is then the wait for that stream after the
+                                      alpha-beta pass */
 #define CISIGMA_OPT_GRAPH 11       /* nonzero: cisigma_apply on a non-NULL stream runs its kernels eagerly
                                       at the first call with a given (C, sigma, dtype, stream) and captures
                                       them into a HIP graph that later calls with the same arguments replay

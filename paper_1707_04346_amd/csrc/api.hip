@@ -873,8 +873,10 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     // the beta-beta pass (memory-bound) overlaps the alpha-beta pass (matrix-core
     // bound) on the side stream: they read different copies of C and write
     // different accumulators; it reuses the materialised rows only after the
-    // alpha-alpha pass, which precedes the fork.  Profiling keeps the passes in order.
-    const bool fork = !par && c->overlap && !prof && c->side;
+    // alpha-alpha pass, which precedes the fork.  The events of the alpha-beta
+    // pass then time it while the other runs; the beta-beta "pass" time is the
+    // wait for it after that.
+    const bool fork = !par && c->overlap && c->side;
     if (fork) {
         HIP_OR_FAIL(c, hipEventRecord(c->ev_fork, s), "apply: fork");
         HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "apply: fork");
