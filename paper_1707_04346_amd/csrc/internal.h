@@ -204,7 +204,7 @@ struct cisigma_ctx {
     // (CISIGMA_OPT_OVERLAP); created with the workspace, default priority
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    int overlap = 1;
+    int overlap = 0;
     // options
     int precision = CISIGMA_FP64;
     int max_space = 0;
