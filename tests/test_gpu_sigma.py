@@ -172,6 +172,32 @@ def test_apply_on_a_side_stream():
     assert rel(S.cpu().numpy(), s_ref) <= TOL64
 
 
+@pytest.mark.parametrize("case", [(8, 4, 4), (9, 5, 4), (10, 5, 5)], ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_overlap_option_matches_oracle(case, dtype):
+    """CISIGMA_OPT_OVERLAP: the beta-beta pass on the context's second stream,
+    joined before the output gather; repeated calls on a caller stream, each
+    checked against the oracle, then the option switched off again."""
+    cis = _cis()
+    ctx, ref = make(*case, seed=4)
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    st = torch.cuda.Stream()
+    ctx.set_option(cis.OPT_OVERLAP, 1)
+    for k in range(3):
+        c = si.ci_vector(ctx.ndet, 20 + k)
+        C = torch.tensor(c, dtype=dtype, device="cuda")
+        S = torch.full_like(C, float("nan"))
+        torch.cuda.synchronize()
+        ctx.apply(C, S, stream=st)
+        st.synchronize()
+        assert rel(S.double().cpu().numpy(), ref.sigma(c)) <= tol, k
+    ctx.set_option(cis.OPT_OVERLAP, 0)
+    S2 = torch.empty_like(C)
+    ctx.apply(C, S2)
+    torch.cuda.synchronize()
+    assert rel(S2.double().cpu().numpy(), ref.sigma(c)) <= tol
+
+
 @pytest.mark.parametrize("case", [(6, 3, 3), (8, 4, 4), (9, 5, 4), (7, 2, 4), (10, 5, 5)],
                          ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
