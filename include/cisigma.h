@@ -67,7 +67,8 @@ extern "C" {
 
 /* option keys for cisigma_set_option */
 #define CISIGMA_OPT_PRECISION 1    /* Davidson vectors and sigma: CISIGMA_FP64 (plain) or CISIGMA_FP32 (mixed) */
-#define CISIGMA_OPT_MAX_SPACE 2    /* Davidson subspace size before collapse (>= 2*nroots); default 8*nroots, min 16 */
+#define CISIGMA_OPT_MAX_SPACE 2    /* Davidson subspace size before collapse (>= 2*nroots); default max(8*nroots, 32),
+                                      capped by what fits in 70% of free device memory */
 #define CISIGMA_OPT_MAX_ITER 3     /* Davidson iteration limit; default 100 */
 #define CISIGMA_OPT_REFINE_EVERY 4 /* mixed mode: also refine in FP64 every R iterations; default 0 = only when the
                                       FP32 iteration meets the convergence test */
@@ -85,6 +86,11 @@ extern "C" {
                                       the beta-beta entry of
                                       cisigma_pass_times is then the wait for that stream after the
                                       alpha-beta pass */
+#define CISIGMA_OPT_THICK_RESTART 13 /* nonzero (default): when the Davidson basis would exceed max_space it
+                                      collapses onto the current Ritz vectors plus the part of the previous
+                                      iteration's Ritz vectors outside them (at most 2 nroots vectors; used
+                                      when nroots <= 8 and 3 nroots <= max_space); 0: the current Ritz
+                                      vectors only */
 #define CISIGMA_OPT_GRAPH 11       /* nonzero: cisigma_apply on a non-NULL stream runs its kernels eagerly
                                       at the first call with a given (C, sigma, dtype, stream) and captures
                                       them into a HIP graph that later calls with the same arguments replay

@@ -22,6 +22,7 @@ OPT_SS_CHUNK = 9
 OPT_SPIN_PARITY = 10
 OPT_GRAPH = 11
 OPT_OVERLAP = 12
+OPT_THICK_RESTART = 13
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")

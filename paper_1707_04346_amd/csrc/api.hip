@@ -1249,6 +1249,9 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
             return CISIGMA_OK;
+        case CISIGMA_OPT_THICK_RESTART:
+            ctx->thick_restart = value != 0;
+            return CISIGMA_OK;
         case CISIGMA_OPT_OVERLAP:
             cis::drop_graphs(ctx);
             ctx->overlap = value != 0;

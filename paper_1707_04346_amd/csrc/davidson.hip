@@ -6,8 +6,10 @@
 //   (3) correction t = r / (theta - H_II) for each unconverged root, made
 //       orthogonal to all previous vectors (classical Gram-Schmidt, twice);
 //   (4) sigma of the new vectors, updated G, re-diagonalisation; repeat.
-// The basis collapses to the current Ritz vectors when it would exceed
-// max_space.  Vector arithmetic runs in HIP kernels with FP64 accumulation;
+// When the basis would exceed max_space it collapses onto the current Ritz
+// vectors together with the part of the previous iteration's Ritz vectors
+// outside them (a thick restart, which keeps the direction the iteration was
+// moving in), or onto the current Ritz vectors alone.  Vector arithmetic runs in HIP kernels with FP64 accumulation;
 // only the projected matrix (max_space^2 doubles) and a few norms cross to the
 // host each iteration.  The projected eigenproblem is solved on the host by
 // cyclic Jacobi rotations.
@@ -36,6 +38,7 @@ constexpr int kRedBlocks = 1024;
 constexpr int kRitzRoots = 4;     // roots per pass of the batched Ritz kernel
 constexpr int kGroup = 8;
 constexpr int kMultiY = 4;        // vectors per pass of the blocked dot / update kernels
+constexpr int kThick = 16;        // most vectors kept by a thick restart (current + previous Ritz vectors)
 
 template <typename T>
 __device__ __forceinline__ double ld(const T *p, int64_t i) { return double(p[i]); }
@@ -234,6 +237,31 @@ __global__ __launch_bounds__(256) void k_subtract(const T *X, int64_t sx, int nx
     }
 }
 
+// V_j <- sum_i q[j * m + i] V_i for j < k <= kThick, in place: every thread
+// reads element n of all m vectors before it writes element n of the first k
+template <typename T>
+__global__ __launch_bounds__(256) void k_combine_inplace(T *V, int64_t sv, int m, const double *q, int k, int64_t N) {
+    extern __shared__ double qs[];
+    for (int i = threadIdx.x; i < k * m; i += blockDim.x) qs[i] = q[i];
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double acc[kThick];
+#pragma unroll
+        for (int j = 0; j < kThick; ++j) acc[j] = 0;
+#pragma unroll 4
+        for (int i = 0; i < m; ++i) {
+            const double v = double(V[i * sv + n]);
+#pragma unroll
+            for (int j = 0; j < kThick; ++j)
+                if (j < k) acc[j] += qs[j * m + i] * v;
+        }
+#pragma unroll
+        for (int j = 0; j < kThick; ++j)
+            if (j < k) V[j * sv + n] = T(acc[j]);
+    }
+}
+
 template <typename TI, typename TO>
 __global__ void k_scale_copy(const TI *src, TO *dst, double f, int64_t N) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -346,7 +374,7 @@ void jacobi_eig(std::vector<double> A, int n, std::vector<double> &w, std::vecto
 struct Dev {
     cisigma_ctx *ctx;
     hipStream_t s;
-    double *partial = nullptr, *dvec = nullptr, *ybuf = nullptr;
+    double *partial = nullptr, *dvec = nullptr, *ybuf = nullptr, *qbuf = nullptr;
     int64_t *pidx = nullptr;
     int grid(int64_t N) const {
         int64_t g = (N + 255) / 256;
@@ -454,6 +482,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         (void)hipFree(B); (void)hipFree(S); (void)hipFree(SX); (void)hipFree(TB); (void)hipFree(X64);
         (void)hipFree(hd); (void)hipFree(sig64);
         (void)hipFree(d.partial); (void)hipFree(d.dvec); (void)hipFree(d.pidx); (void)hipFree(d.ybuf);
+        (void)hipFree(d.qbuf);
     };
     struct Guard { std::function<void()> f; ~Guard() { f(); } } guard{cleanup};
     DV_TRY(hipMalloc(&B, size_t(max_space) * N * es));
@@ -468,6 +497,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     DV_TRY(hipMalloc(&d.dvec, size_t(std::max(kRedBlocks, 512 * kMultiY)) * sizeof(double)));
     DV_TRY(hipMalloc(&d.pidx, kRedBlocks * sizeof(int64_t)));
     DV_TRY(hipMalloc(&d.ybuf, size_t(kRitzRoots) * (512 + 1) * sizeof(double)));
+    DV_TRY(hipMalloc(&d.qbuf, size_t(kThick) * 512 * sizeof(double)));
     DV_TRY(launch_hdiag(ctx, hd, d.s));
 
     const int g = d.grid(N);
@@ -505,6 +535,13 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     bool converged = false, have_rq = false, stalled = false;
     int since_ref = 0;
     int rc = CISIGMA_OK;
+    // Ritz coefficients of the previous iteration (mprev x nroots) in the current
+    // basis, whose first mprev vectors are unchanged since: a thick restart keeps
+    // the part of them outside the current Ritz vectors
+    const bool thick = ctx->thick_restart && 3 * nroots <= max_space && 2 * nroots <= kThick;
+    std::vector<double> Yprev;
+    int mprev = 0;
+    bool prev_ok = false;
     auto sigma_of = [&](const void *x, void *y, int dtype) -> int {
         int r = apply_sigma(ctx, x, y, dtype, d.s);
         if (dtype == CISIGMA_FP32) ++nsig32; else ++nsig64;
@@ -638,8 +675,62 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             if (all_ok) { converged = true; break; }
         }
         if (iter >= ctx->max_iter) break;
-        if (!refined_now && m + nroots > max_space) {
+        bool collapsed = refined_now;
+        if (!refined_now && m + nroots > max_space && thick && prev_ok && mprev <= m) {
+            // thick restart: the current Ritz vectors plus the orthonormalised
+            // remainder of the previous ones, B <- B Q and S <- S Q in place,
+            // G <- Q^T G Q
+            std::vector<double> Q(size_t(2 * nroots) * m, 0.0);
+            for (int r = 0; r < nroots; ++r)
+                for (int i = 0; i < m; ++i) Q[size_t(r) * m + i] = Y[size_t(i) * m + r];
+            int k = nroots;
+            std::vector<double> v(m);
+            for (int r = 0; r < nroots; ++r) {
+                double n0 = 0;
+                for (int i = 0; i < m; ++i) {
+                    v[i] = i < mprev ? Yprev[size_t(i) * nroots + r] : 0.0;
+                    n0 += v[i] * v[i];
+                }
+                for (int pass = 0; pass < 2; ++pass)
+                    for (int j = 0; j < k; ++j) {
+                        double c = 0;
+                        for (int i = 0; i < m; ++i) c += Q[size_t(j) * m + i] * v[i];
+                        for (int i = 0; i < m; ++i) v[i] -= c * Q[size_t(j) * m + i];
+                    }
+                double nv = 0;
+                for (int i = 0; i < m; ++i) nv += v[i] * v[i];
+                if (!(nv > 1e-8 * n0)) continue;
+                nv = std::sqrt(nv);
+                for (int i = 0; i < m; ++i) Q[size_t(k) * m + i] = v[i] / nv;
+                ++k;
+            }
+            if (k > nroots) {
+                DV_TRY(hipMemcpyAsync(d.qbuf, Q.data(), size_t(k) * m * sizeof(double), hipMemcpyHostToDevice, d.s));
+                const size_t lq = size_t(k) * m * sizeof(double);
+                hipLaunchKernelGGL((k_combine_inplace<T>), dim3(g), dim3(256), lq, d.s, B, N, m, d.qbuf, k, N);
+                hipLaunchKernelGGL((k_combine_inplace<T>), dim3(g), dim3(256), lq, d.s, S, N, m, d.qbuf, k, N);
+                DV_TRY(hipGetLastError());
+                std::vector<double> GQ(size_t(m) * k, 0.0);
+                for (int i = 0; i < m; ++i)
+                    for (int b = 0; b < k; ++b) {
+                        double acc = 0;
+                        for (int l = 0; l < m; ++l) acc += Gm[size_t(i) * m + l] * Q[size_t(b) * m + l];
+                        GQ[size_t(i) * k + b] = acc;
+                    }
+                for (int i = 0; i < max_space * max_space; ++i) G[i] = 0;
+                for (int a = 0; a < k; ++a)
+                    for (int b = 0; b <= a; ++b) {
+                        double acc = 0;
+                        for (int i = 0; i < m; ++i) acc += Q[size_t(a) * m + i] * GQ[size_t(i) * k + b];
+                        G[size_t(a) * max_space + b] = G[size_t(b) * max_space + a] = acc;
+                    }
+                m = k;
+                collapsed = true;
+            }
+        }
+        if (!collapsed && m + nroots > max_space) {
             // collapse onto the current Ritz vectors
+            collapsed = true;
             for (int r = 0; r < nroots; ++r)
                 hipLaunchKernelGGL((k_scale_copy<double, T>), dim3(g), dim3(256), 0, d.s, X64 + int64_t(r) * N,
                                    B + int64_t(r) * N, 1.0, N);
@@ -648,6 +739,22 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int i = 0; i < max_space * max_space; ++i) G[i] = 0;
             for (int r = 0; r < nroots; ++r) G[size_t(r) * max_space + r] = theta[r];
             m = nroots;
+        }
+        // this iteration's Ritz vectors, for the next restart: after a collapse
+        // onto them they are the first nroots basis vectors
+        if (refined_now) {
+            prev_ok = false;
+        } else if (collapsed) {
+            Yprev.assign(size_t(m) * nroots, 0.0);
+            for (int r = 0; r < nroots; ++r) Yprev[size_t(r) * nroots + r] = 1.0;
+            mprev = m;
+            prev_ok = true;
+        } else {
+            Yprev.assign(size_t(m) * nroots, 0.0);
+            for (int i = 0; i < m; ++i)
+                for (int r = 0; r < nroots; ++r) Yprev[size_t(i) * nroots + r] = Y[size_t(i) * m + r];
+            mprev = m;
+            prev_ok = true;
         }
         // (3) corrections, orthogonalised against the basis (CGS2, all corrections
         // in one pass over the basis) and then against each other

@@ -209,6 +209,7 @@ struct cisigma_ctx {
     int precision = CISIGMA_FP64;
     int max_space = 0;
     int max_iter = 100;
+    int thick_restart = 1;         // collapses keep the previous Ritz vectors too (CISIGMA_OPT_THICK_RESTART)
     int refine_every = 0;          // mixed mode: 0 = refine only when the FP32 iteration converges
     double resid_tol = -1.0;
     int verbose = 0;

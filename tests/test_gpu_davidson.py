@@ -45,6 +45,25 @@ def test_davidson_mixed_vs_dense(case):
     assert st["sigma_fp32"] > 0 and st["sigma_fp64"] > 0 and st["refinements"] >= 1
 
 
+@pytest.mark.parametrize("thick", [1, 0], ids=["thick", "plain"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_davidson_restarts_vs_dense(thick, prec):
+    """A subspace of 3 nroots vectors forces a collapse every iteration or two:
+    thick restarts (current + previous Ritz vectors) and plain ones (current
+    only) both reach the dense eigenvalues."""
+    cis = _cis()
+    ctx, ref = make(8, 4, 4, seed=6)
+    w = np.linalg.eigvalsh(ref.hmat())
+    nroots = 2
+    ctx.set_option(cis.OPT_THICK_RESTART, thick)
+    ctx.set_option(cis.OPT_MAX_SPACE, 3 * nroots)
+    ctx.set_option(cis.OPT_MAX_ITER, 600)
+    ctx.set_option(cis.OPT_PRECISION, cis.FP64 if prec == "fp64" else cis.FP32)
+    e, st, status = ctx.davidson(nroots, 1e-10)
+    assert status == 0
+    assert np.allclose(e, w[:nroots], atol=1e-8 if prec == "fp64" else 1e-6), (e - w[:nroots])
+
+
 def test_davidson_vectors_and_certificate_cas12():
     """CAS(12,12): GPU FP64 eigenvector; the oracle's sigma of it gives a
     Rayleigh quotient equal to the GPU energy and a small residual."""
