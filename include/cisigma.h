@@ -86,6 +86,13 @@ extern "C" {
                                       the beta-beta entry of
                                       cisigma_pass_times is then the wait for that stream after the
                                       alpha-beta pass */
+#define CISIGMA_OPT_PSPACE 14       /* Davidson P-space (Sec. 2.1 step (2), preconditioner): the exact block
+                                      of H over the P determinants with the lowest H_II (P <= 2048; 0, the
+                                      default: none) gives the initial guess (its lowest eigenvectors) and,
+                                      on those determinants, the correction (theta - H_PP)^-1 r_P in place
+                                      of the diagonal one.  Not used with CISIGMA_OPT_SPIN_PARITY != 0.
+                                      Measured: 3 roots at CAS(16,16) take 347 instead of 360 sigma builds
+                                      with P = 256, no faster overall */
 #define CISIGMA_OPT_THICK_RESTART 13 /* nonzero (default): when the Davidson basis would exceed max_space it
                                       collapses onto the current Ritz vectors plus the part of the previous
                                       iteration's Ritz vectors outside them (at most 2 nroots vectors; used
@@ -211,6 +218,17 @@ int cisigma_set_option(cisigma_ctx *ctx, int key, double value);
  * other C the result is sigma_aa(C) + sigma_ab(C) + sigma_bb(p C^T)).
  */
 int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream);
+
+/*
+ * cisigma_hmat_block -- Hamiltonian matrix elements between determinants of
+ * the space (Eq. 6 with the string operators of Eq. 7: the Slater-Condon
+ * rules): out[i * m + j] = H(rows[i], cols[j]) for vector indices rows[0..n)
+ * and cols[0..m) (the order of cisigma_layout / cisigma_address).
+ *   rows, cols  host int64 arrays; out host double[n * m], written.
+ * Synchronous, evaluated on the host (for small blocks: a P-space, tests).
+ * EINVAL for an index outside [0, ndet) or NULL arrays with n, m > 0.
+ */
+int cisigma_hmat_block(cisigma_ctx *ctx, int n, const int64_t *rows, int m, const int64_t *cols, double *out);
 
 /*
  * cisigma_hdiag -- diagonal H_II into the device array hdiag[ndet] (FP64),

@@ -23,6 +23,7 @@ OPT_SPIN_PARITY = 10
 OPT_GRAPH = 11
 OPT_OVERLAP = 12
 OPT_THICK_RESTART = 13
+OPT_PSPACE = 14
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")
@@ -70,6 +71,8 @@ _lib.cisigma_apply.restype = _i32
 _lib.cisigma_apply.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.cisigma_hdiag.restype = _i32
 _lib.cisigma_hdiag.argtypes = [_vp, _vp, _vp]
+_lib.cisigma_hmat_block.restype = _i32
+_lib.cisigma_hmat_block.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp]
 _lib.cisigma_davidson.restype = _i32
 _lib.cisigma_davidson.argtypes = [_vp, _i32, _f64, _vp, _vp, ctypes.POINTER(Stats)]
 _lib.cisigma_rdm.restype = _i32
@@ -85,7 +88,8 @@ _lib.cisigma_strerror.argtypes = [_i32]
 
 EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "cisigma_address", "cisigma_strings",
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
-           "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm"]
+           "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
+           "cisigma_hmat_block"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -206,6 +210,15 @@ class Context:
 
     def hdiag(self, out, stream=None):
         self._check(_lib.cisigma_hdiag(self._h, _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def hmat_block(self, rows, cols):
+        """H(rows[i], cols[j]) (numpy, n x m) between determinants given by vector index."""
+        r = np.ascontiguousarray(rows, dtype=np.int64)
+        c = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.zeros((r.size, c.size), np.float64)
+        self._check(_lib.cisigma_hmat_block(self._h, int(r.size), r.ctypes.data, int(c.size), c.ctypes.data,
+                                            out.ctypes.data))
         return out
 
     def davidson(self, nroots=1, tol=1e-10, vecs=None, allow_noconv=False):

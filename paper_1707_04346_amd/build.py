@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcisigma.so")
-SOURCES = ["api.hip", "tables.hip", "sigma_ab.hip", "sigma_abx.hip", "sigma_abg.hip", "sigma_ss.hip", "vec.hip", "davidson.hip", "rdm.hip"]
+SOURCES = ["api.hip", "tables.hip", "sigma_ab.hip", "sigma_abx.hip", "sigma_abg.hip", "sigma_ss.hip", "vec.hip", "davidson.hip", "rdm.hip", "hmat.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-munsafe-fp-atomics",

@@ -1187,6 +1187,28 @@ CIS_API int cisigma_address(const cisigma_ctx *ctx, uint32_t alpha_bits, uint32_
     return CISIGMA_OK;
 }
 
+CIS_API int cisigma_hmat_block(cisigma_ctx *ctx, int n, const int64_t *rows, int m, const int64_t *cols,
+                               double *out) {
+    if (!ctx || n < 0 || m < 0 || (n > 0 && !rows) || (m > 0 && !cols) || (n > 0 && m > 0 && !out))
+        return ctx ? cis_set_error(ctx, CISIGMA_EINVAL, "hmat_block: bad arguments") : CISIGMA_EINVAL;
+    std::vector<uint32_t> astr(ctx->sp[0].nstr), bstr(ctx->sp[1].nstr);
+    if (!astr.empty())
+        HIP_OR_FAIL(ctx, hipMemcpy(astr.data(), ctx->sp[0].d_str, astr.size() * 4, hipMemcpyDeviceToHost), "hmat_block");
+    if (!bstr.empty())
+        HIP_OR_FAIL(ctx, hipMemcpy(bstr.data(), ctx->sp[1].d_str, bstr.size() * 4, hipMemcpyDeviceToHost), "hmat_block");
+    std::vector<uint32_t> ca(m), cb(m);
+    for (int j = 0; j < m; ++j)
+        if (!cis::det_strings(ctx, cols[j], astr, bstr, &ca[j], &cb[j]))
+            return cis_set_error(ctx, CISIGMA_EINVAL, "hmat_block: column index out of range");
+    for (int i = 0; i < n; ++i) {
+        uint32_t a, b;
+        if (!cis::det_strings(ctx, rows[i], astr, bstr, &a, &b))
+            return cis_set_error(ctx, CISIGMA_EINVAL, "hmat_block: row index out of range");
+        for (int j = 0; j < m; ++j) out[size_t(i) * m + j] = cis::hmat_element(ctx, a, b, ca[j], cb[j]);
+    }
+    return CISIGMA_OK;
+}
+
 CIS_API int cisigma_strings(const cisigma_ctx *ctx, int spin, uint32_t *out, int *nstr) {
     if (!ctx || !nstr || spin < 0 || spin > 1) return CISIGMA_EINVAL;
     const auto &T = ctx->sp[spin];
@@ -1248,6 +1270,10 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_PSPACE:
+            if (value < 0 || value > 2048) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: pspace out of range");
+            ctx->pspace = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_THICK_RESTART:
             ctx->thick_restart = value != 0;

@@ -268,6 +268,17 @@ __global__ void k_scale_copy(const TI *src, TO *dst, double f, int64_t N) {
     for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) dst[n] = TO(f * double(src[n]));
 }
 
+// x[idx[i]] = v[i] and out[i] = x[idx[i]]: the P-space entries of a vector
+template <typename T>
+__global__ void k_put_entries(T *x, const int64_t *idx, const double *v, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) x[idx[i]] = T(v[i]);
+}
+
+template <typename T>
+__global__ void k_get_entries(const T *x, const int64_t *idx, double *out, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) out[i] = double(x[idx[i]]);
+}
+
 template <typename T>
 __global__ void k_unit(T *x, int64_t N, int64_t idx) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
@@ -374,8 +385,8 @@ void jacobi_eig(std::vector<double> A, int n, std::vector<double> &w, std::vecto
 struct Dev {
     cisigma_ctx *ctx;
     hipStream_t s;
-    double *partial = nullptr, *dvec = nullptr, *ybuf = nullptr, *qbuf = nullptr;
-    int64_t *pidx = nullptr;
+    double *partial = nullptr, *dvec = nullptr, *ybuf = nullptr, *qbuf = nullptr, *pval = nullptr;
+    int64_t *pidx = nullptr, *pdet = nullptr;
     int grid(int64_t N) const {
         int64_t g = (N + 255) / 256;
         return int(g < kRedBlocks ? (g > 0 ? g : 1) : kRedBlocks);
@@ -482,7 +493,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         (void)hipFree(B); (void)hipFree(S); (void)hipFree(SX); (void)hipFree(TB); (void)hipFree(X64);
         (void)hipFree(hd); (void)hipFree(sig64);
         (void)hipFree(d.partial); (void)hipFree(d.dvec); (void)hipFree(d.pidx); (void)hipFree(d.ybuf);
-        (void)hipFree(d.qbuf);
+        (void)hipFree(d.qbuf); (void)hipFree(d.pval); (void)hipFree(d.pdet);
     };
     struct Guard { std::function<void()> f; ~Guard() { f(); } } guard{cleanup};
     DV_TRY(hipMalloc(&B, size_t(max_space) * N * es));
@@ -501,13 +512,21 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     DV_TRY(launch_hdiag(ctx, hd, d.s));
 
     const int g = d.grid(N);
-    // (1) guess: unit vectors on the lowest diagonal elements (ties: lowest index)
+    // P-space: the np determinants with the lowest H_II (ties: lowest index) and
+    // the exact H over them, diagonalised: its lowest eigenvectors are the guess,
+    // and on those determinants the correction is (theta - H_PP)^-1 r_P
+    const int np = (par == 0 && ctx->pspace >= nroots) ? int(std::min<int64_t>(ctx->pspace, dim)) : 0;
+    std::vector<int64_t> pdet;
+    std::vector<double> pdiag, pw, pU;
+    // (1) guess: unit vectors on the lowest diagonal elements (ties: lowest index),
+    // or the lowest eigenvectors of the P-space block
     {
         double pv = -INFINITY;
         int64_t pi = -1;
         std::vector<double> hv(g);
         std::vector<int64_t> hi(g);
-        for (int r = 0; r < nroots; ++r) {
+        const int nlow = std::max(nroots, np);
+        for (int r = 0; r < nlow; ++r) {
             hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx, nside, par);
             DV_TRY(hipMemcpyAsync(hv.data(), d.dvec, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
             DV_TRY(hipMemcpyAsync(hi.data(), d.pidx, g * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
@@ -517,16 +536,86 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int b = 0; b < g; ++b)
                 if (hi[b] >= 0 && (bi < 0 || hv[b] < bv || (hv[b] == bv && hi[b] < bi))) { bv = hv[b]; bi = hi[b]; }
             if (bi < 0) return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: fewer determinants than roots");
+            pv = bv;
+            pi = bi;
+            if (np > 0) {
+                pdet.push_back(bi);
+                pdiag.push_back(bv);
+                continue;
+            }
             const int64_t ra = par ? bi / nside : 0, cb = par ? bi % nside : 0;
             if (par == 0 || ra == cb)
                 hipLaunchKernelGGL(k_unit<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, bi);
             else   // (|Ia Ib> + p |Ib Ia>) / sqrt(2)
                 hipLaunchKernelGGL(k_unit2<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, cb * nside + ra, bi,
                                    T(par) / T(1.4142135623730951));
-            pv = bv;
-            pi = bi;
+        }
+        if (np > 0) {
+            std::vector<uint32_t> astr(ctx->sp[0].nstr), bstr(ctx->sp[1].nstr), pa(np), pb(np);
+            if (!astr.empty())
+                DV_TRY(hipMemcpy(astr.data(), ctx->sp[0].d_str, astr.size() * 4, hipMemcpyDeviceToHost));
+            if (!bstr.empty())
+                DV_TRY(hipMemcpy(bstr.data(), ctx->sp[1].d_str, bstr.size() * 4, hipMemcpyDeviceToHost));
+            for (int i = 0; i < np; ++i)
+                if (!det_strings(ctx, pdet[i], astr, bstr, &pa[i], &pb[i]))
+                    return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: P-space index outside the space");
+            std::vector<double> hpp(size_t(np) * np);
+            for (int i = 0; i < np; ++i)
+                for (int j = 0; j <= i; ++j)
+                    hpp[size_t(i) * np + j] = hpp[size_t(j) * np + i] = hmat_element(ctx, pa[i], pb[i], pa[j], pb[j]);
+            jacobi_eig(hpp, np, pw, pU);
+            DV_TRY(hipMalloc(&d.pdet, size_t(np) * sizeof(int64_t)));
+            DV_TRY(hipMalloc(&d.pval, size_t(np) * nroots * sizeof(double)));
+            DV_TRY(hipMemcpy(d.pdet, pdet.data(), size_t(np) * sizeof(int64_t), hipMemcpyHostToDevice));
+            std::vector<double> u(size_t(np) * nroots);
+            for (int r = 0; r < nroots; ++r)
+                for (int i = 0; i < np; ++i) u[size_t(r) * np + i] = pU[size_t(i) * np + r];
+            DV_TRY(hipMemcpy(d.pval, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice));
+            const int pg = std::min(64, (np + 255) / 256);
+            for (int r = 0; r < nroots; ++r) {
+                hipLaunchKernelGGL(k_unit<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, int64_t(-1));
+                hipLaunchKernelGGL(k_put_entries<T>, dim3(pg), dim3(256), 0, d.s, B + int64_t(r) * N, d.pdet,
+                                   d.pval + size_t(r) * np, np);
+            }
+            DV_TRY(hipGetLastError());
         }
     }
+    // corrections on the P-space determinants of every root: TB holds
+    // t = r / (theta - H_II) there; r_P is recovered and solved exactly
+    auto pspace_correct = [&](const std::vector<double> &theta) -> hipError_t {
+        if (np == 0) return hipSuccess;
+        const int pg = std::min(64, (np + 255) / 256);
+        for (int r = 0; r < nroots; ++r)
+            hipLaunchKernelGGL(k_get_entries<T>, dim3(pg), dim3(256), 0, d.s, TB + int64_t(r) * N, d.pdet,
+                               d.pval + size_t(r) * np, np);
+        std::vector<double> t(size_t(np) * nroots), y(np);
+        hipError_t e = hipMemcpyAsync(t.data(), d.pval, t.size() * sizeof(double), hipMemcpyDeviceToHost, d.s);
+        if (e == hipSuccess) e = hipStreamSynchronize(d.s);
+        if (e != hipSuccess) return e;
+        auto clamp = [](double x) { return std::fabs(x) < 1e-8 ? (x < 0 ? -1e-8 : 1e-8) : x; };
+        for (int r = 0; r < nroots; ++r) {
+            double *tr = t.data() + size_t(r) * np;
+            for (int i = 0; i < np; ++i) tr[i] *= clamp(theta[r] - pdiag[i]);          // r_P
+            for (int k = 0; k < np; ++k) {
+                double acc = 0;
+                for (int i = 0; i < np; ++i) acc += pU[size_t(i) * np + k] * tr[i];
+                y[k] = acc / clamp(theta[r] - pw[k]);
+            }
+            for (int i = 0; i < np; ++i) {
+                double acc = 0;
+                for (int k = 0; k < np; ++k) acc += pU[size_t(i) * np + k] * y[k];
+                tr[i] = acc;
+            }
+        }
+        e = hipMemcpyAsync(d.pval, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice, d.s);
+        if (e != hipSuccess) return e;
+        for (int r = 0; r < nroots; ++r)
+            hipLaunchKernelGGL(k_put_entries<T>, dim3(pg), dim3(256), 0, d.s, TB + int64_t(r) * N, d.pdet,
+                               d.pval + size_t(r) * np, np);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(d.s);   // t is host memory
+        return e;
+    };
     std::vector<double> G(size_t(max_space) * max_space, 0.0);
     std::vector<double> theta(nroots, 0.0), theta_old(nroots, INFINITY), rnorm(nroots, 0.0);
     std::vector<double> erq(nroots, 0.0), r64(nroots, INFINITY);
@@ -756,6 +845,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             mprev = m;
             prev_ok = true;
         }
+        DV_TRY(pspace_correct(theta));
         // (3) corrections, orthogonalised against the basis (CGS2, all corrections
         // in one pass over the basis) and then against each other
         nnew = 0;

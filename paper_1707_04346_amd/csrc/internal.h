@@ -209,6 +209,7 @@ struct cisigma_ctx {
     int precision = CISIGMA_FP64;
     int max_space = 0;
     int max_iter = 100;
+    int pspace = 0;                // Davidson P-space size (CISIGMA_OPT_PSPACE)
     int thick_restart = 1;         // collapses keep the previous Ritz vectors too (CISIGMA_OPT_THICK_RESTART)
     int refine_every = 0;          // mixed mode: 0 = refine only when the FP32 iteration converges
     double resid_tol = -1.0;
@@ -290,6 +291,13 @@ size_t rdm_lds_bytes(const cisigma_ctx *ctx, int dtype);
 size_t rdm_part_elems(const cisigma_ctx *ctx);
 hipError_t launch_rdm(const cisigma_ctx *ctx, const void *cp, int dtype, double *part, double *rdm1, double *rdm2,
                       hipStream_t s);
+
+// Hamiltonian elements between single determinants (hmat.hip): the strings of
+// vector element idx (from host copies of both string tables), and H_IJ by the
+// Slater-Condon rules
+bool det_strings(const cisigma_ctx *c, int64_t idx, const std::vector<uint32_t> &astr,
+                 const std::vector<uint32_t> &bstr, uint32_t *a, uint32_t *b);
+double hmat_element(const cisigma_ctx *c, uint32_t a1, uint32_t b1, uint32_t a2, uint32_t b2);
 
 // Davidson driver (davidson.hip)
 int davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats);

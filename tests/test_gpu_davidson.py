@@ -45,9 +45,32 @@ def test_davidson_mixed_vs_dense(case):
     assert st["sigma_fp32"] > 0 and st["sigma_fp64"] > 0 and st["refinements"] >= 1
 
 
+@pytest.mark.parametrize("case", [(4, 2, 2, None), (5, 3, 2, None), (6, 1, 4, None),
+                                  (7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6]))],
+                         ids=["cas4", "n5a3b2", "n6a1b4", "gas7"])
+def test_hmat_block_matches_oracle(case):
+    """cisigma_hmat_block (the P-space Hamiltonian) against the oracle's dense H:
+    every element of the space for small cases, bit-level agreement not required
+    (same rules, different summation order): 1e-12 absolute."""
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, seed=3, gas=gas)
+    H = ref.hmat()
+    idx = np.arange(ctx.ndet)
+    got = ctx.hmat_block(idx, idx)
+    assert np.abs(got - H).max() <= 1e-12 * max(1.0, np.abs(H).max())
+    # a rectangular block with repeated and permuted indices
+    rng = np.random.default_rng(1)
+    r, c = rng.integers(0, ctx.ndet, 7), rng.permutation(ctx.ndet)[:5]
+    assert np.abs(ctx.hmat_block(r, c) - H[np.ix_(r, c)]).max() <= 1e-12 * max(1.0, np.abs(H).max())
+    cis = _cis()
+    with pytest.raises(cis.CisigmaError):
+        ctx.hmat_block([ctx.ndet], [0])
+
+
+@pytest.mark.parametrize("pspace", [64, 0], ids=["pspace64", "nopspace"])
 @pytest.mark.parametrize("thick", [1, 0], ids=["thick", "plain"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_davidson_restarts_vs_dense(thick, prec):
+def test_davidson_restarts_vs_dense(thick, prec, pspace):
     """A subspace of 3 nroots vectors forces a collapse every iteration or two:
     thick restarts (current + previous Ritz vectors) and plain ones (current
     only) both reach the dense eigenvalues."""
@@ -56,6 +79,7 @@ def test_davidson_restarts_vs_dense(thick, prec):
     w = np.linalg.eigvalsh(ref.hmat())
     nroots = 2
     ctx.set_option(cis.OPT_THICK_RESTART, thick)
+    ctx.set_option(cis.OPT_PSPACE, pspace)
     ctx.set_option(cis.OPT_MAX_SPACE, 3 * nroots)
     ctx.set_option(cis.OPT_MAX_ITER, 600)
     ctx.set_option(cis.OPT_PRECISION, cis.FP64 if prec == "fp64" else cis.FP32)
