@@ -86,6 +86,10 @@ extern "C" {
                                       the beta-beta entry of
                                       cisigma_pass_times is then the wait for that stream after the
                                       alpha-beta pass */
+#define CISIGMA_OPT_LOW_MEMORY 15   /* nonzero: the mixed-precision Davidson frees the FP32 sigma workspace
+                                      before each FP64 refinement and the FP64 one after it, so only one is
+                                      held at a time; done anyway when the FP64 workspace does not fit in
+                                      free memory (CAS(18,18) with a 6-vector subspace).  Default 0 */
 #define CISIGMA_OPT_PSPACE 14       /* Davidson P-space (Sec. 2.1 step (2), preconditioner): the exact block
                                       of H over the P determinants with the lowest H_II (P <= 2048; 0, the
                                       default: none) gives the initial guess (its lowest eigenvectors) and,

@@ -24,6 +24,7 @@ OPT_GRAPH = 11
 OPT_OVERLAP = 12
 OPT_THICK_RESTART = 13
 OPT_PSPACE = 14
+OPT_LOW_MEMORY = 15
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")

@@ -781,6 +781,16 @@ int build_gas_owner(cisigma_ctx *c) {
     return CISIGMA_OK;
 }
 
+// device bytes of the four layout copies of one dtype's workspace (without the
+// materialised same-spin rows, which take what is free)
+size_t workspace_copy_bytes(const cisigma_ctx *c, size_t es) {
+    int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
+    if (c->go.ks) for (int ld : c->pl[0].ld) zero_row = std::max<int64_t>(zero_row, ld);
+    size_t na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
+    size_t nb = size_t(std::max<int64_t>(c->pl[1].size + (c->cas ? c->pl[1].ld[0] : 0), 1)) * es;
+    return 2 * (na + nb);
+}
+
 int ensure_workspace(cisigma_ctx *c, int dtype) {
     auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
     if (W.ready) return CISIGMA_OK;
@@ -901,6 +911,24 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
         for (auto e : ev) c->prof_events.push_back(e);
         c->prof_pending.push_back(1);
     }
+    return CISIGMA_OK;
+}
+
+bool workspace_fits(cisigma_ctx *c, int dtype) {
+    if (c->ws[dtype == CISIGMA_FP32 ? 1 : 0].ready) return true;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return true;
+    const size_t need = workspace_copy_bytes(c, dtype == CISIGMA_FP32 ? 4 : 8);
+    return need + need / 8 + (256u << 20) <= fr;
+}
+
+int release_workspace(cisigma_ctx *c, int dtype) {
+    auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
+    if (!W.ready) return CISIGMA_OK;
+    HIP_OR_FAIL(c, hipDeviceSynchronize(), "release workspace");
+    drop_graphs(c);   // captured graphs name these buffers
+    (void)hipFree(W.cp); (void)hipFree(W.sp); (void)hipFree(W.ct); (void)hipFree(W.st); (void)hipFree(W.ys);
+    W = Workspace{};
     return CISIGMA_OK;
 }
 
@@ -1270,6 +1298,9 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_LOW_MEMORY:
+            ctx->low_memory = value != 0;
             return CISIGMA_OK;
         case CISIGMA_OPT_PSPACE:
             if (value < 0 || value > 2048) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: pspace out of range");

@@ -11,8 +11,8 @@
 // outside them (a thick restart, which keeps the direction the iteration was
 // moving in), or onto the current Ritz vectors alone.  Vector arithmetic runs in HIP kernels with FP64 accumulation;
 // only the projected matrix (max_space^2 doubles) and a few norms cross to the
-// host each iteration.  The projected eigenproblem is solved on the host by
-// cyclic Jacobi rotations.
+// host each iteration.  The projected eigenproblem is solved on the host
+// (Householder tridiagonalisation and implicit QL, symeig.h).
 //
 // Mixed precision (FP32 basis and sigma): whenever the FP32 iteration meets
 // the convergence test (and, if refine_every > 0, every refine_every
@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "symeig.h"
 
 namespace cis {
 namespace {
@@ -329,58 +330,6 @@ __global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, dou
     if (threadIdx.x == 0) { ov[blockIdx.x] = sv[0]; oi[blockIdx.x] = si[0]; }
 }
 
-// symmetric eigenproblem by cyclic Jacobi; A (n x n, row-major) is destroyed;
-// eigenvalues ascending in w, eigenvectors as columns of V
-void jacobi_eig(std::vector<double> A, int n, std::vector<double> &w, std::vector<double> &V) {
-    V.assign(size_t(n) * n, 0.0);
-    for (int i = 0; i < n; ++i) V[size_t(i) * n + i] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0, tot = 0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                double a = A[size_t(i) * n + j];
-                tot += a * a;
-                if (i != j) off += a * a;
-            }
-        if (off <= 1e-30 * tot || off == 0) break;
-        for (int p = 0; p < n; ++p)
-            for (int q = p + 1; q < n; ++q) {
-                double apq = A[size_t(p) * n + q];
-                if (apq == 0) continue;
-                double app = A[size_t(p) * n + p], aqq = A[size_t(q) * n + q];
-                double th = (aqq - app) / (2 * apq);
-                double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1));
-                double c = 1 / std::sqrt(t * t + 1), s = t * c;
-                for (int k = 0; k < n; ++k) {
-                    double akp = A[size_t(k) * n + p], akq = A[size_t(k) * n + q];
-                    A[size_t(k) * n + p] = c * akp - s * akq;
-                    A[size_t(k) * n + q] = s * akp + c * akq;
-                }
-                for (int k = 0; k < n; ++k) {
-                    double apk = A[size_t(p) * n + k], aqk = A[size_t(q) * n + k];
-                    A[size_t(p) * n + k] = c * apk - s * aqk;
-                    A[size_t(q) * n + k] = s * apk + c * aqk;
-                }
-                for (int k = 0; k < n; ++k) {
-                    double vkp = V[size_t(k) * n + p], vkq = V[size_t(k) * n + q];
-                    V[size_t(k) * n + p] = c * vkp - s * vkq;
-                    V[size_t(k) * n + q] = s * vkp + c * vkq;
-                }
-            }
-    }
-    w.resize(n);
-    std::vector<int> idx(n);
-    for (int i = 0; i < n; ++i) { w[i] = A[size_t(i) * n + i]; idx[i] = i; }
-    for (int i = 1; i < n; ++i)
-        for (int j = i; j > 0 && w[idx[j]] < w[idx[j - 1]]; --j) std::swap(idx[j], idx[j - 1]);
-    std::vector<double> w2(n), V2(size_t(n) * n);
-    for (int j = 0; j < n; ++j) {
-        w2[j] = w[idx[j]];
-        for (int k = 0; k < n; ++k) V2[size_t(k) * n + j] = V[size_t(k) * n + idx[j]];
-    }
-    w.swap(w2);
-    V.swap(V2);
-}
 
 struct Dev {
     cisigma_ctx *ctx;
@@ -563,7 +512,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int i = 0; i < np; ++i)
                 for (int j = 0; j <= i; ++j)
                     hpp[size_t(i) * np + j] = hpp[size_t(j) * np + i] = hmat_element(ctx, pa[i], pb[i], pa[j], pb[j]);
-            jacobi_eig(hpp, np, pw, pU);
+            sym_eig(hpp, np, pw, pU);
             DV_TRY(hipMalloc(&d.pdet, size_t(np) * sizeof(int64_t)));
             DV_TRY(hipMalloc(&d.pval, size_t(np) * nroots * sizeof(double)));
             DV_TRY(hipMemcpy(d.pdet, pdet.data(), size_t(np) * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -685,7 +634,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         for (int i = 0; i < m; ++i)
             for (int j = 0; j < m; ++j)
                 Gm[size_t(i) * m + j] = 0.5 * (G[size_t(i) * max_space + j] + G[size_t(j) * max_space + i]);
-        jacobi_eig(Gm, m, w, Y);
+        sym_eig(Gm, m, w, Y);
         ++iter;
         ++since_ref;
         for (int r = 0; r < nroots; ++r) theta[r] = w[r];
@@ -707,6 +656,14 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             ++nref;
             since_ref = 0;
             bool ok64 = true;
+            // spaces where both precisions' sigma workspaces do not fit beside the
+            // basis (CAS(18,18) with FP32 vectors): the FP32 one makes room for the
+            // FP64 one during the refinement
+            const bool swap = ctx->low_memory || !workspace_fits(ctx, CISIGMA_FP64);
+            if (swap) {
+                rc = release_workspace(ctx, CISIGMA_FP32);
+                if (rc) return rc;
+            }
             for (int r = 0; r < nroots; ++r) {
                 double *x = X64 + int64_t(r) * N;
                 rc = sigma_of(x, sig64, CISIGMA_FP64);
@@ -729,6 +686,10 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
                                    1.0, N);
                 hipLaunchKernelGGL((k_scale_copy<double, T>), dim3(g), dim3(256), 0, d.s, sig64, SX + int64_t(r) * N,
                                    1.0, N);
+            }
+            if (swap) {
+                rc = release_workspace(ctx, CISIGMA_FP64);
+                if (rc) return rc;
             }
             have_rq = true;
             if (ctx->verbose) {
@@ -757,7 +718,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             std::vector<double> Gm2(size_t(m) * m);
             for (int i = 0; i < m; ++i)
                 for (int j = 0; j < m; ++j) Gm2[size_t(i) * m + j] = G[size_t(i) * max_space + j];
-            jacobi_eig(Gm2, m, w, Y);
+            sym_eig(Gm2, m, w, Y);
             for (int r = 0; r < nroots; ++r) theta[r] = w[r];
             DV_TRY(ritz_all(m, Y, false));
         } else if (!mixed) {

@@ -209,6 +209,7 @@ struct cisigma_ctx {
     int precision = CISIGMA_FP64;
     int max_space = 0;
     int max_iter = 100;
+    int low_memory = 0;            // swap the sigma workspaces around refinements (CISIGMA_OPT_LOW_MEMORY)
     int pspace = 0;                // Davidson P-space size (CISIGMA_OPT_PSPACE)
     int thick_restart = 1;         // collapses keep the previous Ritz vectors too (CISIGMA_OPT_THICK_RESTART)
     int refine_every = 0;          // mixed mode: 0 = refine only when the FP32 iteration converges
@@ -306,6 +307,11 @@ int apply_sigma(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStre
 // the same through a captured graph (CISIGMA_OPT_GRAPH; non-NULL stream)
 int apply_sigma_graph(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
 void drop_graphs(cisigma_ctx *ctx);
+// whether one dtype's sigma workspace is allocated or its layout copies fit in
+// free memory; freeing it (synchronises the device; the next apply of that
+// dtype allocates it again)
+bool workspace_fits(cisigma_ctx *ctx, int dtype);
+int release_workspace(cisigma_ctx *ctx, int dtype);
 
 }  // namespace cis
 

@@ -88,6 +88,36 @@ def test_davidson_restarts_vs_dense(thick, prec, pspace):
     assert np.allclose(e, w[:nroots], atol=1e-8 if prec == "fp64" else 1e-6), (e - w[:nroots])
 
 
+def test_davidson_mixed_low_memory_swaps_workspaces():
+    """CISIGMA_OPT_LOW_MEMORY: the FP32 and FP64 sigma workspaces are released
+    and re-created around every refinement (forced here with a refinement every
+    8 iterations).  Same arithmetic in fresh buffers: the run matches the one
+    without the option exactly, and the dense energies; plain apply calls of
+    both precisions work afterwards."""
+    cis = _cis()
+    ctx, ref = make(8, 4, 4, seed=8)
+    w = np.linalg.eigvalsh(ref.hmat())
+    runs = []
+    for low in (0, 1):
+        ctx.set_option(cis.OPT_LOW_MEMORY, low)
+        ctx.set_option(cis.OPT_REFINE_EVERY, 8)
+        ctx.set_option(cis.OPT_MAX_ITER, 400)
+        ctx.set_option(cis.OPT_PRECISION, cis.FP32)
+        e, st, status = ctx.davidson(2, 1e-10)
+        assert status == 0 and st["refinements"] >= 2
+        assert np.allclose(e, w[:2], atol=1e-6), (e - w[:2])
+        runs.append((e, st["iterations"], st["sigma_fp32"], st["sigma_fp64"]))
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1:] == runs[1][1:], runs
+    c = si.ci_vector(ctx.ndet, 2)
+    for dt, tol in ((torch.float32, 1e-5), (torch.float64, 1e-10)):
+        C = torch.tensor(c, dtype=dt, device="cuda")
+        S = torch.empty_like(C)
+        ctx.apply(C, S)
+        torch.cuda.synchronize()
+        s_ref = ref.sigma(c)
+        assert np.linalg.norm(S.double().cpu().numpy() - s_ref) <= tol * np.linalg.norm(s_ref)
+
+
 def test_davidson_vectors_and_certificate_cas12():
     """CAS(12,12): GPU FP64 eigenvector; the oracle's sigma of it gives a
     Rayleigh quotient equal to the GPU energy and a small residual."""
