@@ -194,14 +194,17 @@ def stored_same_spin_bytes():
         return None
 
 
-def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector):
+def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector, modes, max_space):
     out = {}
     ctx.set_option(cis.OPT_MAX_ITER, max_iter)
     ctx.set_option(cis.OPT_VERBOSE, 1 if verbose else 0)
+    if max_space:
+        ctx.set_option(cis.OPT_MAX_SPACE, max_space)
     runs = [("fp64", cis.FP64, 0), ("mixed_fp32", cis.FP32, 0)]
     if sector:
         # lowest roots of the even-spin M_S = 0 sector (singlets first)
         runs.append(("mixed_fp32_even_sector", cis.FP32, 1))
+    runs = [r for r in runs if r[0] in modes]
     for mode, prec, parity in runs:
         ctx.set_option(cis.OPT_PRECISION, prec)
         ctx.set_option(cis.OPT_SPIN_PARITY, parity)
@@ -213,9 +216,10 @@ def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector):
                      "refinements": st["refinements"], "residual": st["residual"]}
         log(f"davidson {mode}: {out[mode]}")
     ctx.set_option(cis.OPT_PRECISION, cis.FP64)
-    d = [abs(a - b) for a, b in zip(out["fp64"]["energies"], out["mixed_fp32"]["energies"])]
-    out["max_abs_energy_diff_mixed_vs_fp64"] = max(d)
-    if sector:
+    if "fp64" in out and "mixed_fp32" in out:
+        d = [abs(a - b) for a, b in zip(out["fp64"]["energies"], out["mixed_fp32"]["energies"])]
+        out["max_abs_energy_diff_mixed_vs_fp64"] = max(d)
+    if "fp64" in out and "mixed_fp32_even_sector" in out:
         out["even_sector_E0_minus_full_E0"] = out["mixed_fp32_even_sector"]["energies"][0] - out["fp64"]["energies"][0]
     return out
 
@@ -235,6 +239,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=300)
     ap.add_argument("--verbose", action="store_true", help="one line per Davidson iteration on stderr")
+    ap.add_argument("--davidson-modes", default="fp64,mixed_fp32,mixed_fp32_even_sector",
+                    help="comma list of the Davidson runs: fp64, mixed_fp32, mixed_fp32_even_sector")
+    ap.add_argument("--max-space", type=int, default=0, help="Davidson subspace cap (0: the library's default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain copy kernel of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -309,7 +316,8 @@ def main():
         copy_calibration(torch, args.copy_calibration_mib)
 
     if not args.no_davidson:
-        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose, sector)
+        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose, sector,
+                                          args.davidson_modes.split(","), args.max_space)
 
     cpu = None
     if not args.no_cpu:

@@ -176,31 +176,48 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
     double rr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) rr[r] = 0;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-        double x[R], s[R];
+    // U elements per thread, blockDim apart: 2 U loads in flight per basis vector
+    constexpr int U = 4;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x * U;
+    for (int64_t n0 = int64_t(blockIdx.x) * blockDim.x * U + threadIdx.x; n0 < N; n0 += stride) {
+        double x[R][U], s[R][U];
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = s[r] = 0;
-#pragma unroll 4
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int u = 0; u < U; ++u) x[r][u] = s[r][u] = 0;
+#pragma unroll 2
         for (int i = 0; i < m; ++i) {
-            const double b = double(B[i * sv + n]), c = double(S[i * sv + n]);
+            double b[U], c[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t n = n0 + int64_t(u) * blockDim.x;
+                b[u] = n < N ? double(B[i * sv + n]) : 0.0;
+                c[u] = n < N ? double(S[i * sv + n]) : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    x[r][u] += ys[r][i] * b[u];
+                    s[r][u] += ys[r][i] * c[u];
+                }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t n = n0 + int64_t(u) * blockDim.x;
+            if (n >= N) break;
+            const double h = hd[n];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                x[r] += ys[r][i] * b;
-                s[r] += ys[r][i] * c;
+                if (r >= nr) break;
+                const double res = s[r][u] - th[r] * x[r][u];
+                rr[r] += res * res;
+                xout[r * N + n] = x[r][u];
+                sout[r * N + n] = T(s[r][u]);
+                double dd = th[r] - h;
+                if (fabs(dd) < 1e-8) dd = dd < 0 ? -1e-8 : 1e-8;
+                tout[r * N + n] = T(res / dd);
             }
-        }
-        const double h = hd[n];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            if (r >= nr) break;
-            const double res = s[r] - th[r] * x[r];
-            rr[r] += res * res;
-            xout[r * N + n] = x[r];
-            sout[r * N + n] = T(s[r]);
-            double dd = th[r] - h;
-            if (fabs(dd) < 1e-8) dd = dd < 0 ? -1e-8 : 1e-8;
-            tout[r * N + n] = T(res / dd);
         }
     }
 #pragma unroll

@@ -210,7 +210,7 @@ struct cisigma_ctx {
     int max_space = 0;
     int max_iter = 100;
     int low_memory = 0;            // swap the sigma workspaces around refinements (CISIGMA_OPT_LOW_MEMORY)
-    int pspace = 0;                // Davidson P-space size (CISIGMA_OPT_PSPACE)
+    int pspace = 256;              // Davidson P-space size (CISIGMA_OPT_PSPACE)
     int thick_restart = 1;         // collapses keep the previous Ritz vectors too (CISIGMA_OPT_THICK_RESTART)
     int refine_every = 0;          // mixed mode: 0 = refine only when the FP32 iteration converges
     double resid_tol = -1.0;
