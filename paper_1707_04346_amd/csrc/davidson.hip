@@ -420,6 +420,21 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     const int dt = mixed ? CISIGMA_FP32 : CISIGMA_FP64;
     const int64_t N = ctx->lay.ndet;
     const size_t es = sizeof(T);
+    // sigma workspaces left by earlier apply calls (their materialised same-spin
+    // rows take half of what was free) are released when the basis would not fit
+    // beside them at full size; the next sigma allocates them again, sized to
+    // what is free then
+    {
+        const int want = ctx->max_space > 0 ? ctx->max_space : std::max(8 * nroots, 32);
+        const size_t need = size_t(2 * want + 2 * nroots) * N * es + size_t(nroots + 1) * N * 8 +
+                            (mixed ? size_t(N) * 8 : 0);
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && need + (256u << 20) > size_t(0.7 * double(fr))) {
+            int rc0 = release_workspace(ctx, CISIGMA_FP32);
+            if (rc0 == CISIGMA_OK) rc0 = release_workspace(ctx, CISIGMA_FP64);
+            if (rc0) return rc0;
+        }
+    }
     int max_space = ctx->max_space;
     if (max_space <= 0) {
         // default: a generous subspace (restarts slow Davidson down on strongly
