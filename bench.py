@@ -315,10 +315,6 @@ def main():
     if args.copy_calibration_mib > 0:
         copy_calibration(torch, args.copy_calibration_mib)
 
-    if not args.no_davidson:
-        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose, sector,
-                                          args.davidson_modes.split(","), args.max_space)
-
     cpu = None
     if not args.no_cpu:
         # sigma of the benchmark vector in both precisions, checked against the oracle on its sampled rows
@@ -332,6 +328,15 @@ def main():
         cpu, errs = cpu_baseline(spec, h, g, C32, args.cpu_seconds, sig)
         extra["sigma_rel_error_vs_oracle_sampled_rows"] = errs
         log(f"cpu baseline: {cpu}; sigma errors vs oracle: {errs}")
+        del sig
+        C64 = S64 = None
+
+    if not args.no_davidson:
+        # the Davidson basis lives in the library's own allocations: hand back what torch holds
+        del C32, S32
+        torch.cuda.empty_cache()
+        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose, sector,
+                                          args.davidson_modes.split(","), args.max_space)
 
     cfg = {"workload": f"{args.workload}: {n} orbitals, {na} alpha + {nb} beta electrons"
                        + (f", GAS {spec['gas']}" if spec["gas"] else " (CAS)")
