@@ -242,6 +242,8 @@ def main():
     ap.add_argument("--davidson-modes", default="fp64,mixed_fp32,mixed_fp32_even_sector",
                     help="comma list of the Davidson runs: fp64, mixed_fp32, mixed_fp32_even_sector")
     ap.add_argument("--max-space", type=int, default=0, help="Davidson subspace cap (0: the library's default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let cisigma_autotune pick the launch parameters before timing (its report goes to extra)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain copy kernel of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -261,11 +263,21 @@ def main():
     init_s = time.perf_counter() - t0
     log(f"init {args.workload}: ndet={ctx.ndet} in {init_s:.2f} s")
 
+    tune = {}
+    if args.autotune:
+        t0 = time.perf_counter()
+        for name, prec in (("fp32", cis.FP32), ("fp64", cis.FP64)):
+            if name == "fp64" and args.no_fp64:
+                continue
+            tune[name] = ctx.autotune(prec, 3).strip().splitlines()
+            log(f"autotune {name}: {tune[name]}")
+        tune["seconds"] = time.perf_counter() - t0
+
     dt32, pp32, C32, S32 = time_sigma(ctx, cis, torch, "fp32", args.steps, args.warmup)
     ms32 = 1e3 * dt32 / args.steps
     path32 = ctx.last_path(cis.FP32)
     log(f"fp32 sigma: {ms32:.2f} ms/step, passes {pp32}, path flags {path32}")
-    extra = {"init_seconds": init_s, "fp32_pass_ms": pp32,
+    extra = {"init_seconds": init_s, "fp32_pass_ms": pp32, **({"autotune": tune} if tune else {}),
              "fp32_path": {"ab_owner_computes": bool(path32 & cis.PATH_AB_OWNER),
                            "same_spin_materialised": bool(path32 & cis.PATH_SS_MATERIALISED)}}
     # M_S = 0 sector (n_alpha = n_beta, one block): the beta-beta pass is replaced by a transpose

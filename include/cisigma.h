@@ -86,6 +86,13 @@ extern "C" {
                                       the beta-beta entry of
                                       cisigma_pass_times is then the wait for that stream after the
                                       alpha-beta pass */
+#define CISIGMA_OPT_GAS_UNIT_ORDER 16 /* launch order of the GAS owner-computes units (both precisions):
+                                      0 (default) most source tiles per row first, 1 alpha-type order,
+                                      2 most total work first, 3 heavy and light alternating; set by
+                                      cisigma_autotune per precision */
+#define CISIGMA_OPT_SS_SPLIT 17     /* column split of the grid of the same-spin kernels that scatter with
+                                      atomics (GAS spaces), 1..64; 0 (default): a heuristic; set by
+                                      cisigma_autotune */
 #define CISIGMA_OPT_LOW_MEMORY 15   /* nonzero: the mixed-precision Davidson frees the FP32 sigma workspace
                                       before each FP64 refinement and the FP64 one after it, so only one is
                                       held at a time; done anyway when the FP64 workspace does not fit in
@@ -233,6 +240,25 @@ int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void 
  * EINVAL for an index outside [0, ndet) or NULL arrays with n, m > 0.
  */
 int cisigma_hmat_block(cisigma_ctx *ctx, int n, const int64_t *rows, int m, const int64_t *cols, double *out);
+
+/*
+ * cisigma_autotune -- picks the launch parameters of cisigma_apply for this
+ * space and dtype by timing them (Sec. 3.3: the batches of the GAS partition;
+ * here their order on one GPU): for each knob in turn, every candidate value
+ * is set and reps applies of a fixed synthetic vector are timed with HIP
+ * events; the fastest value stays set.  Knobs: the launch order of the GAS
+ * owner-computes units (most source tiles per row first, alpha-type order,
+ * most total work first, heavy and light alternating) and the column split of
+ * the same-spin kernels that scatter with atomics (GAS spaces).  Results do not
+ * depend on the knobs beyond rounding order.
+ *   dtype       CISIGMA_FP32 or CISIGMA_FP64: the precision tuned
+ *   reps        timed applies per candidate, 1..100
+ *   report      host char[report_len] (may be NULL when report_len = 0): one
+ *               line per timing and per choice, NUL-terminated, truncated
+ * Synchronous; allocates two vectors for the duration of the call; drops the
+ * captured apply graphs.  EINVAL for bad arguments.
+ */
+int cisigma_autotune(cisigma_ctx *ctx, int dtype, int reps, char *report, int report_len);
 
 /*
  * cisigma_hdiag -- diagonal H_II into the device array hdiag[ndet] (FP64),

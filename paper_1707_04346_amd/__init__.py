@@ -25,6 +25,8 @@ OPT_OVERLAP = 12
 OPT_THICK_RESTART = 13
 OPT_PSPACE = 14
 OPT_LOW_MEMORY = 15
+OPT_GAS_UNIT_ORDER = 16
+OPT_SS_SPLIT = 17
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libcisigma.so is not built ({LIB_PATH}); run __graft_entry__.build()")
@@ -72,6 +74,8 @@ _lib.cisigma_apply.restype = _i32
 _lib.cisigma_apply.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.cisigma_hdiag.restype = _i32
 _lib.cisigma_hdiag.argtypes = [_vp, _vp, _vp]
+_lib.cisigma_autotune.restype = _i32
+_lib.cisigma_autotune.argtypes = [_vp, _i32, _i32, ctypes.c_char_p, _i32]
 _lib.cisigma_hmat_block.restype = _i32
 _lib.cisigma_hmat_block.argtypes = [_vp, _i32, _vp, _i32, _vp, _vp]
 _lib.cisigma_davidson.restype = _i32
@@ -90,7 +94,7 @@ _lib.cisigma_strerror.argtypes = [_i32]
 EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "cisigma_address", "cisigma_strings",
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
            "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
-           "cisigma_hmat_block"]
+           "cisigma_hmat_block", "cisigma_autotune"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -212,6 +216,13 @@ class Context:
     def hdiag(self, out, stream=None):
         self._check(_lib.cisigma_hdiag(self._h, _ptr(out), _stream_ptr(stream)))
         return out
+
+    def autotune(self, dtype=FP32, reps=3):
+        """Time the apply launch parameters of this space for dtype and keep the
+        fastest; returns the library's report (one line per timing and choice)."""
+        buf = ctypes.create_string_buffer(8192)
+        self._check(_lib.cisigma_autotune(self._h, int(dtype), int(reps), buf, len(buf)))
+        return buf.value.decode()
 
     def hmat_block(self, rows, cols):
         """H(rows[i], cols[j]) (numpy, n x m) between determinants given by vector index."""

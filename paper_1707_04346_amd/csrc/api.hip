@@ -914,6 +914,45 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     return CISIGMA_OK;
 }
 
+int gas_set_unit_order(cisigma_ctx *c, int d, int order) {
+    GasOwner &G = c->go;
+    const auto &U = G.units[d];
+    if (U.empty()) return CISIGMA_OK;
+    const auto &A = c->sp[0];
+    const size_t nu = U.size();
+    std::vector<size_t> ord(nu);
+    for (size_t k = 0; k < nu; ++k) ord[k] = k;
+    auto work = [&](size_t k) { return double(U[k].nact) * A.tcount[U[k].ta]; };
+    if (order == 1) {
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+            return U[x].ta != U[y].ta ? U[x].ta < U[y].ta : U[x].lo < U[y].lo;
+        });
+    } else if (order == 2 || order == 3) {
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return work(x) > work(y); });
+        if (order == 3) {
+            std::vector<size_t> alt;
+            for (size_t i = 0, j = nu; i < j;) {
+                alt.push_back(ord[i++]);
+                if (i < j) alt.push_back(ord[--j]);
+            }
+            ord.swap(alt);
+        }
+    }
+    std::vector<int> utab;
+    int nblk = 0;
+    for (size_t k : ord) {
+        const auto &un = U[k];
+        utab.insert(utab.end(), {un.ta, un.lo, un.hi, un.act0, un.nact, A.tstart[un.ta], nblk, 0});
+        nblk += A.tcount[un.ta];
+    }
+    HIP_OR_FAIL(c, hipDeviceSynchronize(), "unit order");
+    drop_graphs(c);
+    HIP_OR_FAIL(c, hipMemcpy(G.d_units[d], utab.data(), utab.size() * sizeof(int), hipMemcpyHostToDevice),
+                "unit order");
+    c->unit_order[d] = order;
+    return CISIGMA_OK;
+}
+
 bool workspace_fits(cisigma_ctx *c, int dtype) {
     if (c->ws[dtype == CISIGMA_FP32 ? 1 : 0].ready) return true;
     size_t fr = 0, tot = 0;
@@ -1237,6 +1276,114 @@ CIS_API int cisigma_hmat_block(cisigma_ctx *ctx, int n, const int64_t *rows, int
     return CISIGMA_OK;
 }
 
+namespace {
+__global__ void k_fill_ramp(void *x, int64_t n, int fp32) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double v = 1.0 / double(1 + (i % 977));
+        if (fp32) static_cast<float *>(x)[i] = float(v); else static_cast<double *>(x)[i] = v;
+    }
+}
+}  // namespace
+
+CIS_API int cisigma_autotune(cisigma_ctx *ctx, int dtype, int reps, char *report, int report_len) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if ((dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64) || reps < 1 || reps > 100 || (report_len > 0 && !report))
+        return cis_set_error(ctx, CISIGMA_EINVAL, "autotune: bad arguments");
+    const int d = dtype == CISIGMA_FP32 ? 1 : 0;
+    const size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
+    const int64_t N = ctx->lay.ndet;
+    const int parity = ctx->spin_parity;
+    const int graph = ctx->graph_mode, prof = ctx->profile;
+    std::string rep;
+    void *C = nullptr, *S = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto done = [&](int rc) {
+        (void)hipFree(C); (void)hipFree(S);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        ctx->spin_parity = parity; ctx->graph_mode = graph; ctx->profile = prof;
+        if (report_len > 0) {
+            const size_t n = std::min(rep.size(), size_t(report_len - 1));
+            std::memcpy(report, rep.data(), n);
+            report[n] = 0;
+        }
+        return rc;
+    };
+    // timed on a fixed vector, eager launches, no spin-parity restriction
+    ctx->spin_parity = 0; ctx->graph_mode = 0; ctx->profile = 0;
+    hipError_t e = hipMalloc(&C, size_t(std::max<int64_t>(N, 1)) * es);
+    if (e == hipSuccess) e = hipMalloc(&S, size_t(std::max<int64_t>(N, 1)) * es);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e != hipSuccess) return done(hip_fail(ctx, e, "autotune: buffers"));
+    const hipStream_t s = ctx->stream;
+    hipLaunchKernelGGL(k_fill_ramp, dim3(1024), dim3(256), 0, s, C, N, int(d == 1));
+    auto time_apply = [&](float *ms) -> int {
+        int rc = cis::apply_sigma(ctx, C, S, dtype, s);    // warm-up (allocates the workspace once)
+        if (rc) return rc;
+        HIP_OR_FAIL(ctx, hipEventRecord(e0, s), "autotune: events");
+        for (int r = 0; r < reps && rc == 0; ++r) rc = cis::apply_sigma(ctx, C, S, dtype, s);
+        if (rc) return rc;
+        HIP_OR_FAIL(ctx, hipEventRecord(e1, s), "autotune: events");
+        HIP_OR_FAIL(ctx, hipEventSynchronize(e1), "autotune: events");
+        HIP_OR_FAIL(ctx, hipEventElapsedTime(ms, e0, e1), "autotune: events");
+        *ms /= float(reps);
+        return CISIGMA_OK;
+    };
+    char line[160];
+    {
+        float ms = 0;
+        const int rc = time_apply(&ms);
+        if (rc) return done(rc);
+        std::snprintf(line, sizeof line, "as set: %.3f ms per sigma\n", double(ms));
+        rep += line;
+    }
+    // knob 1: launch order of the GAS owner units of this precision
+    if (!ctx->go.units[d].empty()) {
+        int best = ctx->unit_order[d];
+        float best_ms = 0;
+        for (int order = 0; order < 4; ++order) {
+            int rc = cis::gas_set_unit_order(ctx, d, order);
+            float ms = 0;
+            if (rc == 0) rc = time_apply(&ms);
+            if (rc) return done(rc);
+            std::snprintf(line, sizeof line, "gas_unit_order %d: %.3f ms per sigma\n", order, double(ms));
+            rep += line;
+            if (order == 0 || ms < best_ms) { best = order; best_ms = ms; }
+        }
+        int rc = cis::gas_set_unit_order(ctx, d, best);
+        if (rc) return done(rc);
+        std::snprintf(line, sizeof line, "gas_unit_order -> %d\n", best);
+        rep += line;
+    }
+    // knob 2: column split of the same-spin atomic kernels (spaces without the materialised form)
+    // (the workspace exists now: the materialised form is used exactly when its rows were allocated)
+    const bool atomic_ss = !(ctx->cas && ctx->ab_mode == 0 && ctx->ws[d].ys != nullptr);
+    if (atomic_ss && (ctx->sp[0].nel >= 2 || ctx->sp[1].nel >= 2)) {
+        int best = 0;
+        float best_ms = 0;
+        const int cands[] = {0, 1, 2, 4, 8, 16, 32};
+        for (int k = 0; k < 7; ++k) {
+            cis::drop_graphs(ctx);
+            ctx->ss_split = cands[k];
+            float ms = 0;
+            const int rc = time_apply(&ms);
+            if (rc) return done(rc);
+            std::snprintf(line, sizeof line, "same_spin_split %d%s: %.3f ms per sigma\n", cands[k],
+                          cands[k] == 0 ? " (heuristic)" : "", double(ms));
+            rep += line;
+            if (k == 0 || ms < best_ms) { best = cands[k]; best_ms = ms; }
+        }
+        cis::drop_graphs(ctx);
+        ctx->ss_split = best;
+        std::snprintf(line, sizeof line, "same_spin_split -> %d\n", best);
+        rep += line;
+    }
+    if (rep.empty()) rep = "nothing to tune for this space and precision\n";
+    return done(CISIGMA_OK);
+}
+
 CIS_API int cisigma_strings(const cisigma_ctx *ctx, int spin, uint32_t *out, int *nstr) {
     if (!ctx || !nstr || spin < 0 || spin > 1) return CISIGMA_EINVAL;
     const auto &T = ctx->sp[spin];
@@ -1298,6 +1445,17 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: same-spin chunk must be a non-negative multiple of 64");
             ctx->ss_chunk = int(value);
+            return CISIGMA_OK;
+        case CISIGMA_OPT_GAS_UNIT_ORDER: {
+            if (value < 0 || value > 3) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit order out of range");
+            int rc = cis::gas_set_unit_order(ctx, 0, int(value));
+            if (rc == CISIGMA_OK) rc = cis::gas_set_unit_order(ctx, 1, int(value));
+            return rc;
+        }
+        case CISIGMA_OPT_SS_SPLIT:
+            if (value < 0 || value > 64) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: split out of range");
+            cis::drop_graphs(ctx);
+            ctx->ss_split = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_LOW_MEMORY:
             ctx->low_memory = value != 0;

@@ -209,6 +209,8 @@ struct cisigma_ctx {
     int precision = CISIGMA_FP64;
     int max_space = 0;
     int max_iter = 100;
+    int ss_split = 0;              // same-spin atomic kernels: column split of the grid (0: heuristic; autotuned)
+    int unit_order[2] = {0, 0};    // GAS owner units' launch order per precision ([0] FP64, [1] FP32; autotuned)
     int low_memory = 0;            // swap the sigma workspaces around refinements (CISIGMA_OPT_LOW_MEMORY)
     int pspace = 256;              // Davidson P-space size (CISIGMA_OPT_PSPACE)
     int thick_restart = 1;         // collapses keep the previous Ritz vectors too (CISIGMA_OPT_THICK_RESTART)
@@ -311,6 +313,10 @@ void drop_graphs(cisigma_ctx *ctx);
 // free memory; freeing it (synchronises the device; the next apply of that
 // dtype allocates it again)
 bool workspace_fits(cisigma_ctx *ctx, int dtype);
+// launch order of the GAS owner units of one precision: 0 most source tiles per
+// row first (as built), 1 alpha type order, 2 most total work first, 3 heavy
+// and light alternating; rewrites the device unit table
+int gas_set_unit_order(cisigma_ctx *ctx, int d, int order);
 int release_workspace(cisigma_ctx *ctx, int dtype);
 
 }  // namespace cis

@@ -44,6 +44,7 @@ struct SsArgs {
     T *Ys;
     int64_t ldy;
     int tile_begin, tile_end, col_begin;
+    int ysplit;                 // column split of the grid (0: heuristic)
 };
 
 template <typename T, int KS, int MBL, bool STORE>
@@ -413,6 +414,7 @@ hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
     const int items = (STORE ? a.tile_end - a.tile_begin : a.ntiles) * (kTileCols / TW);
     int ysplit = 1;
     while (int64_t(a.nK) * ysplit < 2048 && 4 * ysplit < items) ysplit *= 2;
+    if (a.ysplit > 0) ysplit = a.ysplit;
     hipLaunchKernelGGL((k_sigma_ss<T, KS, MBL, STORE>), dim3(a.nK, ysplit), dim3(256), lds, s, a);
     return hipGetLastError();
 }
@@ -497,6 +499,7 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
     a.nps = ctx->nps;
     a.nto = ctx->sp[other].ntype;
     a.ntiles = L.ntiles;
+    a.ysplit = ctx->ss_split;
     if (!Ys) {
         if (ss_shape_compiled(S.npv)) return dispatch_ss<T, false>(a, s);
         int ysplit = 1;

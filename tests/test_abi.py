@@ -48,6 +48,7 @@ def test_strerror_and_null_handling():
     assert lib.cisigma_apply(None, None, None, 0, None) == cis.EINVAL
     assert lib.cisigma_davidson(None, 1, 1e-8, None, None, None) == cis.EINVAL
     assert lib.cisigma_hmat_block(None, 0, None, 0, None, None) == cis.EINVAL
+    assert lib.cisigma_autotune(None, cis.FP32, 1, None, 0) == cis.EINVAL
     assert b"NULL" in lib.cisigma_last_error(None)
     h = ctypes.c_void_p()
     # bad sizes are rejected before any device work
