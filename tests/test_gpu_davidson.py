@@ -88,6 +88,22 @@ def test_davidson_restarts_vs_dense(thick, prec, pspace):
     assert np.allclose(e, w[:nroots], atol=1e-8 if prec == "fp64" else 1e-6), (e - w[:nroots])
 
 
+@pytest.mark.parametrize("case", [(4, 2, 2, 2), (5, 2, 3, 3), (2, 1, 1, 1)], ids=["cas4", "n5a2b3", "n2"])
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_davidson_pspace_covers_the_space(case, prec):
+    """Spaces smaller than the P-space: the guess is already exact, the
+    corrections vanish, and the driver still ends with the dense eigenvalues."""
+    norb, na, nb, nroots = case
+    cis = _cis()
+    ctx, ref = make(norb, na, nb, seed=5)
+    w = np.linalg.eigvalsh(ref.hmat())
+    assert ctx.ndet <= 256
+    ctx.set_option(cis.OPT_PRECISION, cis.FP64 if prec == "fp64" else cis.FP32)
+    e, st, status = ctx.davidson(nroots, 1e-10)
+    assert status == 0
+    assert np.allclose(e, w[:nroots], atol=1e-8 if prec == "fp64" else 1e-6), (e - w[:nroots])
+
+
 def test_davidson_mixed_low_memory_swaps_workspaces():
     """CISIGMA_OPT_LOW_MEMORY: the FP32 and FP64 sigma workspaces are released
     and re-created around every refinement (forced here with a refinement every
