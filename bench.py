@@ -62,16 +62,27 @@ def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0, parity=0):
     dt = time.perf_counter() - t0
     passes, ncalls = ctx.pass_times()
     ctx.set_option(cis.OPT_PROFILE, 0)
-    ctx.set_option(cis.OPT_SPIN_PARITY, 0)
     assert ncalls == steps
     per_pass = {k: v / ncalls for k, v in passes.items()}
+    # the same number of steps once more, each between two events on the stream it runs on
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for k in range(steps):
+        ctx.apply(C, S)
+        ev[k + 1].record()
+    torch.cuda.synchronize()
+    step_ms = sorted(ev[k].elapsed_time(ev[k + 1]) for k in range(steps))
+    per_pass["step_median"] = step_ms[len(step_ms) // 2]
+    per_pass["step_min"] = step_ms[0]
+    ctx.set_option(cis.OPT_SPIN_PARITY, 0)
     return dt, per_pass, C, S
 
 
 def cpu_baseline(spec, h, g, C_dev, target_s, gpu_sigmas):
-    """The oracle's row-sampled sigma of the benchmark vector, timed; the same
-    rows also give the GPU sigma errors against the oracle (gpu_sigmas: name ->
-    device sigma of the same vector), returned as a second value."""
+    """The oracle's row-sampled sigma of the benchmark vector, timed on all its
+    threads and, for a few seconds, on one; the same rows also give the GPU
+    sigma errors against the oracle (gpu_sigmas: name -> device sigma of the
+    same vector).  Returns (baseline, errors, one-thread sigma builds/s)."""
     import numpy as np
     import oracle
     sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
@@ -97,11 +108,33 @@ def cpu_baseline(spec, h, g, C_dev, target_s, gpu_sigmas):
     for name, S in gpu_sigmas.items():
         got = S[idx].double().cpu().numpy()
         errs[name] = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    return {"value": rows_per_s / sp.ndet, "unit": "sigma builds/s", "cores": oracle.max_threads(),
+    # the same sampling on one thread, for a few seconds
+    nthreads = oracle.max_threads()
+    oracle.set_threads(1)
+    try:
+        rows1 = rng.integers(0, sp.ndet, 256)
+        t0 = time.perf_counter()
+        n1 = 0
+        while time.perf_counter() - t0 < min(3.0, target_s):
+            sp.sigma_rows(rows1, c)
+            n1 += rows1.size
+        rate1 = n1 / (time.perf_counter() - t0)
+    finally:
+        oracle.set_threads(nthreads)
+    one_thread = rate1 / sp.ndet
+    model = "unknown CPU"
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": rows_per_s / sp.ndet, "unit": "sigma builds/s", "cores": nthreads,
             "kind": "oracle",
-            "sample": f"{done} random output determinants of the same CAS vector through the oracle's "
-                      f"row-sampled Slater-Condon sigma ({t_used:.1f} s, {rows_per_s:.0f} rows/s), scaled to "
-                      f"the {sp.ndet} rows of one sigma build"}, errs
+            "sample": f"{done} random output determinants of the same {sp.ndet}-determinant vector through "
+                      f"the oracle's row-sampled Slater-Condon sigma ({t_used:.1f} s, {rows_per_s:.0f} rows/s "
+                      f"on {nthreads} threads of {model}), scaled to the {sp.ndet} rows of one sigma build"}, errs, one_thread
 
 
 def copy_calibration(torch, mib):
@@ -337,8 +370,9 @@ def main():
             ctx.apply(C64, S64)
             torch.cuda.synchronize()
             sig["fp64"] = S64
-        cpu, errs = cpu_baseline(spec, h, g, C32, args.cpu_seconds, sig)
+        cpu, errs, one_thread = cpu_baseline(spec, h, g, C32, args.cpu_seconds, sig)
         extra["sigma_rel_error_vs_oracle_sampled_rows"] = errs
+        extra["oracle_one_thread_sigma_builds_per_s"] = one_thread
         log(f"cpu baseline: {cpu}; sigma errors vs oracle: {errs}")
         del sig
         C64 = S64 = None
