@@ -120,6 +120,10 @@ extern "C" {
                                       cisigma_apply and cisigma_davidson to vectors with
                                       C(Ib, Ia) = p C(Ia, Ib) (p = +1: even total spin S, singlets first;
                                       p = -1: odd S), which drops the beta-beta pass; 0 (default): none.
+                                      H conserves S^2 and the Davidson guess is built on the lowest
+                                      diagonal elements, so a sector run can miss a root of a spin its
+                                      guess lacks (a quintet below the lowest singlet): ask for more
+                                      roots to include such states.
                                       Needs nalpha = nbeta (EINVAL otherwise) and a one-block (CAS)
                                       space (EUNSUPPORTED for GAS spaces) */
 
