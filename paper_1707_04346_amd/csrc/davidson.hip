@@ -255,29 +255,61 @@ __global__ __launch_bounds__(256) void k_subtract(const T *X, int64_t sx, int nx
     }
 }
 
-// V_j <- sum_i q[j * m + i] V_i for j < k <= kThick, in place: every thread
-// reads element n of all m vectors before it writes element n of the first k
-template <typename T>
+// V_j <- sum_i q[j * m + i] V_i for j < k <= KM, in place: every thread reads
+// element n of all m vectors before it writes element n of the first k (U
+// elements per thread, blockDim apart, for more loads in flight)
+template <typename T, int KM>
 __global__ __launch_bounds__(256) void k_combine_inplace(T *V, int64_t sv, int m, const double *q, int k, int64_t N) {
-    extern __shared__ double qs[];
-    for (int i = threadIdx.x; i < k * m; i += blockDim.x) qs[i] = q[i];
+    constexpr int U = KM <= 8 ? 4 : 2;
+    extern __shared__ double qs[];                       // [m][KM], zero beyond k
+    for (int i = threadIdx.x; i < m * KM; i += blockDim.x) {
+        const int row = i / KM, j = i % KM;
+        qs[i] = j < k ? q[j * m + row] : 0.0;
+    }
     __syncthreads();
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-        double acc[kThick];
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x * U;
+    for (int64_t n0 = int64_t(blockIdx.x) * blockDim.x * U + threadIdx.x; n0 < N; n0 += stride) {
+        double acc[KM][U];
 #pragma unroll
-        for (int j = 0; j < kThick; ++j) acc[j] = 0;
-#pragma unroll 4
+        for (int j = 0; j < KM; ++j)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[j][u] = 0;
         for (int i = 0; i < m; ++i) {
-            const double v = double(V[i * sv + n]);
+            double v[U];
 #pragma unroll
-            for (int j = 0; j < kThick; ++j)
-                if (j < k) acc[j] += qs[j * m + i] * v;
+            for (int u = 0; u < U; ++u) {
+                const int64_t n = n0 + int64_t(u) * blockDim.x;
+                v[u] = n < N ? double(V[i * sv + n]) : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < KM; ++j) {
+                const double c = qs[i * KM + j];
+#pragma unroll
+                for (int u = 0; u < U; ++u) acc[j][u] += c * v[u];
+            }
         }
 #pragma unroll
-        for (int j = 0; j < kThick; ++j)
-            if (j < k) V[j * sv + n] = T(acc[j]);
+        for (int u = 0; u < U; ++u) {
+            const int64_t n = n0 + int64_t(u) * blockDim.x;
+            if (n >= N) break;
+#pragma unroll
+            for (int j = 0; j < KM; ++j)
+                if (j < k) V[j * sv + n] = T(acc[j][u]);
+        }
     }
+}
+
+template <typename T>
+void launch_combine(T *V, int64_t sv, int m, const double *q, int k, int64_t N, int g, hipStream_t s) {
+    if (k <= 4)
+        hipLaunchKernelGGL((k_combine_inplace<T, 4>), dim3(g), dim3(256), size_t(m) * 4 * sizeof(double), s, V, sv,
+                           m, q, k, N);
+    else if (k <= 8)
+        hipLaunchKernelGGL((k_combine_inplace<T, 8>), dim3(g), dim3(256), size_t(m) * 8 * sizeof(double), s, V, sv,
+                           m, q, k, N);
+    else
+        hipLaunchKernelGGL((k_combine_inplace<T, kThick>), dim3(g), dim3(256), size_t(m) * kThick * sizeof(double),
+                           s, V, sv, m, q, k, N);
 }
 
 template <typename TI, typename TO>
@@ -788,9 +820,8 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             }
             if (k > nroots) {
                 DV_TRY(hipMemcpyAsync(d.qbuf, Q.data(), size_t(k) * m * sizeof(double), hipMemcpyHostToDevice, d.s));
-                const size_t lq = size_t(k) * m * sizeof(double);
-                hipLaunchKernelGGL((k_combine_inplace<T>), dim3(g), dim3(256), lq, d.s, B, N, m, d.qbuf, k, N);
-                hipLaunchKernelGGL((k_combine_inplace<T>), dim3(g), dim3(256), lq, d.s, S, N, m, d.qbuf, k, N);
+                launch_combine<T>(B, N, m, d.qbuf, k, N, g, d.s);
+                launch_combine<T>(S, N, m, d.qbuf, k, N, g, d.s);
                 DV_TRY(hipGetLastError());
                 std::vector<double> GQ(size_t(m) * k, 0.0);
                 for (int i = 0; i < m; ++i)
