@@ -172,6 +172,25 @@ def test_apply_on_a_side_stream():
     assert rel(S.cpu().numpy(), s_ref) <= TOL64
 
 
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_cas_sigma_is_bitwise_reproducible(dtype):
+    """One-block spaces take the owner-computes alpha-beta kernel (fixed scatter
+    plan) and the materialised same-spin form (plain stores, fixed gather
+    order): no atomics, so repeated applies agree bit for bit."""
+    cis = _cis()
+    ctx, _ = make(10, 5, 5, seed=3)
+    c = si.ci_vector(ctx.ndet, 4)
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S1, S2 = torch.empty_like(C), torch.empty_like(C)
+    ctx.apply(C, S1)
+    for _ in range(3):
+        ctx.apply(C, S2)
+        torch.cuda.synchronize()
+        assert torch.equal(S1, S2)
+    prec = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert ctx.last_path(prec) == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
+
+
 @pytest.mark.parametrize("case", [(8, 4, 4), (9, 5, 4), (10, 5, 5)], ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
 def test_overlap_option_matches_oracle(case, dtype):
