@@ -6,6 +6,10 @@
 //
 //   R(a, Jb)  = C(Ja_a, Jb)        a = the single alpha excitations Ja_a of Ia, plus Ia itself
 //   W(kl, Jb) = sum_a A(kl, a) R(a, Jb),  A(kl, a) = s_a (i_a j_a|kl),  A(kl, Ia) = sum_{j in Ia} (jj|kl)
+//
+// Ia's own row either takes a k slot of the matrix product (SELF) or, when the
+// excitations alone fill whole k steps, starts the accumulators as the rank-1
+// term A(kl, Ia) C(Ia, Jb) (one k step fewer: 16 instead of 17 at CAS(16,16)).
 //   sigma(Ia, Ib) += sum_{(kl, Jb): Ib = E_kl Jb} <Ib|E_kl|Jb> W(kl, Jb)
 //
 // (kl runs over unordered pairs k >= l: E_kl and E_lk share the integral.)
@@ -47,10 +51,22 @@ struct AbxArgs {
 // lane and tile.  A producing wave owns one 16-column half of the 32-column
 // tile (cb) and a run of row blocks [rb0, rb0 + nrb).
 
+// A(m, Ia) = sum_{j in Ia} (jj|kl) for the kl pair of row m
+template <typename T>
+__device__ __forceinline__ T abx_self_coef(const AbxArgs<T> &p, uint32_t xa, int m) {
+    T val = 0;
+    for (uint32_t b = xa; b; b &= b - 1) {
+        const int j = __ffs(b) - 1;
+        val += p.gp[int64_t(j * p.n + j) * p.kp + m];
+    }
+    return val;
+}
+
 // A fragments of Ia for the wave's row blocks -- row m (kl) = 16*(rb0 + r) +
 // lane%16, column k = 4t + lane/16 -- and the byte offsets of the gathered rows
-// (missing excitations read the zero row Na).
-template <typename T, int KS, int RBW>
+// (missing excitations read the zero row Na).  With SELF, column anexc is Ia's
+// own row.
+template <typename T, int KS, int RBW, bool SELF>
 __device__ __forceinline__ void abx_fragments(const AbxArgs<T> &p, int Ia, int lane, int cb, int rb0, int nrb,
                                               T (&A)[RBW][KS], uint32_t (&boff)[KS]) {
     const uint32_t xa = p.astr[Ia];
@@ -69,7 +85,7 @@ __device__ __forceinline__ void abx_fragments(const AbxArgs<T> &p, int Ia, int l
                 g = p.gp + int64_t(i * p.n + j) * p.kp;
                 sg = (e & 1) ? T(-1) : T(1);
             }
-        } else if (k == p.anexc) {
+        } else if (SELF && k == p.anexc) {
             J = Ia;
         }
         boff[t] = (uint32_t(J) * uint32_t(p.ld) + col) * uint32_t(sizeof(T));   // < cp_bytes
@@ -80,16 +96,30 @@ __device__ __forceinline__ void abx_fragments(const AbxArgs<T> &p, int Ia, int l
             if (r < nrb && m < p.npair) {
                 if (g) {
                     val = sg * g[m];
-                } else if (k == p.anexc) {
-                    for (uint32_t b = xa; b; b &= b - 1) {
-                        const int j = __ffs(b) - 1;
-                        val += p.gp[int64_t(j * p.n + j) * p.kp + m];
-                    }
+                } else if (SELF && k == p.anexc) {
+                    val = abx_self_coef(p, xa, m);
                 }
             }
             A[r][t] = val;
         }
     }
+}
+
+// Without SELF: A(m, Ia) for the lane's accumulator rows m = 16*(rb0 + r) +
+// out_row(lane, i), and the byte offset of C(Ia, column) of the lane's column
+template <typename T, int RBW>
+__device__ __forceinline__ void abx_self_fragments(const AbxArgs<T> &p, int Ia, int lane, int cb, int rb0, int nrb,
+                                                   T (&dI)[RBW][4], uint32_t &boffI) {
+    using M = Mfma<T>;
+    const uint32_t xa = p.astr[Ia];
+#pragma unroll
+    for (int r = 0; r < RBW; ++r)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = (rb0 + r) * 16 + M::out_row(lane, i);
+            dI[r][i] = (r < nrb && m < p.npair) ? abx_self_coef(p, xa, m) : T(0);
+        }
+    boffI = (uint32_t(Ia) * uint32_t(p.ld) + uint32_t(cb * 16 + (lane & 15))) * uint32_t(sizeof(T));   // < cp_bytes
 }
 
 template <typename T, int KS>
@@ -101,15 +131,25 @@ __device__ __forceinline__ void abx_load(__amdgpu_buffer_rsrc_t cr, const uint32
 
 // W = A R on the matrix cores for the rows held in b; as each k step is
 // consumed, b[t] is reloaded with the rows of tile `next` (always a valid
-// tile), so the loads stay in flight for a whole tile.
-template <typename T, int KS, int RBW>
+// tile), so the loads stay in flight for a whole tile.  Without SELF the
+// accumulators start from A(kl, Ia) C(Ia, Jb), cI holding C(Ia, Jb) of this
+// tile (reloaded likewise).
+template <typename T, int KS, int RBW, bool SELF>
 __device__ __forceinline__ void abx_products(__amdgpu_buffer_rsrc_t cr, const T (&A)[RBW][KS],
                                              const uint32_t (&boff)[KS], int next, T (&b)[KS],
-                                             typename Mfma<T>::acc_t (&acc)[RBW]) {
+                                             typename Mfma<T>::acc_t (&acc)[RBW], const T (&dI)[RBW][4],
+                                             uint32_t boffI, T &cI) {
     using M = Mfma<T>;
     const uint32_t soff = uint32_t(next) * uint32_t(kAbxNT * sizeof(T));
+    if constexpr (SELF) {
 #pragma unroll
-    for (int r = 0; r < RBW; ++r) acc[r] = typename M::acc_t{0, 0, 0, 0};
+        for (int r = 0; r < RBW; ++r) acc[r] = typename M::acc_t{0, 0, 0, 0};
+    } else {
+#pragma unroll
+        for (int r = 0; r < RBW; ++r)
+            acc[r] = typename M::acc_t{dI[r][0] * cI, dI[r][1] * cI, dI[r][2] * cI, dI[r][3] * cI};
+        buffer_ld(cI, cr, boffI, soff);
+    }
 #pragma unroll
     for (int t = 0; t < KS; ++t) {
 #pragma unroll
@@ -137,7 +177,7 @@ __device__ __forceinline__ void abx_store_w(T *W, const typename Mfma<T>::acc_t 
 // the other six multiply), but the FP64 sigma row leaves room for one W tile
 // only: the producing waves compute the next tile's W in registers while the
 // scatter waves consume this tile's, and store it between two barriers.
-template <typename T, int KS, int RB, int EW>
+template <typename T, int KS, int RB, int EW, bool SELF>
 __global__ __launch_bounds__(512, 1) void k_sigma_ab_x(AbxArgs<T> p) {
     using acc_t = typename Mfma<T>::acc_t;
     using vec_t = typename Mfma<T>::vec_t;
@@ -163,19 +203,24 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_x(AbxArgs<T> p) {
         const int nrb = RB - rb0 < RBW ? RB - rb0 : RBW;   // may be <= 0 for small RB
         T A[RBW][KS];
         uint32_t boff[KS];
-        abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        abx_fragments<T, KS, RBW, SELF>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        T dI[RBW][4] = {};
+        uint32_t boffI = 0;
+        if constexpr (!SELF) abx_self_fragments<T, RBW>(p, Ia, lane, cb, rb0, nrb, dI, boffI);
         const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes);
         T b[KS];
+        T cI = 0;
         acc_t acc[RBW];
         abx_load<T, KS>(cr, boff, 0, b);
-        abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
+        if constexpr (!SELF) buffer_ld(cI, cr, boffI, 0u);
+        abx_products<T, KS, RBW, SELF>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc, dI, boffI, cI);
         __syncthreads();                       // the sigma row is in LDS
         abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
         __syncthreads();                       // W of tile 0 ready
         for (int tile = 0; tile < ntile; ++tile) {
             if (tile + 1 < ntile) {
                 const int t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
-                abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);
+                abx_products<T, KS, RBW, SELF>(cr, A, boff, t2, b, acc, dI, boffI, cI);
             }
             __syncthreads();                   // W of this tile consumed
             if (tile + 1 < ntile) abx_store_w<T, RBW>(W, acc, lane, cb, rb0, nrb);
@@ -225,7 +270,7 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_x(AbxArgs<T> p) {
 // 4-6 compute W of tile t+1 into one of two W buffers while waves 3 and 7
 // scatter tile t from the other; one barrier per tile.  LDS: two W tiles and
 // the sigma row (~88 KB for CAS(16,16)).
-template <typename T, int KS, int RB, int EW>
+template <typename T, int KS, int RB, int EW, bool SELF>
 __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
     using acc_t = typename Mfma<T>::acc_t;
     using vec_t = typename Mfma<T>::vec_t;
@@ -253,18 +298,23 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         const int nrb = RB - rb0 < RBW ? RB - rb0 : RBW;   // may be <= 0 for small RB
         T A[RBW][KS];
         uint32_t boff[KS];
-        abx_fragments<T, KS, RBW>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        abx_fragments<T, KS, RBW, SELF>(p, Ia, lane, cb, rb0, nrb, A, boff);
+        T dI[RBW][4] = {};
+        uint32_t boffI = 0;
+        if constexpr (!SELF) abx_self_fragments<T, RBW>(p, Ia, lane, cb, rb0, nrb, dI, boffI);
         const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes);
         T b[KS];
+        T cI = 0;
         acc_t acc[RBW];
         abx_load<T, KS>(cr, boff, 0, b);
-        abx_products<T, KS, RBW>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc);
+        if constexpr (!SELF) buffer_ld(cI, cr, boffI, 0u);
+        abx_products<T, KS, RBW, SELF>(cr, A, boff, ntile > 1 ? 1 : 0, b, acc, dI, boffI, cI);
         abx_store_w<T, RBW>(W0, acc, lane, cb, rb0, nrb);
         __syncthreads();                       // W of tile 0 ready
         for (int tile = 0; tile < ntile; ++tile) {
             if (tile + 1 < ntile) {
                 const int t2 = tile + 2 < ntile ? tile + 2 : ntile - 1;
-                abx_products<T, KS, RBW>(cr, A, boff, t2, b, acc);
+                abx_products<T, KS, RBW, SELF>(cr, A, boff, t2, b, acc, dI, boffI, cI);
                 abx_store_w<T, RBW>((tile + 1) & 1 ? W1 : W0, acc, lane, cb, rb0, nrb);
             }
             __syncthreads();
@@ -308,20 +358,20 @@ size_t abx_lds(int ld, int rb) {
     return (nw * 16 * rb * kAbxWS + ld + 64) * sizeof(T);
 }
 
-template <typename T, int KS, int RB, int EW>
+template <typename T, int KS, int RB, int EW, bool SELF>
 hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s) {
     const size_t lds = abx_lds<T>(a.ld, RB);
-    if (lds > 160 * 1024 || 16 * RB < a.npair || 4 * KS < a.anexc + 1) return hipErrorInvalidValue;
+    if (lds > 160 * 1024 || 16 * RB < a.npair || 4 * KS < a.anexc + (SELF ? 1 : 0)) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_ws<T, KS, RB, EW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_ws<T, KS, RB, EW, SELF>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_sigma_ab_ws<T, KS, RB, EW>), dim3(a.Na), dim3(512), lds, s, a);
+        hipLaunchKernelGGL((k_sigma_ab_ws<T, KS, RB, EW, SELF>), dim3(a.Na), dim3(512), lds, s, a);
     } else {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RB, EW>),
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RB, EW, SELF>),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW>), dim3(a.Na), dim3(512), lds, s, a);
+        hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW, SELF>), dim3(a.Na), dim3(512), lds, s, a);
     }
     return hipGetLastError();
 }
@@ -338,6 +388,13 @@ int rb_of(int npair) { return (npair + 15) / 16; }
     X(8, 5, 6) X(8, 5, 16) X(10, 5, 6) X(10, 5, 16) X(11, 6, 8) X(11, 6, 16) X(13, 7, 8) X(13, 7, 16)   \
     X(15, 8, 10) X(15, 8, 16) X(17, 9, 10) X(17, 9, 16)
 
+// Shapes with Ia's row as the rank-1 start of the accumulators, for the
+// CAS(n, n/2) spaces of even n and their neighbours whose excitation count is
+// a multiple of 4 (there it saves a k step; elsewhere the row fills padding)
+#define CIS_ABX_SHAPES_R1(X)                                                                           \
+    X(1, 1, 2) X(1, 1, 16) X(2, 2, 2) X(2, 2, 16) X(4, 3, 4) X(4, 3, 16) X(6, 4, 4) X(6, 4, 16)         \
+    X(9, 5, 6) X(9, 5, 16) X(12, 7, 8) X(12, 7, 16) X(16, 9, 10) X(16, 9, 16)
+
 int width_for(int ks, int rb, int need) {
     int best = 0;
 #define CIS_W(K, R, E) if (ks == K && rb == R && E >= need && (best == 0 || E < best)) best = E;
@@ -348,9 +405,17 @@ int width_for(int ks, int rb, int need) {
 
 template <typename T>
 bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err) {
-    const int ks = ks_of(a.anexc), rb = rb_of(a.npair);
+    const int rb = rb_of(a.npair);
+    if (a.anexc > 0 && a.anexc % 4 == 0) {
+        const int ks1 = a.anexc / 4;
+#define CIS_RUN1(K, R, E) \
+    if (ks1 == K && rb == R && ew == E) { *err = run_abx<T, K, R, E, false>(a, s); return true; }
+        CIS_ABX_SHAPES_R1(CIS_RUN1)
+#undef CIS_RUN1
+    }
+    const int ks = ks_of(a.anexc);
 #define CIS_RUN(K, R, E) \
-    if (ks == K && rb == R && ew == E) { *err = run_abx<T, K, R, E>(a, s); return true; }
+    if (ks == K && rb == R && ew == E) { *err = run_abx<T, K, R, E, true>(a, s); return true; }
     CIS_ABX_SHAPES(CIS_RUN)
 #undef CIS_RUN
     return false;
