@@ -249,6 +249,46 @@ def test_cas_takes_the_fast_paths(case, dtype):
     assert rel(s, ref.sigma(c)) <= tol
 
 
+# One-block spaces whose alpha excitation count n_a (n - n_a) is a multiple of 4
+# start the alpha-beta accumulators from the rank-1 term of Ia's own row
+# instead of giving that row a k step: one space per compiled shape of that
+# form not already run above (n = 8, 12 there; n = 16 in the full-size tests).
+@pytest.mark.parametrize("case", [(4, 2, 2), (6, 2, 3), (10, 4, 5)], ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_rank1_self_row_shapes(case, dtype):
+    cis = _cis()
+    norb, na, nb = case
+    ctx, ref = make(norb, na, nb, seed=17)
+    c = si.ci_vector(ctx.ndet, 18)
+    s = gpu_sigma(ctx, c, dtype)
+    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) & cis.PATH_AB_OWNER
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert rel(s, ref.sigma(c)) <= tol
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_rank1_self_row_cas14_sampled(dtype):
+    """14 orbitals, 6 alpha + 7 beta electrons (3003 x 3432 determinants, 48
+    alpha excitations): 2048 random rows plus the ends of the first and last
+    alpha rows and of their first and last 32-column tiles, against the oracle."""
+    cis = _cis()
+    ctx, ref = make(14, 6, 7, seed=19)
+    c = si.ci_vector(ctx.ndet, 20)
+    nb = 3432
+    extra = [0, 31, 32, nb - 32, nb - 1, ctx.ndet - nb, ctx.ndet - nb + 31, ctx.ndet - 1]
+    rng = np.random.default_rng(22)
+    rows = np.unique(np.concatenate([rng.integers(0, ctx.ndet, 2048), np.array(extra)])).astype(np.int64)
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S = torch.empty_like(C)
+    ctx.apply(C, S)
+    torch.cuda.synchronize()
+    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) & cis.PATH_AB_OWNER
+    got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
+    want = ref.sigma_rows(rows, c)
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert rel(got, want) <= tol
+
+
 @pytest.mark.parametrize("case", [(7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])),
                                   (8, 3, 4, ([3, 5], [5, 7], [6, 7])),
                                   (6, 3, 3, ([2, 2, 2], [0, 0, 6], [6, 6, 6]))], ids=["gas7", "gas8", "gas6open"])
