@@ -7,7 +7,11 @@ Prints one JSON line with
   * value: sigma builds/s of the FP32 path (FP32 MFMA, FP32 accumulation);
   * roofline: the alpha-beta contraction kernel (the dominant one) against the
     FP32 matrix-core peak, its duration measured with HIP events on its own
-    stream over the timed region;
+    stream over the timed region; its numerator is the method's own work, the
+    sparse minimum 2 * sum over determinants of (alpha single excitations) x
+    (beta single excitations) whose source determinant is in the space
+    (2 [n_a (n - n_a + 1)]^2 N_det for a CAS), not the products the kernel
+    issues (those are reported beside it as issued_flops);
   * cpu_baseline: the CPU oracle (plain Slater-Condon sigma) on a bounded
     random sample of output determinants of the same workload, scaled to
     sigma builds/s;
@@ -16,7 +20,12 @@ Prints one JSON line with
     converge the Davidson energies (3 roots) in FP64 and in mixed precision
     (FP32 sigma and basis, FP64 projected problem and final refinement), with
     the largest energy difference between the two, plus mixed precision in the
-    even sector.
+    even sector; every Davidson eigenvector is checked against the oracle's
+    sigma on sampled rows (energy_check_vs_oracle: sampled residual norm scaled
+    to the whole vector and the energy error bound it implies);
+  * extra.workloads: the GAS(20,20) space (FP32 and FP64 sigma, per pass) and
+    the CAS(18,18) space (FP32 sigma), each with its sigma_3 fraction of peak on
+    the same sparse-minimum numerator.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cas16]
 """
@@ -35,6 +44,80 @@ HBM_PEAK = 8000.0                         # GB/s
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def sigma3_min_products(spec):
+    """(alpha excitation, beta excitation) products per sigma_3: for every
+    determinant (I_a, I_b) of the space, the number of pairs (single excitation
+    of I_a incl. E_kk, single excitation of I_b incl. E_kk) whose source
+    determinant is in the space (Sec. 3.1: blocks of occupation types).  Counted
+    per block from the occupation types alone; returns (products, ndet)."""
+    import math
+    n, na, nb = spec["norb"], spec["nalpha"], spec["nbeta"]
+    gn, mn, mx = spec["gas"] if spec["gas"] else ([n], [na + nb], [na + nb])
+    G = len(gn)
+
+    def tuples(ne):
+        out = []
+
+        def rec(g, left, cur):
+            if g == G:
+                if left == 0:
+                    out.append(tuple(cur))
+                return
+            for k in range(min(gn[g], left) + 1):
+                rec(g + 1, left - k, cur + [k])
+        rec(0, ne, [])
+        return out
+
+    def allowed(ta, tb):
+        c = 0
+        for g in range(G):
+            c += ta[g] + tb[g]
+            if c < mn[g] or c > mx[g]:
+                return False
+        return True
+
+    def moves(t):
+        # single excitations of a string of type t, grouped by source type:
+        # electron from space gi to space gj (gi == gj includes the k == l terms)
+        res = []
+        for gi in range(G):
+            for gj in range(G):
+                c = t[gi] * (gn[gi] - t[gi] + 1) if gi == gj else t[gi] * (gn[gj] - t[gj])
+                if c:
+                    s = list(t)
+                    s[gi] -= 1
+                    s[gj] += 1
+                    res.append((tuple(s), c))
+        return res
+
+    count = lambda t: math.prod(math.comb(gn[g], t[g]) for g in range(G))
+    tot = ndet = 0
+    for ta in tuples(na):
+        for tb in tuples(nb):
+            if not allowed(ta, tb):
+                continue
+            nd = count(ta) * count(tb)
+            ndet += nd
+            tot += nd * sum(ca * cb for sa, ca in moves(ta) for sb, cb in moves(tb) if allowed(sa, sb))
+    return tot, ndet
+
+
+def same_spin_floors(spec, ndet, w):
+    """Floors of one same-spin pass of a one-block space (spin alpha; the beta
+    pass is the same with the spins exchanged for n_a = n_b): compulsory HBM
+    bytes (C read + sigma read-modify-write, 3 N_det w) at 8 TB/s, and the
+    VALU flops of the sparse string Hamiltonian (2 N_a nnz N_b, nnz = 1 +
+    n_a (n - n_a) + C(n_a, 2) C(n - n_a, 2) per row) at the FP32 or FP64 peak."""
+    import math
+    n, na, nb = spec["norb"], spec["nalpha"], spec["nbeta"]
+    nnz = 1 + na * (n - na) + math.comb(na, 2) * math.comb(n - na, 2)
+    nstr_a = math.comb(n, na)
+    flops = 2.0 * nstr_a * nnz * (ndet // nstr_a)
+    byt = 3.0 * ndet * w
+    return {"compulsory_bytes": byt, "hbm_floor_ms": byt / (HBM_PEAK * 1e9) * 1e3, "valu_flops": flops,
+            "valu_floor_ms": flops / ((PEAK["fp32"] if w == 4 else PEAK["fp64"]) * 1e12) * 1e3}
 
 
 def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0, parity=0):
@@ -227,7 +310,41 @@ def stored_same_spin_bytes():
         return None
 
 
-def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector, modes, max_space):
+def cpu_leg_energy_check(spec, h, g, vecs, energies, nrows, seed, full_space=True):
+    """Part of the CPU-oracle leg: the oracle's sigma (plain Slater-Condon, FP64)
+    of each returned eigenvector x on nrows random determinants.  Per root the
+    residual r = H x - E x on those rows, scaled to the whole vector,
+    ||r|| ~ sqrt(N_det / nrows * sum_rows r_i^2) for normalised x, and the
+    bound it implies on |E - lambda| for the nearest exact eigenvalue lambda of
+    the symmetric H: ||r||.  For a full-space run, where the computed roots are
+    the lowest eigenvalues, also ||r||^2 / gap with gap the distance to the
+    nearest other computed root (Kato-Temple; an estimate, since the gap itself
+    is computed).  A sector run has no such estimate: eigenvalues of the other
+    sector may lie between its roots."""
+    import numpy as np
+    import oracle
+    sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
+    rng = np.random.default_rng(seed)
+    rows = np.unique(rng.integers(0, sp.ndet, nrows))
+    out = []
+    t0 = time.perf_counter()
+    for r, e in enumerate(energies):
+        x = vecs[r].double().cpu().numpy()
+        x /= np.linalg.norm(x)
+        res = sp.sigma_rows(rows, x) - e * x[rows]
+        rn = float(np.sqrt(sp.ndet / rows.size * np.sum(res ** 2)))
+        others = [abs(e - f) for k, f in enumerate(energies) if k != r]
+        gap = min(others) if others else None
+        out.append({"root": r, "energy": float(e), "sampled_residual_norm": rn, "bound_residual": rn,
+                    "kato_temple_estimate": (rn * rn / gap) if (gap and full_space) else None})
+    return {"rows": int(rows.size), "seconds": time.perf_counter() - t0, "roots": out,
+            "note": "oracle sigma of the returned eigenvectors on random rows; |E - exact| <= bound_residual"}
+
+
+def davidson_runs(ctx, cis, torch, nroots, tol, max_iter, verbose, sector, modes, max_space, check=None):
+    """Davidson to convergence in each mode; with check = (spec, h, g, nrows)
+    every run's eigenvectors are certified against the oracle on sampled rows
+    (the CPU-oracle leg)."""
     out = {}
     ctx.set_option(cis.OPT_MAX_ITER, max_iter)
     ctx.set_option(cis.OPT_VERBOSE, 1 if verbose else 0)
@@ -241,12 +358,23 @@ def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector, modes, max_s
     for mode, prec, parity in runs:
         ctx.set_option(cis.OPT_PRECISION, prec)
         ctx.set_option(cis.OPT_SPIN_PARITY, parity)
+        vecs = None
+        if check is not None:
+            vecs = torch.empty(nroots, ctx.ndet, dtype=torch.float64 if prec == cis.FP64 else torch.float32,
+                               device="cuda")
         t0 = time.perf_counter()
-        e, st, status = ctx.davidson(nroots, tol, allow_noconv=True)
+        e, st, status = ctx.davidson(nroots, tol, vecs=vecs, allow_noconv=True)
+        secs = time.perf_counter() - t0
         ctx.set_option(cis.OPT_SPIN_PARITY, 0)
-        out[mode] = {"seconds": time.perf_counter() - t0, "energies": [float(x) for x in e], "status": status,
+        out[mode] = {"seconds": secs, "energies": [float(x) for x in e], "status": status,
                      "iterations": st["iterations"], "sigma_fp32": st["sigma_fp32"], "sigma_fp64": st["sigma_fp64"],
                      "refinements": st["refinements"], "residual": st["residual"]}
+        if vecs is not None:
+            spec, h, g, nrows = check
+            out[mode]["energy_check_vs_oracle"] = cpu_leg_energy_check(spec, h, g, vecs, out[mode]["energies"],
+                                                                       nrows, 31, full_space=parity == 0)
+            del vecs
+            torch.cuda.empty_cache()
         log(f"davidson {mode}: {out[mode]}")
     ctx.set_option(cis.OPT_PRECISION, cis.FP64)
     if "fp64" in out and "mixed_fp32" in out:
@@ -254,6 +382,36 @@ def davidson_runs(ctx, cis, nroots, tol, max_iter, verbose, sector, modes, max_s
         out["max_abs_energy_diff_mixed_vs_fp64"] = max(d)
     if "fp64" in out and "mixed_fp32_even_sector" in out:
         out["even_sector_E0_minus_full_E0"] = out["mixed_fp32_even_sector"]["energies"][0] - out["fp64"]["energies"][0]
+    return out
+
+
+def extra_workload(name, cis, torch, si, steps, warmup, fp64):
+    """sigma timing of another configuration (per pass, HIP events), with the
+    sigma_3 kernel's fraction of the matrix-core peak on the method's own work
+    (the sparse minimum of sigma3_min_products)."""
+    spec = si.WORKLOADS[name]
+    h, g = si.integrals(spec["norb"], spec["nchol"], 0)
+    t0 = time.perf_counter()
+    ctx = cis.Context(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
+    out = {"ndet": ctx.ndet, "init_seconds": time.perf_counter() - t0, "gas": spec["gas"]}
+    prod, nd = sigma3_min_products(spec)
+    assert nd == ctx.ndet
+    out["sigma3_min_flops"] = 2.0 * prod
+    for dt in (("fp32", "fp64") if fp64 else ("fp32",)):
+        d, pp, C, S = time_sigma(ctx, cis, torch, dt, steps, warmup)
+        del C, S
+        torch.cuda.empty_cache()
+        ms = 1e3 * d / steps
+        flags = ctx.last_path(cis.FP32 if dt == "fp32" else cis.FP64)
+        out[dt] = {"ms_per_sigma": ms, "sigma_per_s": 1e3 / ms, "pass_ms": pp,
+                   "sigma3_tflops": 2.0 * prod / (pp["sigma_ab"] / 1e3) / 1e12,
+                   "sigma3_frac_of_peak": 2.0 * prod / (pp["sigma_ab"] / 1e3) / 1e12 / PEAK[dt],
+                   "path": {"ab_owner_computes": bool(flags & cis.PATH_AB_OWNER),
+                            "same_spin_materialised": bool(flags & cis.PATH_SS_MATERIALISED)},
+                   "sigma3_shape": ctx.last_shape(cis.FP32 if dt == "fp32" else cis.FP64)}
+        log(f"{name} {dt}: {out[dt]}")
+    ctx.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -277,6 +435,11 @@ def main():
     ap.add_argument("--max-space", type=int, default=0, help="Davidson subspace cap (0: the library's default)")
     ap.add_argument("--autotune", action="store_true",
                     help="let cisigma_autotune pick the launch parameters before timing (its report goes to extra)")
+    ap.add_argument("--check-rows", type=int, default=10000,
+                    help="random rows of the oracle's sigma per Davidson eigenvector (energy check)")
+    ap.add_argument("--extra-workloads", default="gas20,cas18",
+                    help="comma list of other configurations whose sigma is timed into extra.workloads ('' for none)")
+    ap.add_argument("--extra-steps", type=int, default=3, help="timed sigma builds per extra workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain copy kernel of this many MiB (for counter calibration)")
     args = ap.parse_args()
@@ -327,10 +490,14 @@ def main():
                       "speedup_fp32_vs_fp64": ms64 / ms32})
         log(f"fp64 sigma: {ms64:.2f} ms/step, passes {pp64}, path flags {ctx.last_path(cis.FP64)}")
 
-    # alpha-beta contraction: 2 * M * K * N flops issued by the matrix cores,
-    # M = alpha excitations per string (na*(n-na)), K = orbital pairs k>=l (n(n+1)/2), N = determinants
-    M, K = na * (n - na), n * (n + 1) // 2
-    flops = 2.0 * M * K * ctx.ndet
+    # alpha-beta contraction (sigma_3), on the method's own work: the sparse minimum
+    # of (alpha excitation, beta excitation) products, 2 [n_a (n - n_a + 1)]^2 N_det
+    # for a CAS.  The owner-computes kernel issues more: M = n_a (n - n_a) gathered
+    # alpha rows x K = n(n+1)/2 orbital pairs per determinant (issued_flops).
+    prod, nd = sigma3_min_products(spec)
+    assert nd == ctx.ndet
+    flops = 2.0 * prod
+    issued = 2.0 * na * (n - na) * (n * (n + 1) // 2) * ctx.ndet
     ab_s = pp32["sigma_ab"] / 1e3
     achieved = flops / ab_s / 1e12
     owner = bool(path32 & cis.PATH_AB_OWNER)
@@ -340,17 +507,30 @@ def main():
                 "kernel": ("k_sigma_ab_ws (owner-computes sigma_3: gathered C rows -> FP32 MFMA on six waves over "
                            "three SIMDs, LDS scatter on two waves on the fourth)" if owner
                            else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
-                "flops_per_launch": flops, "avg_launch_ms": pp32["sigma_ab"]}
+                "flops_per_launch": flops,
+                "flops_definition": "sparse minimum: 2 x sum over determinants of (alpha single excitations incl. "
+                                    "E_kk) x (beta single excitations incl. E_kk) with the source determinant in "
+                                    "the space",
+                "issued_flops": issued, "issued_frac": issued / ab_s / 1e12 / PEAK["fp32"],
+                "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
-    if args.workload == "cas16":
-        ssb = stored_same_spin_bytes()
+    if spec["gas"] is None:
+        # same-spin passes against their floors: t / max(HBM floor, VALU floor); the
+        # counter bytes (when the committed summary matches the kernel source) beside them
+        ss = same_spin_floors(spec, ctx.ndet, 4)
+        t_ss = pp32["sigma_aa"]
+        ss.update({"pass_ms": t_ss, "frac_of_floor": max(ss["hbm_floor_ms"], ss["valu_floor_ms"]) / t_ss,
+                   "compulsory_GBps": ss["compulsory_bytes"] / (t_ss / 1e3) / 1e9,
+                   "note": "frac_of_floor = max(compulsory-bytes time at 8 TB/s, VALU time of the sparse string "
+                           "Hamiltonian at the FP32 peak) / pass time; the 60% HBM target is judged on it"})
+        ssb = stored_same_spin_bytes() if args.workload == "cas16" else None
         if ssb is not None:
-            # HBM-bound passes: counted bytes over the pass time, against the 8 TB/s peak
-            rate = ssb / (pp32["sigma_aa"] / 1e3) / 1e9
-            extra["same_spin_pass_hbm"] = {"bytes_per_pass": ssb, "achieved_GBps": rate, "peak_GBps": HBM_PEAK,
-                                           "frac": rate / HBM_PEAK}
+            ss["counter_bytes_per_pass"] = ssb
+            ss["counter_GBps"] = ssb / (t_ss / 1e3) / 1e9
+        extra["same_spin_pass"] = ss
     if not args.no_fp64:
         extra["sigma_ab_tflops_fp64"] = flops / (pp64["sigma_ab"] / 1e3) / 1e12
+        extra["sigma_ab_frac_fp64"] = extra["sigma_ab_tflops_fp64"] / PEAK["fp64"]
 
     # NEXT: spin-summed 1- and 2-particle density matrices (one-block spaces, n <= 16)
     if spec["gas"] is None and n <= 16 and not args.no_rdm:
@@ -381,13 +561,26 @@ def main():
         # the Davidson basis lives in the library's own allocations: hand back what torch holds
         del C32, S32
         torch.cuda.empty_cache()
-        extra["davidson"] = davidson_runs(ctx, cis, args.nroots, args.tol, args.max_iter, args.verbose, sector,
-                                          args.davidson_modes.split(","), args.max_space)
+        extra["davidson"] = davidson_runs(ctx, cis, torch, args.nroots, args.tol, args.max_iter, args.verbose,
+                                          sector, args.davidson_modes.split(","), args.max_space,
+                                          None if args.no_cpu else (spec, h, g, args.check_rows))
+
+    ndet = ctx.ndet
+    C32 = S32 = None
+    ctx.close()
+    torch.cuda.empty_cache()
+    if args.extra_workloads:
+        # the other configurations of the metric: sigma timing per pass and sigma_3's fraction of peak
+        extra["workloads"] = {}
+        for name in args.extra_workloads.split(","):
+            if name and name != args.workload:
+                extra["workloads"][name] = extra_workload(name, cis, torch, si, args.extra_steps, 1,
+                                                          name != "cas18")
 
     cfg = {"workload": f"{args.workload}: {n} orbitals, {na} alpha + {nb} beta electrons"
                        + (f", GAS {spec['gas']}" if spec["gas"] else " (CAS)")
-                       + f", {ctx.ndet} determinants, seeded synthetic integrals (P={spec['nchol']})",
-           "ndet": ctx.ndet, "norb": n, "nalpha": na, "nbeta": nb}
+                       + f", {ndet} determinants, seeded synthetic integrals (P={spec['nchol']})",
+           "ndet": ndet, "norb": n, "nalpha": na, "nbeta": nb}
     line = {
         "metric": "sigma builds/s + sigma_ab TFLOP/s at CAS(16,16); Davidson time to 1e-6 Eh, FP32 vs FP64",
         "value": args.steps / dt32,

@@ -333,6 +333,20 @@ int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls);
 #define CISIGMA_PATH_SS_MATERIALISED 2   /* same-spin parts by materialised pair products + gather */
 int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags);
 
+/*
+ * cisigma_last_shape -- the compiled shape of the owner-computes sigma_3
+ * kernel (the alpha-beta part of Eq. 8) that the most recent cisigma_apply of
+ * dtype launched, for tests that must know which variant ran:
+ *   shape[0]  k steps of gathered alpha rows (4 rows each)
+ *   shape[1]  16-row blocks of orbital pairs
+ *   shape[2]  scatter-plan entries per lane and tile
+ *   shape[3]  0: no owner-computes kernel ran (general kernel); 1: one-block
+ *             kernel with the own row in a k step; 2: one-block kernel with the
+ *             own row as the rank-1 start of the accumulators; 3: GAS units
+ * shape is a host int[4], written.  EINVAL for NULL arguments or a bad dtype.
+ */
+int cisigma_last_shape(const cisigma_ctx *ctx, int dtype, int *shape);
+
 /* message of the most recent failure on ctx (never NULL) */
 const char *cisigma_last_error(const cisigma_ctx *ctx);
 

@@ -84,6 +84,8 @@ _lib.cisigma_rdm.restype = _i32
 _lib.cisigma_rdm.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
 _lib.cisigma_last_path.restype = _i32
 _lib.cisigma_last_path.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
+_lib.cisigma_last_shape.restype = _i32
+_lib.cisigma_last_shape.argtypes = [_vp, _i32, _vp]
 _lib.cisigma_pass_times.restype = _i32
 _lib.cisigma_pass_times.argtypes = [_vp, _vp, ctypes.POINTER(_i32)]
 _lib.cisigma_last_error.restype = ctypes.c_char_p
@@ -94,7 +96,7 @@ _lib.cisigma_strerror.argtypes = [_i32]
 EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "cisigma_address", "cisigma_strings",
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
            "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
-           "cisigma_hmat_block", "cisigma_autotune"]
+           "cisigma_hmat_block", "cisigma_autotune", "cisigma_last_shape"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -267,6 +269,15 @@ class Context:
         f = _i32()
         self._check(_lib.cisigma_last_path(self._h, int(dtype), ctypes.byref(f)))
         return f.value
+
+    def last_shape(self, dtype=FP32):
+        """(k steps, pair row blocks, plan entries per lane, variant) of the
+        owner-computes sigma_3 kernel of the most recent apply of dtype;
+        variant 0: general kernel, 1: own row in a k step, 2: rank-1 own row,
+        3: GAS units."""
+        sh = np.zeros(4, np.int32)
+        self._check(_lib.cisigma_last_shape(self._h, int(dtype), sh.ctypes.data))
+        return tuple(int(x) for x in sh)
 
     def last_error(self):
         return _lib.cisigma_last_error(self._h).decode()

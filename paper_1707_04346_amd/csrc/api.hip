@@ -859,6 +859,7 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     }
     auto mark = [&](int pass) -> hipError_t { return prof ? hipEventRecord(ev[pass + 1], s) : hipSuccess; };
     c->last_path[dtype == CISIGMA_FP32] = mat ? CISIGMA_PATH_SS_MATERIALISED : 0;
+    for (int &v : c->last_shape[dtype == CISIGMA_FP32]) v = 0;
     // M_S = 0 sector (Sec. 3.3): for C(Ib, Ia) = p C(Ia, Ib) the beta-beta part
     // is p times the transposed alpha-alpha part.  The alpha-alpha part then goes
     // to the second accumulator (same shape when nalpha = nbeta), the alpha-beta
@@ -1045,6 +1046,12 @@ CIS_API int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls) {
 CIS_API int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags) {
     if (!ctx || !flags || (dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64)) return CISIGMA_EINVAL;
     *flags = ctx->last_path[dtype == CISIGMA_FP32];
+    return CISIGMA_OK;
+}
+
+CIS_API int cisigma_last_shape(const cisigma_ctx *ctx, int dtype, int *shape) {
+    if (!ctx || !shape || (dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64)) return CISIGMA_EINVAL;
+    for (int i = 0; i < 4; ++i) shape[i] = ctx->last_shape[dtype == CISIGMA_FP32][i];
     return CISIGMA_OK;
 }
 

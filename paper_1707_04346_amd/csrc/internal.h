@@ -218,6 +218,7 @@ struct cisigma_ctx {
     double resid_tol = -1.0;
     int verbose = 0;
     int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]
+    int last_shape[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // owner-computes sigma_3 shape of the last apply
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
     int ab_mode = 0;
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)

@@ -302,8 +302,12 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.units = G.d_units[d];
     a.nunits = int(G.units[d].size());
     a.nvirt = G.maxcols[d];
-#define CIS_RUN(K, R, E) \
-    if (G.ks == K && G.rb == R && G.plan[d].ew == E) *err = run_abg<T, K, R, E>(a, G.nblocks[d], s);
+    int *kshape = const_cast<cisigma_ctx *>(ctx)->last_shape[sizeof(T) == 4];
+#define CIS_RUN(K, R, E)                                                \
+    if (G.ks == K && G.rb == R && G.plan[d].ew == E) {                  \
+        *err = run_abg<T, K, R, E>(a, G.nblocks[d], s);                 \
+        kshape[0] = K; kshape[1] = R; kshape[2] = E; kshape[3] = 3;     \
+    }
     CIS_ABG_SHAPES(CIS_RUN)
 #undef CIS_RUN
     return true;

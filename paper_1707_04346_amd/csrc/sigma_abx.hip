@@ -390,7 +390,9 @@ int rb_of(int npair) { return (npair + 15) / 16; }
 
 // Shapes with Ia's row as the rank-1 start of the accumulators, for the
 // CAS(n, n/2) spaces of even n and their neighbours whose excitation count is
-// a multiple of 4 (there it saves a k step; elsewhere the row fills padding)
+// a multiple of 4 (there it saves a k step; elsewhere the row fills padding).
+// The 16-entry plan width serves spaces whose target groups would span more
+// than four lanes at the narrow width (CAS(8,8), CAS(12,12) and smaller).
 #define CIS_ABX_SHAPES_R1(X)                                                                           \
     X(1, 1, 2) X(1, 1, 16) X(2, 2, 2) X(2, 2, 16) X(4, 3, 4) X(4, 3, 16) X(6, 4, 4) X(6, 4, 16)         \
     X(9, 5, 6) X(9, 5, 16) X(12, 7, 8) X(12, 7, 16) X(16, 9, 10) X(16, 9, 16)
@@ -403,19 +405,28 @@ int width_for(int ks, int rb, int need) {
     return best;
 }
 
+// shape[4] receives {KS, RB, EW, 1: row in a k step, 2: rank-1 start}
 template <typename T>
-bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err) {
+bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, int *shape) {
     const int rb = rb_of(a.npair);
     if (a.anexc > 0 && a.anexc % 4 == 0) {
         const int ks1 = a.anexc / 4;
-#define CIS_RUN1(K, R, E) \
-    if (ks1 == K && rb == R && ew == E) { *err = run_abx<T, K, R, E, false>(a, s); return true; }
+#define CIS_RUN1(K, R, E)                                           \
+    if (ks1 == K && rb == R && ew == E) {                           \
+        *err = run_abx<T, K, R, E, false>(a, s);                    \
+        shape[0] = K; shape[1] = R; shape[2] = E; shape[3] = 2;     \
+        return true;                                                \
+    }
         CIS_ABX_SHAPES_R1(CIS_RUN1)
 #undef CIS_RUN1
     }
     const int ks = ks_of(a.anexc);
-#define CIS_RUN(K, R, E) \
-    if (ks == K && rb == R && ew == E) { *err = run_abx<T, K, R, E, true>(a, s); return true; }
+#define CIS_RUN(K, R, E)                                            \
+    if (ks == K && rb == R && ew == E) {                            \
+        *err = run_abx<T, K, R, E, true>(a, s);                     \
+        shape[0] = K; shape[1] = R; shape[2] = E; shape[3] = 1;     \
+        return true;                                                \
+    }
     CIS_ABX_SHAPES(CIS_RUN)
 #undef CIS_RUN
     return false;
@@ -448,7 +459,7 @@ bool owner_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hi
     if (cpb >= (uint64_t(1) << 31) || plb >= (uint64_t(1) << 31)) return false;
     x.cp_bytes = uint32_t(cpb);
     x.plan_bytes = uint32_t(plb);
-    return dispatch_abx<T>(x, P.ew, s, err);
+    return dispatch_abx<T>(x, P.ew, s, err, const_cast<cisigma_ctx *>(ctx)->last_shape[sizeof(T) == 4]);
 }
 
 }  // namespace

@@ -7,6 +7,7 @@ import torch
 
 import oracle
 import synth_inputs as si
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -20,8 +21,6 @@ def _cis():
     return cis
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 def sigma(ctx, c, dtype):

@@ -8,6 +8,7 @@ import torch
 
 import oracle
 import synth_inputs as si
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +25,6 @@ def make(norb, na, nb, seed=0):
     return _cis().Context(norb, na, nb, h, g), oracle.Space(norb, na, nb, h, g)
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 EDGE = [(32, 1, 1), (32, 2, 1), (32, 0, 3), (24, 2, 2), (20, 1, 3), (17, 2, 2), (17, 3, 1)]

@@ -12,6 +12,7 @@ import torch
 
 import oracle
 import synth_inputs as si
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -24,8 +25,6 @@ def _cis():
     return cis
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 @pytest.mark.parametrize("case", CASES, ids=["cas8", "cas6a3b2", "gas7"])

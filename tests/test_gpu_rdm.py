@@ -17,6 +17,7 @@ import torch
 
 import oracle
 import synth_inputs as si
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -42,8 +43,6 @@ def gpu_rdm(ctx, C):
     return g1.cpu().numpy(), g2.cpu().numpy()
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 SMALL = [(4, 2, 2), (6, 3, 3), (6, 3, 2), (5, 1, 3), (5, 0, 2), (8, 4, 4), (9, 5, 4), (10, 4, 4)]
@@ -85,7 +84,7 @@ def test_rdm_identities_cas12(dtype):
     w = si.WORKLOADS["cas12"]
     ctx, _, h, g = make(w["norb"], w["nalpha"], w["nbeta"], w["nchol"])
     c = si.ci_vector(ctx.ndet, 0)
-    _identities(ctx, h, g, torch.tensor(c, dtype=dtype, device="cuda"), 1e-10 if dtype == torch.float64 else 2e-5)
+    _identities(ctx, h, g, torch.tensor(c, dtype=dtype, device="cuda"), 1e-10 if dtype == torch.float64 else 1e-5)
 
 
 def test_rdm_identities_cas16_fp32():
@@ -95,7 +94,7 @@ def test_rdm_identities_cas16_fp32():
     gen = torch.Generator(device="cuda")
     gen.manual_seed(11)
     C = torch.randn(ctx.ndet, dtype=torch.float32, device="cuda", generator=gen)
-    _identities(ctx, h, g, C, 2e-5)
+    _identities(ctx, h, g, C, 1e-5)
     del C
     ctx.close()
 

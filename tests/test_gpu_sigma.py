@@ -14,6 +14,7 @@ import torch
 
 import oracle
 import synth_inputs as si
+from tolerance import rel
 
 pytestmark = pytest.mark.gpu
 
@@ -38,8 +39,6 @@ def gpu_sigma(ctx, c, dtype):
     return S.double().cpu().numpy()
 
 
-def rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
 # (norb, nalpha, nbeta, gas)
@@ -253,15 +252,27 @@ def test_cas_takes_the_fast_paths(case, dtype):
 # start the alpha-beta accumulators from the rank-1 term of Ia's own row
 # instead of giving that row a k step: one space per compiled shape of that
 # form not already run above (n = 8, 12 there; n = 16 in the full-size tests).
-@pytest.mark.parametrize("case", [(4, 2, 2), (6, 2, 3), (10, 4, 5)], ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
+# The expected shape (k steps, pair row blocks, plan entries per lane, variant)
+# is the compiled kernel each space must get: variant 2 = rank-1 own row,
+# 1 = own row in a k step.  The plan width is the narrow one unless a target's
+# contributions within a 32-column tile would span more than four lanes at it
+# (then 16).
+SHAPES = [((4, 2, 2), (1, 1, 2, 2)), ((6, 2, 3), (2, 2, 16, 2)), ((10, 4, 5), (6, 4, 16, 2)),
+          ((8, 4, 4), (4, 3, 16, 2)), ((12, 6, 6), (9, 5, 16, 2)), ((7, 2, 4), (3, 2, 16, 1)),
+          ((9, 5, 4), (6, 3, 16, 1)), ((7, 4, 2), (4, 2, 4, 1))]
+
+
+@pytest.mark.parametrize("case,shape", SHAPES, ids=[f"n{c[0]}a{c[1]}b{c[2]}" for c, _ in SHAPES])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
-def test_rank1_self_row_shapes(case, dtype):
+def test_rank1_self_row_shapes(case, shape, dtype):
     cis = _cis()
     norb, na, nb = case
     ctx, ref = make(norb, na, nb, seed=17)
     c = si.ci_vector(ctx.ndet, 18)
     s = gpu_sigma(ctx, c, dtype)
-    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) & cis.PATH_AB_OWNER
+    dt = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert ctx.last_path(dt) & cis.PATH_AB_OWNER
+    assert ctx.last_shape(dt) == shape, ctx.last_shape(dt)
     tol = TOL64 if dtype == torch.float64 else TOL32
     assert rel(s, ref.sigma(c)) <= tol
 
@@ -282,7 +293,9 @@ def test_rank1_self_row_cas14_sampled(dtype):
     S = torch.empty_like(C)
     ctx.apply(C, S)
     torch.cuda.synchronize()
-    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) & cis.PATH_AB_OWNER
+    dt = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert ctx.last_path(dt) & cis.PATH_AB_OWNER
+    assert ctx.last_shape(dt) == (12, 7, 8, 2), ctx.last_shape(dt)
     got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
     want = ref.sigma_rows(rows, c)
     tol = TOL64 if dtype == torch.float64 else TOL32

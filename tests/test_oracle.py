@@ -493,3 +493,28 @@ def test_rdm_single_determinant_closed_form():
     g1, g2 = S.rdm(C)
     assert np.abs(g1 - np.diag(Np)).max() < 1e-14
     assert np.abs(g2 - want2).max() < 1e-14
+
+
+def test_cas66_recipe_values():
+    """The CAS(6,6) workload under the seeded recipe against values recorded
+    independently when the workloads were defined (tests/golden/cas66_recipe.txt):
+    diag(h) to the 6 printed decimals, (00|00), the lowest diagonal element and
+    its index, and the four lowest eigenvalues of the oracle's dense H."""
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "cas66_recipe.txt")) as f:
+        for ln in f:
+            if ln.strip() and not ln.startswith("#"):
+                k, v = ln.split()
+                vals[k] = float(v)
+    h, g = si.integrals(6, 12, 0)
+    for p in range(6):
+        assert abs(h[p, p] - vals[f"h{p}{p}"]) <= 5e-7
+    assert abs(g[0, 0, 0, 0] - vals["eri0000"]) <= 1e-12
+    sp = oracle.Space(6, 3, 3, h, g)
+    d = sp.hdiag()
+    assert int(np.argmin(d)) == int(vals["argmin_hdiag"])
+    assert abs(d.min() - vals["min_hdiag"]) <= 1e-11
+    w = np.linalg.eigvalsh(sp.hmat())
+    for k in range(4):
+        assert abs(w[k] - vals[f"E{k}"]) <= 1e-11, (k, w[k])
