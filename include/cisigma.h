@@ -235,6 +235,29 @@ int cisigma_set_option(cisigma_ctx *ctx, int key, double value);
 int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream);
 
 /*
+ * cisigma_apply_noalloc -- cisigma_apply for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same sigma = H C, with the same arguments,
+ * ordering and asynchrony, and the same kernels, but the sigma workspace is
+ * carved from a static device array of 64 MiB that the library holds on every
+ * GPU it runs on until the process ends; the call makes no hipMalloc, hipFree
+ * or other allocating call and no memset (it clears what must start at zero
+ * with kernels).  Options act as for cisigma_apply except CISIGMA_OPT_PROFILE,
+ * CISIGMA_OPT_OVERLAP and CISIGMA_OPT_GRAPH, which it ignores.
+ *   Limit: the four padded layout copies of the space must fit in the 64 MiB
+ *   (about 16 M elements FP32, 8 M FP64: CAS(12,12) and smaller in either
+ *   precision); the materialised same-spin rows take what is left (column
+ *   chunks), and when less than one 64-column chunk is left the same-spin parts
+ *   run on the atomic kernels.  Larger spaces: EUNSUPPORTED, with the bytes
+ *   needed in cisigma_last_error.
+ *   The current device must be the one cisigma_init ran on (EINVAL otherwise).
+ * Every call on a GPU shares that GPU's one array, whichever context makes it:
+ * calls that overlap in time on one GPU (other streams, other host threads)
+ * race on it and give wrong results.  Order them on one stream, or synchronise.
+ */
+int cisigma_apply_noalloc(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream);
+
+/*
  * cisigma_hmat_block -- Hamiltonian matrix elements between determinants of
  * the space (Eq. 6 with the string operators of Eq. 7: the Slater-Condon
  * rules): out[i * m + j] = H(rows[i], cols[j]) for vector indices rows[0..n)

@@ -84,6 +84,8 @@ _lib.cisigma_rdm.restype = _i32
 _lib.cisigma_rdm.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
 _lib.cisigma_last_path.restype = _i32
 _lib.cisigma_last_path.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
+_lib.cisigma_apply_noalloc.restype = _i32
+_lib.cisigma_apply_noalloc.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.cisigma_last_shape.restype = _i32
 _lib.cisigma_last_shape.argtypes = [_vp, _i32, _vp]
 _lib.cisigma_pass_times.restype = _i32
@@ -96,7 +98,8 @@ _lib.cisigma_strerror.argtypes = [_i32]
 EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "cisigma_address", "cisigma_strings",
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
            "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
-           "cisigma_hmat_block", "cisigma_autotune", "cisigma_last_shape"]
+           "cisigma_hmat_block", "cisigma_autotune", "cisigma_last_shape",
+           "cisigma_apply_noalloc"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -210,6 +213,17 @@ class Context:
         if not (C.is_contiguous() and sigma.is_contiguous()):
             raise CisigmaError(EINVAL, "C and sigma must be contiguous")
         self._check(_lib.cisigma_apply(self._h, _ptr(C), _ptr(sigma), dt, _stream_ptr(stream)))
+        return sigma
+
+    def apply_noalloc(self, C, sigma, stream=None):
+        """sigma = H C through cisigma_apply_noalloc (workspace in the library's
+        static device scratch; no allocation)."""
+        dt = FP32 if str(C.dtype).endswith("float32") else FP64
+        if str(sigma.dtype) != str(C.dtype) or C.numel() != self.ndet or sigma.numel() != self.ndet:
+            raise CisigmaError(EINVAL, "C and sigma must be device tensors of ndet elements of one dtype")
+        if not (C.is_contiguous() and sigma.is_contiguous()):
+            raise CisigmaError(EINVAL, "C and sigma must be contiguous")
+        self._check(_lib.cisigma_apply_noalloc(self._h, _ptr(C), _ptr(sigma), dt, _stream_ptr(stream)))
         return sigma
 
     def apply_raw(self, c_ptr, s_ptr, dtype, stream_ptr=None):

@@ -14,11 +14,20 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "internal.h"
 
 #define CIS_API extern "C" __attribute__((visibility("default")))
+
+// Scratch of cisigma_apply_noalloc: the sigma workspace (padded layout copies,
+// accumulators and materialised same-spin rows) of spaces small enough to fit,
+// in a static device array.  Every GPU the library runs on holds its own copy
+// until the process ends; host code never passes `scratch` itself to a kernel
+// but the device address looked up once per device (noalloc_scratch below).
+constexpr size_t kNoallocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
 
 int cis_set_error(cisigma_ctx *ctx, int code, const std::string &msg) {
     if (ctx) ctx->err = msg;
@@ -50,6 +59,26 @@ int hip_fail(cisigma_ctx *ctx, hipError_t e, const char *where) {
         hipError_t e_ = (x);                           \
         if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
     } while (0)
+
+// device address of `scratch` on device dev, looked up on the first request for
+// that device (with it current) and kept; nullptr with *err set on failure
+void *noalloc_scratch(int dev, hipError_t *err) {
+    static std::mutex mu;
+    static std::array<void *, 64> ptr{};
+    *err = hipSuccess;
+    if (dev < 0 || dev >= int(ptr.size())) {
+        *err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (*err != hipSuccess) return nullptr;
+        ptr[dev] = p;
+    }
+    return ptr[dev];
+}
 
 uint64_t binom(int m, int k) {
     if (k < 0 || k > m) return 0;
@@ -781,26 +810,46 @@ int build_gas_owner(cisigma_ctx *c) {
     return CISIGMA_OK;
 }
 
+// bytes of one alpha-major (*na) and one beta-major (*nb) layout copy of a
+// dtype's workspace; one-block spaces (and GAS spaces with owner tables) add
+// one zero row after the copy (rows the owner-computes sigma_3 and the
+// pair-product kernels read in place of missing ones)
+void workspace_copy_sizes(const cisigma_ctx *c, size_t es, size_t *na, size_t *nb) {
+    int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
+    if (c->go.ks) for (int ld : c->pl[0].ld) zero_row = std::max<int64_t>(zero_row, ld);
+    *na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
+    *nb = size_t(std::max<int64_t>(c->pl[1].size + (c->cas ? c->pl[1].ld[0] : 0), 1)) * es;
+}
+
 // device bytes of the four layout copies of one dtype's workspace (without the
 // materialised same-spin rows, which take what is free)
 size_t workspace_copy_bytes(const cisigma_ctx *c, size_t es) {
-    int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
-    if (c->go.ks) for (int ld : c->pl[0].ld) zero_row = std::max<int64_t>(zero_row, ld);
-    size_t na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
-    size_t nb = size_t(std::max<int64_t>(c->pl[1].size + (c->cas ? c->pl[1].ld[0] : 0), 1)) * es;
+    size_t na = 0, nb = 0;
+    workspace_copy_sizes(c, es, &na, &nb);
     return 2 * (na + nb);
+}
+
+// rows of the materialised same-spin products (one-type spins whose pair count
+// has MFMA kernels), their widest row, and whether every spin qualifies
+bool ys_shape(const cisigma_ctx *c, size_t *rows, size_t *cols) {
+    *rows = 0;
+    *cols = 0;
+    bool ok = c->cas;
+    for (int s = 0; s < 2; ++s)
+        if (c->sp[s].nel >= 2) {
+            *rows = std::max(*rows, size_t(c->sp[s].nK) * c->sp[s].npv);
+            *cols = std::max(*cols, size_t(c->pl[s].ld[0]));
+            ok = ok && cis::same_spin_materialisable(c->sp[s].npv);
+        }
+    return ok && *rows > 0;
 }
 
 int ensure_workspace(cisigma_ctx *c, int dtype) {
     auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
     if (W.ready) return CISIGMA_OK;
     size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
-    // one-block spaces: one extra zero row after each copy (rows the owner-computes
-    // sigma_3 and the pair-product kernels read in place of missing ones)
-    int64_t zero_row = c->cas ? c->pl[0].ld[0] : 0;
-    if (c->go.ks) for (int ld : c->pl[0].ld) zero_row = std::max<int64_t>(zero_row, ld);
-    size_t na = size_t(std::max<int64_t>(c->pl[0].size + zero_row, 1)) * es;
-    size_t nb = size_t(std::max<int64_t>(c->pl[1].size + (c->cas ? c->pl[1].ld[0] : 0), 1)) * es;
+    size_t na = 0, nb = 0;
+    workspace_copy_sizes(c, es, &na, &nb);
     size_t fr = 0, tot = 0;
     if (hipMemGetInfo(&fr, &tot) == hipSuccess && 2 * (na + nb) + (64u << 20) > fr)
         return cis_set_error(c, CISIGMA_ENOMEM, "apply: not enough device memory for the sigma workspace");
@@ -813,23 +862,14 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     HIP_OR_FAIL(c, hipMemset(W.ct, 0, nb), "apply: workspace");
     // materialised same-spin rows for one-type spins: all columns if they fit in half
     // of what is free, else column chunks (multiples of 64)
-    if (c->cas) {
-        size_t rows = 0, cols = 0;
-        bool shapes_ok = true;
-        for (int s = 0; s < 2; ++s)
-            if (c->sp[s].nel >= 2) {
-                rows = std::max(rows, size_t(c->sp[s].nK) * c->sp[s].npv);
-                cols = std::max(cols, size_t(c->pl[s].ld[0]));
-                shapes_ok = shapes_ok && cis::same_spin_materialisable(c->sp[s].npv);
-            }
-        if (rows > 0 && shapes_ok && hipMemGetInfo(&fr, &tot) == hipSuccess) {
-            size_t budget = fr / 2;
-            size_t chunk = std::min(cols, budget / (rows * es) / cis::kTileCols * cis::kTileCols);
-            if (chunk >= size_t(cis::kTileCols) && hipMalloc(&W.ys, rows * chunk * es) == hipSuccess)
-                W.ys_chunk = int(chunk);
-            else
-                W.ys = nullptr;
-        }
+    size_t rows = 0, cols = 0;
+    if (ys_shape(c, &rows, &cols) && hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        size_t budget = fr / 2;
+        size_t chunk = std::min(cols, budget / (rows * es) / cis::kTileCols * cis::kTileCols);
+        if (chunk >= size_t(cis::kTileCols) && hipMalloc(&W.ys, rows * chunk * es) == hipSuccess)
+            W.ys_chunk = int(chunk);
+        else
+            W.ys = nullptr;
     }
     if (!c->side) {
         HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "apply: side stream");
@@ -845,14 +885,16 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
 
 namespace cis {
 
-int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s) {
-    int rc = ensure_workspace(c, dtype);
-    if (rc) return rc;
-    auto &W = c->ws[dtype == CISIGMA_FP32 ? 1 : 0];
+namespace {
+
+// the passes of one sigma on workspace W; own = W belongs to the context (then
+// profiling events and the side stream of the overlap option may be used)
+int apply_sigma_ws(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s, const Workspace &W,
+                   bool own) {
     // one-type spins with room for the materialised same-spin rows avoid global atomics there
     const bool mat = c->cas && c->ab_mode == 0 && W.ys != nullptr;
     hipEvent_t ev[CISIGMA_NPASS + 1];
-    const bool prof = c->profile;
+    const bool prof = own && c->profile;
     if (prof) {
         for (auto &e : ev) HIP_OR_FAIL(c, hipEventCreate(&e), "apply: profiling events");
         HIP_OR_FAIL(c, hipEventRecord(ev[0], s), "apply: profiling events");
@@ -887,7 +929,7 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
     // alpha-alpha pass, which precedes the fork.  The events of the alpha-beta
     // pass then time it while the other runs; the beta-beta "pass" time is the
     // wait for it after that.
-    const bool fork = !par && c->overlap && c->side;
+    const bool fork = own && !par && c->overlap && c->side;
     if (fork) {
         HIP_OR_FAIL(c, hipEventRecord(c->ev_fork, s), "apply: fork");
         HIP_OR_FAIL(c, hipStreamWaitEvent(c->side, c->ev_fork, 0), "apply: fork");
@@ -913,6 +955,53 @@ int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream
         c->prof_pending.push_back(1);
     }
     return CISIGMA_OK;
+}
+
+}  // namespace
+
+int apply_sigma(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s) {
+    int rc = ensure_workspace(c, dtype);
+    if (rc) return rc;
+    return apply_sigma_ws(c, C, sigma, dtype, s, c->ws[dtype == CISIGMA_FP32 ? 1 : 0], true);
+}
+
+// The workspace in the static scratch array, laid out as the allocated one:
+// alpha-major copy, its accumulator, beta-major copy, its accumulator (each
+// 256-byte aligned), then as many columns of the materialised same-spin rows as
+// fit (none: the same-spin parts take the atomic kernels).  Every call clears
+// the two copies (padding columns and zero rows must read as zeros; another
+// call may have left other data there) with fill kernels, no memset.
+int apply_sigma_noalloc(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s) {
+    if (!c->scratch) return cis_set_error(c, CISIGMA_EDEVICE, "apply_noalloc: scratch address not available");
+    const size_t es = dtype == CISIGMA_FP32 ? 4 : 8;
+    size_t na = 0, nb = 0;
+    workspace_copy_sizes(c, es, &na, &nb);
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    const size_t copies = 2 * up(na) + 2 * up(nb);
+    if (copies > kNoallocScratchBytes)
+        return cis_set_error(c, CISIGMA_EUNSUPPORTED,
+                             "apply_noalloc: the space needs " + std::to_string(copies) +
+                                 " bytes of workspace, more than the " + std::to_string(kNoallocScratchBytes) +
+                                 "-byte static scratch");
+    unsigned char *base = static_cast<unsigned char *>(c->scratch);
+    Workspace W{};
+    W.cp = base;
+    W.sp = base + up(na);
+    W.ct = base + 2 * up(na);
+    W.st = base + 2 * up(na) + up(nb);
+    size_t rows = 0, cols = 0;
+    if (ys_shape(c, &rows, &cols)) {
+        const size_t chunk =
+            std::min(cols, (kNoallocScratchBytes - copies) / (rows * es) / cis::kTileCols * cis::kTileCols);
+        if (chunk >= size_t(cis::kTileCols)) {
+            W.ys = base + copies;
+            W.ys_chunk = int(chunk);
+        }
+    }
+    W.ready = true;
+    HIP_OR_FAIL(c, launch_fill(W.cp, int64_t(na / es), dtype, s), "apply_noalloc: clear");
+    HIP_OR_FAIL(c, launch_fill(W.ct, int64_t(nb / es), dtype, s), "apply_noalloc: clear");
+    return apply_sigma_ws(c, C, sigma, dtype, s, W, false);
 }
 
 int gas_set_unit_order(cisigma_ctx *c, int d, int order) {
@@ -1202,6 +1291,12 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    // set-up of cisigma_apply_noalloc: the device address of this device's scratch
+    // array (looked up once per device, with it current)
+    if (he == hipSuccess) {
+        c->dev = dev;
+        c->scratch = noalloc_scratch(dev, &he);
+    }
     if (he != hipSuccess) {
         int rc = hip_fail(c, he, "init: device");
         free_ctx(c);
@@ -1511,6 +1606,20 @@ CIS_API int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtyp
     if (ctx->graph_mode && stream && !ctx->profile)
         return cis::apply_sigma_graph(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
     return cis::apply_sigma(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
+}
+
+CIS_API int cisigma_apply_noalloc(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream) {
+    if (!ctx) return CISIGMA_EINVAL;
+    if (!C || !sigma) return cis_set_error(ctx, CISIGMA_EINVAL, "apply_noalloc: NULL vector");
+    if (dtype != CISIGMA_FP32 && dtype != CISIGMA_FP64)
+        return cis_set_error(ctx, CISIGMA_EINVAL, "apply_noalloc: bad dtype");
+    const size_t bytes = size_t(ctx->lay.ndet) * (dtype == CISIGMA_FP32 ? 4 : 8);
+    const char *a = static_cast<const char *>(C), *b = static_cast<const char *>(sigma);
+    if (a < b + bytes && b < a + bytes) return cis_set_error(ctx, CISIGMA_EINVAL, "apply_noalloc: C and sigma overlap");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ctx->dev)
+        return cis_set_error(ctx, CISIGMA_EINVAL, "apply_noalloc: the current device is not the context's");
+    return cis::apply_sigma_noalloc(ctx, C, sigma, dtype, static_cast<hipStream_t>(stream));
 }
 
 CIS_API int cisigma_rdm(cisigma_ctx *ctx, const void *C, int dtype, double *rdm1, double *rdm2, void *stream) {

@@ -200,6 +200,8 @@ struct cisigma_ctx {
     int act_max = 0;
     cis::GasOwner go;              // owner-computes sigma_3 tables for GAS spaces (go.ks = 0: none)
     hipStream_t stream = nullptr;  // own stream for synchronous calls
+    int dev = 0;                   // HIP device the context's tables live on
+    void *scratch = nullptr;       // device address of that device's no-allocation scratch (api.hip)
     // beta-beta pass of apply on a second stream, overlapping the alpha-beta pass
     // (CISIGMA_OPT_OVERLAP); created with the workspace, default priority
     hipStream_t side = nullptr;
@@ -307,6 +309,8 @@ double hmat_element(const cisigma_ctx *c, uint32_t a1, uint32_t b1, uint32_t a2,
 int davidson(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats);
 // sigma of one device vector on the given stream (api.hip)
 int apply_sigma(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
+// the same with the workspace carved from the static scratch array (no allocation)
+int apply_sigma_noalloc(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
 // the same through a captured graph (CISIGMA_OPT_GRAPH; non-NULL stream)
 int apply_sigma_graph(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, hipStream_t s);
 void drop_graphs(cisigma_ctx *ctx);
