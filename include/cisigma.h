@@ -289,9 +289,24 @@ int cisigma_autotune(cisigma_ctx *ctx, int dtype, int reps, char *report, int re
 
 /*
  * cisigma_hdiag -- diagonal H_II into the device array hdiag[ndet] (FP64),
- * asynchronously on stream.
+ * asynchronously on stream: the diagonal of H that step (2) of the Davidson
+ * iteration of Sec. 3.3 divides the residual by (the preconditioner), from the
+ * Slater-Condon rules of Eq. 6 with I = J.  hdiag is caller-owned device
+ * memory; EINVAL for a NULL context or array.
  */
 int cisigma_hdiag(cisigma_ctx *ctx, double *hdiag, void *stream);
+
+/*
+ * cisigma_set_log -- JSON-lines log of cisigma_davidson: when path is a
+ * non-empty string, every later Davidson call appends to that file one line per
+ * iteration, {"call": c, "iteration": k, "dim": m, "precision": "fp64"|"mixed",
+ * "energies": [...], "residuals": [...], "sigma_fp32": n, "sigma_fp64": n,
+ * "seconds": t}, and one per FP64 refinement of the mixed mode (key
+ * "refinement", energies = FP64 Rayleigh quotients, residuals = FP64 residual
+ * norms).  NULL or "" stops logging.  The path is copied; the file is opened
+ * and closed by each Davidson call.  EINVAL for a NULL context.
+ */
+int cisigma_set_log(cisigma_ctx *ctx, const char *path);
 
 /*
  * cisigma_davidson -- lowest nroots eigenpairs of H (Sec. 3.3).

@@ -84,6 +84,8 @@ _lib.cisigma_rdm.restype = _i32
 _lib.cisigma_rdm.argtypes = [_vp, _vp, _i32, _vp, _vp, _vp]
 _lib.cisigma_last_path.restype = _i32
 _lib.cisigma_last_path.argtypes = [_vp, _i32, ctypes.POINTER(_i32)]
+_lib.cisigma_set_log.restype = _i32
+_lib.cisigma_set_log.argtypes = [_vp, ctypes.c_char_p]
 _lib.cisigma_apply_noalloc.restype = _i32
 _lib.cisigma_apply_noalloc.argtypes = [_vp, _vp, _vp, _i32, _vp]
 _lib.cisigma_last_shape.restype = _i32
@@ -99,7 +101,7 @@ EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "ci
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
            "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
            "cisigma_hmat_block", "cisigma_autotune", "cisigma_last_shape",
-           "cisigma_apply_noalloc"]
+           "cisigma_apply_noalloc", "cisigma_set_log"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -292,6 +294,10 @@ class Context:
         sh = np.zeros(4, np.int32)
         self._check(_lib.cisigma_last_shape(self._h, int(dtype), sh.ctypes.data))
         return tuple(int(x) for x in sh)
+
+    def set_log(self, path):
+        """Davidson JSON-lines log file (None: off)."""
+        self._check(_lib.cisigma_set_log(self._h, None if path is None else str(path).encode()))
 
     def last_error(self):
         return _lib.cisigma_last_error(self._h).decode()

@@ -1596,6 +1596,12 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
     }
 }
 
+CIS_API int cisigma_set_log(cisigma_ctx *ctx, const char *path) {
+    if (!ctx) return CISIGMA_EINVAL;
+    ctx->log_path = path ? path : "";
+    return CISIGMA_OK;
+}
+
 CIS_API int cisigma_apply(cisigma_ctx *ctx, const void *C, void *sigma, int dtype, void *stream) {
     if (!ctx) return CISIGMA_EINVAL;
     if (!C || !sigma) return cis_set_error(ctx, CISIGMA_EINVAL, "apply: NULL vector");

@@ -634,6 +634,21 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     std::vector<double> erq(nroots, 0.0), r64(nroots, INFINITY);
     std::vector<double> w, Y, col(max_space + 8);
     int m = 0, nnew = nroots, iter = 0, nsig32 = 0, nsig64 = 0, nref = 0;
+    // JSON-lines log (cisigma_set_log): one line per iteration and per FP64 refinement
+    FILE *logf = ctx->log_path.empty() ? nullptr : std::fopen(ctx->log_path.c_str(), "a");
+    const int call = ++ctx->log_calls;
+    struct LogClose { FILE *f; ~LogClose() { if (f) std::fclose(f); } } log_close{logf};
+    auto secs = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    auto log_line = [&](const char *kind, int k, const double *e, const double *res) {
+        if (!logf) return;
+        std::fprintf(logf, "{\"call\": %d, \"%s\": %d, \"dim\": %d, \"precision\": \"%s\", \"energies\": [", call,
+                     kind, k, m, mixed ? "mixed" : "fp64");
+        for (int r = 0; r < nroots; ++r) std::fprintf(logf, "%s%.15g", r ? ", " : "", e[r]);
+        std::fprintf(logf, "], \"residuals\": [");
+        for (int r = 0; r < nroots; ++r) std::fprintf(logf, "%s%.6g", r ? ", " : "", res[r]);
+        std::fprintf(logf, "], \"sigma_fp32\": %d, \"sigma_fp64\": %d, \"seconds\": %.6f}\n", nsig32, nsig64, secs());
+        std::fflush(logf);
+    };
     bool converged = false, have_rq = false, stalled = false;
     int since_ref = 0;
     int rc = CISIGMA_OK;
@@ -707,6 +722,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         bool all_ok = true;
         for (int r = 0; r < nroots; ++r)
             if (!(std::fabs(theta[r] - theta_old[r]) <= tol && rnorm[r] <= rtol)) all_ok = false;
+        log_line("iteration", iter, theta.data(), rnorm.data());
         if (ctx->verbose) {
             std::fprintf(stderr, "davidson it %3d dim %3d", iter, m);
             for (int r = 0; r < nroots; ++r) std::fprintf(stderr, "  E%d %.12f |r| %.3e", r, theta[r], rnorm[r]);
@@ -756,6 +772,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
                 if (rc) return rc;
             }
             have_rq = true;
+            log_line("refinement", nref, erq.data(), r64.data());
             if (ctx->verbose) {
                 std::fprintf(stderr, "  refine %d:", nref);
                 for (int r = 0; r < nroots; ++r) std::fprintf(stderr, "  E%d %.12f |r64| %.3e", r, erq[r], r64[r]);

@@ -219,6 +219,8 @@ struct cisigma_ctx {
     int refine_every = 0;          // mixed mode: 0 = refine only when the FP32 iteration converges
     double resid_tol = -1.0;
     int verbose = 0;
+    std::string log_path;          // Davidson JSON-lines log (cisigma_set_log; empty: none)
+    int log_calls = 0;             // Davidson calls logged so far
     int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]
     int last_shape[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // owner-computes sigma_3 shape of the last apply
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
