@@ -59,6 +59,8 @@ def _load():
     vp, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_uint32
     lib.or_create.restype = vp
     lib.or_create.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, vp]
+    lib.or_create_sym.restype = vp
+    lib.or_create_sym.argtypes = [i32, i32, i32, i32, vp, vp, vp, vp, i32, vp, vp]
     lib.or_free.argtypes = [vp]
     lib.or_ndet.restype = i64
     lib.or_ndet.argtypes = [vp]
@@ -105,10 +107,12 @@ class Space:
 
     ``gas`` is None (CAS) or ``(norb_per_space, min_cum, max_cum)`` with
     cumulative bounds on the total (alpha+beta) electron count of spaces
-    1..g (Sec. 3.1 occupation types).
+    1..g (Sec. 3.1 occupation types).  ``orbsym`` (irrep 0..7 of each
+    orbital, D2h products as XOR) with ``target`` keeps only determinants
+    whose string irreps multiply to the target (the S of Sec. 3.1, Eq. 9).
     """
 
-    def __init__(self, norb, nalpha, nbeta, h1e, eri, gas=None):
+    def __init__(self, norb, nalpha, nbeta, h1e, eri, gas=None, orbsym=None, target=0):
         lib = _load()
         self.norb, self.nalpha, self.nbeta = int(norb), int(nalpha), int(nbeta)
         if gas is None:
@@ -117,8 +121,16 @@ class Space:
         self.gas = (gn.copy(), gmin.copy(), gmax.copy())
         self.h1e = np.ascontiguousarray(h1e, dtype=np.float64).reshape(norb, norb)
         self.eri = np.ascontiguousarray(eri, dtype=np.float64).reshape(norb, norb, norb, norb)
-        self._h = lib.or_create(self.norb, self.nalpha, self.nbeta, len(gn), _ptr(gn), _ptr(gmin),
-                                _ptr(gmax), _ptr(self.h1e), _ptr(self.eri))
+        self.orbsym = None if orbsym is None else np.ascontiguousarray(orbsym, dtype=np.int32).copy()
+        self.target = int(target)
+        if self.orbsym is None:
+            self._h = lib.or_create(self.norb, self.nalpha, self.nbeta, len(gn), _ptr(gn), _ptr(gmin),
+                                    _ptr(gmax), _ptr(self.h1e), _ptr(self.eri))
+        else:
+            assert self.orbsym.size == self.norb
+            self._h = lib.or_create_sym(self.norb, self.nalpha, self.nbeta, len(gn), _ptr(gn), _ptr(gmin),
+                                        _ptr(gmax), _ptr(self.orbsym), self.target, _ptr(self.h1e),
+                                        _ptr(self.eri))
         if not self._h:
             raise ValueError("oracle: invalid space definition")
         self.ndet = int(lib.or_ndet(self._h))

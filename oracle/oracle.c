@@ -13,11 +13,18 @@
  *     electrons in norb spatial orbitals whose cumulative (alpha+beta)
  *     occupation of GAS spaces 1..g lies within [min_cum[g], max_cum[g]] for
  *     every g.  One GAS space whose bounds equal n_alpha+n_beta is the CAS.
+ *   * Spatial symmetry (the S of the TTSS blocks, Sec. 3.1, Eq. 9; the D2h
+ *     spaces of Sec. 4-5), when orbital irreps are given: the irrep of a
+ *     string is the product of the irreps of its occupied orbitals (D2h and
+ *     its subgroups: irreps 0..7, product = bitwise XOR), and the space keeps
+ *     only determinants whose alpha and beta irreps multiply to the target
+ *     irrep.  A string's type is then its per-space counts followed by its
+ *     irrep.
  *   * Determinant order (an interface contract, the paper fixes none):
  *     occupation types sorted lexicographically by their per-space electron
- *     counts; blocks (alpha type, beta type) in alpha-type-major order; inside
- *     a block, row-major [I_alpha][I_beta]; strings of one type in ascending
- *     bitmask order.
+ *     counts (then by irrep); blocks (alpha type, beta type) in
+ *     alpha-type-major order; inside a block, row-major [I_alpha][I_beta];
+ *     strings of one type in ascending bitmask order.
  *   * sigma_I = sum_J <I|H|J> C_J, over every J of the space that differs from
  *     I by at most two spin orbitals (Eq. 4 / Eq. 5; determinants that differ
  *     by more do not couple, Sec. 3.1).  <I|H|J> is the Slater-Condon matrix
@@ -50,13 +57,14 @@
 typedef struct {
     int norb, nel[2];
     int ngas, gas_norb[OR_MAXG], gas_first[OR_MAXG], min_cum[OR_MAXG], max_cum[OR_MAXG];
+    int sym, orbsym[32], target;  /* orbital irreps (0..7) and target irrep when sym != 0 */
     /* per spin: kept strings, sorted by bitmask */
     int nstr[2];
     uint32_t *str[2];
     int *stype[2];
     int *srank[2];
     int ntype[2];
-    int *tocc[2];     /* ntype x ngas */
+    int *tocc[2];     /* ntype x (ngas + 1): per-space counts, then the irrep (0 without symmetry) */
     int *tcount[2];
     int *tstart[2];   /* start of each type inside tlist */
     uint32_t *tlist[2]; /* strings grouped by type, ascending bitmask inside a type */
@@ -71,22 +79,29 @@ typedef struct {
 
 static inline int popc(uint32_t x) { return __builtin_popcount(x); }
 
-/* occupation of each GAS space for a string */
+/* type of a string: occupation of each GAS space, then its irrep */
 static void occ_tuple(const or_space *S, uint32_t s, int *out) {
     for (int g = 0; g < S->ngas; ++g) {
         uint32_t m = 0;
         for (int k = 0; k < S->gas_norb[g]; ++k) m |= 1u << (S->gas_first[g] + k);
         out[g] = popc(s & m);
     }
+    int irrep = 0;
+    if (S->sym)
+        for (int p = 0; p < S->norb; ++p)
+            if ((s >> p) & 1u) irrep ^= S->orbsym[p];
+    out[S->ngas] = irrep;
 }
 
-/* Do an alpha occupation tuple and a beta one form an allowed GAS pair? */
+/* Do an alpha type and a beta type form an allowed pair (GAS bounds, and the
+ * product of their irreps is the target)? */
 static int pair_allowed(const or_space *S, const int *ta, const int *tb) {
     int cum = 0;
     for (int g = 0; g < S->ngas; ++g) {
         cum += ta[g] + tb[g];
         if (cum < S->min_cum[g] || cum > S->max_cum[g]) return 0;
     }
+    if (S->sym && (ta[S->ngas] ^ tb[S->ngas]) != S->target) return 0;
     return 1;
 }
 
@@ -107,13 +122,22 @@ static uint64_t next_comb(uint64_t x) {
 
 void or_free(or_space *S);
 
-/* Build the determinant space.  Returns NULL on bad arguments. */
-or_space *or_create(int norb, int na, int nb, int ngas, const int *gas_norb,
-                    const int *min_cum, const int *max_cum, const double *h, const double *g) {
+/* Build the determinant space (orbsym NULL: no spatial symmetry).  Returns
+ * NULL on bad arguments. */
+or_space *or_create_sym(int norb, int na, int nb, int ngas, const int *gas_norb, const int *min_cum,
+                        const int *max_cum, const int *orbsym, int target, const double *h, const double *g) {
     if (norb < 1 || norb > 32 || na < 0 || nb < 0 || na > norb || nb > norb) return NULL;
     if (ngas < 1 || ngas > OR_MAXG) return NULL;
+    if (orbsym) {
+        if (target < 0 || target > 7) return NULL;
+        for (int p = 0; p < norb; ++p)
+            if (orbsym[p] < 0 || orbsym[p] > 7) return NULL;
+    }
     or_space *S = (or_space *)calloc(1, sizeof(or_space));
     S->norb = norb; S->nel[0] = na; S->nel[1] = nb; S->ngas = ngas;
+    S->sym = orbsym != NULL;
+    S->target = orbsym ? target : 0;
+    for (int p = 0; p < norb; ++p) S->orbsym[p] = orbsym ? orbsym[p] : 0;
     int tot = 0;
     for (int gi = 0; gi < ngas; ++gi) {
         S->gas_first[gi] = tot;
@@ -123,7 +147,7 @@ or_space *or_create(int norb, int na, int nb, int ngas, const int *gas_norb,
         tot += gas_norb[gi];
     }
     if (tot != norb) { free(S); return NULL; }
-    int G = ngas;
+    int G = ngas + 1;   /* type width: per-space counts and the irrep */
     /* enumerate all strings of each spin and their occupation tuples */
     uint32_t *all[2]; int nall[2]; int *allocc[2];
     for (int s = 0; s < 2; ++s) {
@@ -157,7 +181,7 @@ or_space *or_create(int norb, int na, int nb, int ngas, const int *gas_norb,
         }
         /* sort lexicographically (insertion sort; few types) */
         for (int i = 1; i < ntup[s]; ++i) {
-            int tmp[OR_MAXG]; memcpy(tmp, tup[s] + i * G, sizeof(int) * G);
+            int tmp[OR_MAXG + 1]; memcpy(tmp, tup[s] + i * G, sizeof(int) * G);
             int j = i - 1;
             while (j >= 0 && tuple_cmp(tup[s] + j * G, tmp, G) > 0) {
                 memcpy(tup[s] + (j + 1) * G, tup[s] + j * G, sizeof(int) * G); --j;
@@ -234,6 +258,11 @@ or_space *or_create(int norb, int na, int nb, int ngas, const int *gas_norb,
     memcpy(S->g, g, sizeof(double) * n2 * n2);
     for (int s = 0; s < 2; ++s) { free(all[s]); free(allocc[s]); free(tup[s]); free(keep[s]); }
     return S;
+}
+
+or_space *or_create(int norb, int na, int nb, int ngas, const int *gas_norb,
+                    const int *min_cum, const int *max_cum, const double *h, const double *g) {
+    return or_create_sym(norb, na, nb, ngas, gas_norb, min_cum, max_cum, NULL, 0, h, g);
 }
 
 void or_free(or_space *S) {

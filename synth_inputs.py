@@ -22,8 +22,15 @@ the paper's benchmark convention (Sec. 5): every coefficient 1/ndet.
 import numpy as np
 
 
-def integrals(norb, nchol, seed=0):
-    """(h1e[n,n], eri[n,n,n,n]) in FP64 from the recipe above."""
+def integrals(norb, nchol, seed=0, orbsym=None):
+    """(h1e[n,n], eri[n,n,n,n]) in FP64 from the recipe above.
+
+    With ``orbsym`` (irrep 0..7 of each orbital; D2h products as XOR) the same
+    draws are made and then shaped to the point group: h_pq is zeroed unless
+    orbsym[p] == orbsym[q], and factor P carries irrep P % 8, so L^P_pq is
+    zeroed unless orbsym[p] ^ orbsym[q] == P % 8.  (pq|rs) = sum_P L^P_pq L^P_rs
+    is then nonzero only when the four irreps multiply to the totally symmetric
+    one, and stays 8-fold symmetric and PSD."""
     n = int(norb)
     rng = np.random.default_rng(seed)
     eps = np.sort(rng.uniform(-2.0, 1.0, n))
@@ -32,6 +39,11 @@ def integrals(norb, nchol, seed=0):
     h = h + h.T + np.diag(eps)
     L = rng.normal(0.0, 0.15, (int(nchol), n, n))
     L = np.triu(L) + np.transpose(np.triu(L, 1), (0, 2, 1))
+    if orbsym is not None:
+        s = np.asarray(orbsym, dtype=np.int64)
+        pq = s[:, None] ^ s[None, :]
+        h = np.where(pq == 0, h, 0.0)
+        L = np.where(pq[None, :, :] == (np.arange(int(nchol)) % 8)[:, None, None], L, 0.0)
     Lf = L.reshape(int(nchol), n * n)
     eri = (Lf.T @ Lf).reshape(n, n, n, n)
     return np.ascontiguousarray(h), np.ascontiguousarray(eri)
@@ -57,4 +69,9 @@ WORKLOADS = {
     # and at most two particles in space 3 (cumulative total-electron bounds).
     "gas20": dict(norb=20, nalpha=10, nbeta=10, nchol=40,
                   gas=([6, 8, 6], [10, 18, 20], [12, 20, 20])),
+    # D2h-labelled active spaces (the point-group blocking of Sec. 3.1; the paper's
+    # spaces are all D2h, Sec. 4-5): orbital p in irrep p % 8, totally symmetric target
+    "cas12_d2h": dict(norb=12, nalpha=6, nbeta=6, nchol=24, gas=None, orbsym=[p % 8 for p in range(12)], target=0),
+    "cas16_d2h": dict(norb=16, nalpha=8, nbeta=8, nchol=32, gas=None, orbsym=[p % 8 for p in range(16)], target=0),
+    "cas18_d2h": dict(norb=18, nalpha=9, nbeta=9, nchol=36, gas=None, orbsym=[p % 8 for p in range(18)], target=0),
 }

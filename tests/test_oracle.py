@@ -518,3 +518,114 @@ def test_cas66_recipe_values():
     w = np.linalg.eigvalsh(sp.hmat())
     for k in range(4):
         assert abs(w[k] - vals[f"E{k}"]) <= 1e-11, (k, w[k])
+
+
+# ---- spatial symmetry (the S of the TTSS blocks, Sec. 3.1 Eq. 9; D2h spaces, Sec. 4-5) ----
+
+SYM_CASES = [
+    (6, 3, 3, [0, 1, 2, 3, 0, 1], None),
+    (7, 3, 2, [0, 1, 2, 3, 4, 5, 6], None),
+    (8, 4, 4, [p % 8 for p in range(8)], None),
+    (7, 3, 3, [0, 1, 1, 2, 3, 0, 5], ([2, 3, 2], [3, 5, 6], [4, 6, 6])),
+]
+
+
+def _sym_tally(norb, na, nb, orbsym, target, gas):
+    """Independent count and order of the symmetric space: itertools strings,
+    irreps by XOR, GAS bounds, types (counts per space, irrep) sorted."""
+    gn, mn, mx = gas if gas else ([norb], [na + nb], [na + nb])
+    first = np.concatenate([[0], np.cumsum(gn)[:-1]])
+
+    def strings(ne):
+        out = []
+        for occ in itertools.combinations(range(norb), ne):
+            x = sum(1 << p for p in occ)
+            cnt = tuple(sum(1 for p in occ if first[g] <= p < first[g] + gn[g]) for g in range(len(gn)))
+            irr = 0
+            for p in occ:
+                irr ^= orbsym[p]
+            out.append((cnt + (irr,), x))
+        return out
+
+    def ok(ta, tb):
+        c = 0
+        for g in range(len(gn)):
+            c += ta[g] + tb[g]
+            if c < mn[g] or c > mx[g]:
+                return False
+        return (ta[-1] ^ tb[-1]) == target
+
+    A, B = strings(na), strings(nb)
+    ta_all = sorted({t for t, _ in A})
+    tb_all = sorted({t for t, _ in B})
+    ta_k = [t for t in ta_all if any(ok(t, u) for u in tb_all)]
+    tb_k = [u for u in tb_all if any(ok(t, u) for t in ta_all)]
+    dets = []
+    for t in ta_k:
+        for u in tb_k:
+            if ok(t, u):
+                sa = sorted(x for tt, x in A if tt == t)
+                sb = sorted(x for tt, x in B if tt == u)
+                dets += [(a, b) for a in sa for b in sb]
+    return dets
+
+
+@pytest.mark.parametrize("case", SYM_CASES, ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}" + ("gas" if c[4] else ""))
+def test_symmetric_space_order_and_counts(case):
+    norb, na, nb, orbsym, gas = case
+    h, g = si.integrals(norb, 2 * norb, 1, orbsym=orbsym)
+    total = 0
+    for target in range(8):
+        want = _sym_tally(norb, na, nb, orbsym, target, gas)
+        sp = oracle.Space(norb, na, nb, h, g, gas=gas, orbsym=orbsym, target=target)
+        assert sp.ndet == len(want)
+        if sp.ndet:
+            got = [tuple(int(v) for v in d) for d in sp.dets()]
+            assert got == want
+        total += sp.ndet
+    assert total == oracle.Space(norb, na, nb, h, g, gas=gas).ndet
+
+
+def test_symmetric_integrals_recipe():
+    orbsym = [p % 8 for p in range(10)]
+    h, g = si.integrals(10, 20, 3, orbsym=orbsym)
+    s = np.array(orbsym)
+    assert np.all(h[(s[:, None] != s[None, :])] == 0)
+    x = s[:, None, None, None] ^ s[None, :, None, None] ^ s[None, None, :, None] ^ s[None, None, None, :]
+    assert np.all(g[x != 0] == 0)
+    assert np.abs(g[x == 0]).max() > 1e-3
+    assert np.allclose(g, g.transpose(1, 0, 2, 3)) and np.allclose(g, g.transpose(2, 3, 0, 1))
+    assert np.linalg.eigvalsh(g.reshape(100, 100)).min() > -1e-12
+    # the draws before the shaping are those of the unsymmetric recipe
+    h0, _ = si.integrals(10, 20, 3)
+    assert np.array_equal(np.diag(h), np.diag(h0))
+
+
+@pytest.mark.parametrize("case", SYM_CASES[:3], ids=lambda c: f"n{c[0]}a{c[1]}b{c[2]}")
+def test_symmetry_blocks_split_the_spectrum(case):
+    """H with point-group integrals has no element between determinants of
+    different total irrep: the spectra of the eight symmetric spaces together
+    are the spectrum of the whole space (dense eigh), and sigma of a vector
+    of one symmetric space, embedded in the whole space, vanishes outside it
+    and equals that space's own sigma inside."""
+    norb, na, nb, orbsym, gas = case
+    h, g = si.integrals(norb, 2 * norb, 2, orbsym=orbsym)
+    full = oracle.Space(norb, na, nb, h, g, gas=gas)
+    w_full = np.linalg.eigvalsh(full.hmat())
+    parts = []
+    for target in range(8):
+        sp = oracle.Space(norb, na, nb, h, g, gas=gas, orbsym=orbsym, target=target)
+        if sp.ndet == 0:
+            continue
+        parts.append(np.linalg.eigvalsh(sp.hmat()))
+        c = si.ci_vector(sp.ndet, target)
+        idx = np.array([full.address(int(a), int(b)) for a, b in sp.dets()])
+        C = np.zeros(full.ndet)
+        C[idx] = c
+        s_full = full.sigma(C)
+        s_sym = sp.sigma(c)
+        assert np.allclose(s_full[idx], s_sym, atol=1e-12)
+        mask = np.ones(full.ndet, bool)
+        mask[idx] = False
+        assert np.abs(s_full[mask]).max() <= 1e-12
+    assert np.allclose(np.sort(np.concatenate(parts)), w_full, atol=1e-10)
