@@ -172,6 +172,29 @@ typedef struct cisigma_ctx cisigma_ctx;
 int cisigma_init(cisigma_ctx **ctx, int norb, int nalpha, int nbeta, const cisigma_gas *gas,
                  const double *h1e, const double *eri);
 
+/*
+ * cisigma_init_sym -- cisigma_init with spatial (point-group) symmetry, the S of
+ * the TTSS blocks of Sec. 3.1 (Eq. 9) for the D2h spaces of Sec. 4-5.
+ *   orbsym  host int[norb]: the irrep of each orbital, 0..7, in a labelling
+ *           where the product of two irreps is their bitwise XOR (D2h and its
+ *           subgroups C2v, C2h, D2, Cs, Ci, C2, C1), 0 the totally symmetric
+ *           irrep.  NULL: no symmetry (exactly cisigma_init).
+ *   target  the irrep of the space, 0..7.
+ * The irrep of a string is the product of the irreps of its occupied orbitals.
+ * The space keeps the determinants of cisigma_init whose alpha and beta string
+ * irreps multiply to target.  A string type is then (GAS occupation tuple,
+ * irrep): types are ordered by tuple, then by irrep, strings of a type by
+ * ascending bitmask, and blocks (alpha type, beta type) as in cisigma_init
+ * (alpha-type-major, row-major inside).  The integrals must respect the
+ * symmetry: h_pq = 0 unless orbsym[p] == orbsym[q] and (pq|rs) = 0 unless
+ * orbsym[p]^orbsym[q]^orbsym[r]^orbsym[s] == 0, to 1e-12 of the largest
+ * element (EINVAL otherwise), so that H does not couple the space to the
+ * rest.  Sigma and Davidson then act on the symmetric space only.  EINVAL
+ * also for irreps outside 0..7 or an empty space.
+ */
+int cisigma_init_sym(cisigma_ctx **ctx, int norb, int nalpha, int nbeta, const cisigma_gas *gas,
+                     const int *orbsym, int target, const double *h1e, const double *eri);
+
 /* release all device memory of the context; NULL is ignored */
 void cisigma_free(cisigma_ctx *ctx);
 

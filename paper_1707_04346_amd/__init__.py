@@ -56,6 +56,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i32, _i64, _u32, _f64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint32, ctypes.c_double
 _lib.cisigma_init.restype = _i32
 _lib.cisigma_init.argtypes = [ctypes.POINTER(_vp), _i32, _i32, _i32, _vp, _vp, _vp]
+_lib.cisigma_init_sym.restype = _i32
+_lib.cisigma_init_sym.argtypes = [ctypes.POINTER(_vp), _i32, _i32, _i32, _vp, _vp, _i32, _vp, _vp]
 _lib.cisigma_free.restype = None
 _lib.cisigma_free.argtypes = [_vp]
 _lib.cisigma_ndet.restype = _i64
@@ -101,7 +103,7 @@ EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "ci
            "cisigma_excitations", "cisigma_set_option", "cisigma_apply", "cisigma_hdiag", "cisigma_davidson",
            "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
            "cisigma_hmat_block", "cisigma_autotune", "cisigma_last_shape",
-           "cisigma_apply_noalloc", "cisigma_set_log"]
+           "cisigma_apply_noalloc", "cisigma_set_log", "cisigma_init_sym"]
 PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
 
 
@@ -135,9 +137,10 @@ def _stream_ptr(stream):
 
 
 class Context:
-    """cisigma_init / cisigma_free around one (norb, nalpha, nbeta[, gas]) problem."""
+    """cisigma_init (cisigma_init_sym with orbsym) / cisigma_free around one
+    (norb, nalpha, nbeta[, gas][, orbsym, target]) problem."""
 
-    def __init__(self, norb, nalpha, nbeta, h1e, eri, gas=None):
+    def __init__(self, norb, nalpha, nbeta, h1e, eri, gas=None, orbsym=None, target=0):
         h1e = np.ascontiguousarray(h1e, dtype=np.float64)
         eri = np.ascontiguousarray(eri, dtype=np.float64)
         self._keep = []
@@ -149,8 +152,16 @@ class Context:
             self._keep.append(g)
             gp = ctypes.addressof(g)
         h = _vp()
-        st = _lib.cisigma_init(ctypes.byref(h), int(norb), int(nalpha), int(nbeta), gp, h1e.ctypes.data,
-                               eri.ctypes.data)
+        if orbsym is None:
+            st = _lib.cisigma_init(ctypes.byref(h), int(norb), int(nalpha), int(nbeta), gp, h1e.ctypes.data,
+                                   eri.ctypes.data)
+        else:
+            osym = np.ascontiguousarray(orbsym, dtype=np.int32)
+            if osym.size != int(norb):
+                raise CisigmaError(EINVAL, "orbsym needs one irrep per orbital")
+            self._keep.append(osym)
+            st = _lib.cisigma_init_sym(ctypes.byref(h), int(norb), int(nalpha), int(nbeta), gp, osym.ctypes.data,
+                                       int(target), h1e.ctypes.data, eri.ctypes.data)
         if st != OK:
             raise CisigmaError(st, "cisigma_init failed")
         self._h = h

@@ -122,7 +122,8 @@ void free_ctx(cisigma_ctx *c) {
     for (int s = 0; s < 2; ++s) {
         auto &T = c->sp[s];
         (void)hipFree(T.d_str); (void)hipFree(T.d_stype); (void)hipFree(T.d_exc); (void)hipFree(T.d_pairs);
-        (void)hipFree(T.d_tkey); (void)hipFree(T.d_tstart); (void)hipFree(T.d_radix); (void)hipFree(T.d_adiag);
+        (void)hipFree(T.d_gkey); (void)hipFree(T.d_graw); (void)hipFree(T.d_radix); (void)hipFree(T.d_adiag);
+        (void)hipFree(T.d_remap);
         (void)hipFree(T.d_pair_inv);
         auto &L = c->pl[s];
         (void)hipFree(L.d_seg); (void)hipFree(L.d_ld); (void)hipFree(L.d_tile_u); (void)hipFree(L.d_tile_c0);
@@ -161,9 +162,9 @@ int64_t host_string_index(const cisigma_ctx *c, int spin, uint32_t x) {
     if (c->n < 32 && (x >> c->n)) return -1;
     uint64_t key = 0;
     for (int g = 0; g < G; ++g) key += uint64_t(__builtin_popcount(x & c->gas.mask[g])) * c->gas.keymul[g];
-    auto it = std::lower_bound(T.tkey.begin(), T.tkey.end(), key);
-    if (it == T.tkey.end() || *it != key) return -1;
-    int t = int(it - T.tkey.begin());
+    auto it = std::lower_bound(T.gkey.begin(), T.gkey.end(), key);
+    if (it == T.gkey.end() || *it != key) return -1;
+    int t = int(it - T.gkey.begin());
     uint64_t rank = 0, radix = 1;
     for (int g = 0; g < G; ++g) {
         uint32_t sub = (x & c->gas.mask[g]) >> c->gas.first[g];
@@ -176,9 +177,18 @@ int64_t host_string_index(const cisigma_ctx *c, int spin, uint32_t x) {
             sub &= sub - 1;
         }
         rank += r * radix;
-        radix *= binom(__builtin_popcount(c->gas.mask[g]), T.tocc[size_t(t) * G + g]);
+        radix *= binom(__builtin_popcount(c->gas.mask[g]), T.gtocc[size_t(t) * G + g]);
     }
-    return T.tstart[t] + int64_t(rank);
+    const int64_t raw = T.graw[t] + int64_t(rank);
+    return c->sym ? T.remap[size_t(raw)] : raw;
+}
+
+// Are alpha type ta and beta type tb a block of the space: GAS bounds on their
+// occupations and, with spatial symmetry, irreps multiplying to the target?
+bool block_allowed(const cisigma_ctx *c, int ta, int tb) {
+    const int G = c->gas.ngas;
+    if (!pair_allowed(c, &c->sp[0].tocc[size_t(ta) * G], &c->sp[1].tocc[size_t(tb) * G])) return false;
+    return !c->sym || (c->sp[0].tirrep[ta] ^ c->sp[1].tirrep[tb]) == c->target;
 }
 
 int build_integrals(cisigma_ctx *c) {
@@ -302,7 +312,13 @@ int build_active_tiles(cisigma_ctx *c) {
     const int ng = c->gas.ngas;
     const auto &L = c->pl[0];
     auto reach = [&](const cis::SpinTables &S, int t) {
-        std::vector<int> out{t};
+        // types one single excitation can lead to: the same occupations (any irrep
+        // with spatial symmetry) or one electron moved between two GAS spaces
+        std::vector<int> out;
+        for (int u = 0; u < S.ntype; ++u)
+            if (std::equal(S.tocc.begin() + size_t(t) * ng, S.tocc.begin() + size_t(t + 1) * ng,
+                           S.tocc.begin() + size_t(u) * ng))
+                out.push_back(u);
         for (int i = 0; i < ng; ++i)
             for (int j = 0; j < ng; ++j) {
                 if (i == j || S.tocc[size_t(t) * ng + i] == 0) continue;
@@ -568,6 +584,9 @@ int build_scatter_plan(cisigma_ctx *c) {
 // kernel for the shape (or when the tables do not fit) the general kernel runs.
 int build_gas_owner(cisigma_ctx *c) {
     constexpr int WS = 33;
+    // its tables group an alpha string's excitations by source type per type; with
+    // spatial symmetry the source irrep depends on the orbitals, not on the type
+    if (c->sym) return CISIGMA_OK;
     auto &G = c->go;
     const auto &A = c->sp[0], &B = c->sp[1];
     const int n = c->n, ng = c->gas.ngas;
@@ -1157,13 +1176,26 @@ CIS_API int64_t cisigma_ndet(const cisigma_ctx *ctx) { return ctx ? ctx->lay.nde
 
 CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, const cisigma_gas *gas,
                          const double *h1e, const double *eri) {
+    return cisigma_init_sym(out, norb, nalpha, nbeta, gas, nullptr, 0, h1e, eri);
+}
+
+CIS_API int cisigma_init_sym(cisigma_ctx **out, int norb, int nalpha, int nbeta, const cisigma_gas *gas,
+                             const int *orbsym, int target, const double *h1e, const double *eri) {
     if (!out) return CISIGMA_EINVAL;
     *out = nullptr;
     if (norb < 1 || norb > 32 || nalpha < 0 || nbeta < 0 || nalpha > norb || nbeta > norb || !h1e || !eri)
         return CISIGMA_EINVAL;
+    if (orbsym) {
+        if (target < 0 || target > 7) return CISIGMA_EINVAL;
+        for (int p = 0; p < norb; ++p)
+            if (orbsym[p] < 0 || orbsym[p] > 7) return CISIGMA_EINVAL;
+    }
     cisigma_ctx *c = new (std::nothrow) cisigma_ctx();
     if (!c) return CISIGMA_ENOMEM;
     c->n = norb; c->na = nalpha; c->nb = nbeta;
+    c->sym = orbsym != nullptr;
+    c->target = orbsym ? target : 0;
+    for (int p = 0; p < norb; ++p) c->orbsym[p] = orbsym ? orbsym[p] : 0;
     // GAS
     if (gas) {
         if (gas->ngas < 1 || gas->ngas > cis::kMaxGas || !gas->norb || !gas->min_cum || !gas->max_cum) {
@@ -1229,7 +1261,29 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
                         return CISIGMA_EINVAL;
                     }
                 }
-    // occupation types per spin, kept when they pair with a type of the other spin
+    // with spatial symmetry the integrals must respect it: h_pq = 0 unless p and q
+    // share an irrep, (pq|rs) = 0 unless the four irreps multiply to the totally
+    // symmetric one (otherwise H couples the space to determinants outside it)
+    if (c->sym) {
+        for (int p = 0; p < norb; ++p)
+            for (int q = 0; q < norb; ++q)
+                if (c->orbsym[p] != c->orbsym[q] && std::fabs(c->h[size_t(p) * norb + q]) > th) {
+                    cis_set_error(c, CISIGMA_EINVAL, "init: h1e breaks the orbital symmetry");
+                    free_ctx(c);
+                    return CISIGMA_EINVAL;
+                }
+        for (int p = 0; p < norb; ++p)
+            for (int q = 0; q < norb; ++q)
+                for (int r = 0; r < norb; ++r)
+                    for (int t = 0; t < norb; ++t)
+                        if ((c->orbsym[p] ^ c->orbsym[q] ^ c->orbsym[r] ^ c->orbsym[t]) != 0 &&
+                            std::fabs(G4(p, q, r, t)) > tg) {
+                            cis_set_error(c, CISIGMA_EINVAL, "init: eri breaks the orbital symmetry");
+                            free_ctx(c);
+                            return CISIGMA_EINVAL;
+                        }
+    }
+    // GAS occupation tuples per spin, kept when they pair with a tuple of the other spin
     std::vector<std::vector<int>> tup[2];
     for (int s = 0; s < 2; ++s) {
         std::vector<int> cur(G, 0);
@@ -1243,7 +1297,7 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
     for (int s = 0; s < 2; ++s) {
         auto &T = c->sp[s];
         T.nel = s == 0 ? nalpha : nbeta;
-        T.tstart.assign(1, 0);
+        T.graw.assign(1, 0);
         for (size_t i = 0; i < tup[s].size(); ++i) {
             if (!keep[s][i]) continue;
             uint64_t cnt = 1, key = 0;
@@ -1251,18 +1305,108 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
                 cnt *= binom(c->gas_norb[g], tup[s][i][g]);
                 key += uint64_t(tup[s][i][g]) * c->gas.keymul[g];
             }
-            for (int g = 0; g < G; ++g) T.tocc.push_back(tup[s][i][g]);
-            T.tcount.push_back(int(cnt));
-            T.tkey.push_back(key);
-            if (T.tstart.back() + cnt > (1u << 21) - 1) {
+            if (uint64_t(T.graw.back()) + cnt > (uint64_t(1) << (c->sym ? 27 : 21)) - 1) {
+                cis_set_error(c, CISIGMA_EUNSUPPORTED, "init: too many strings of one spin");
+                free_ctx(c);
+                return CISIGMA_EUNSUPPORTED;
+            }
+            for (int g = 0; g < G; ++g) T.gtocc.push_back(tup[s][i][g]);
+            T.gkey.push_back(key);
+            T.graw.push_back(T.graw.back() + int(cnt));
+        }
+        T.ngtype = int(T.gkey.size());
+    }
+    if (!c->sym) {
+        // the types are the GAS types; string index = raw index
+        for (int s = 0; s < 2; ++s) {
+            auto &T = c->sp[s];
+            T.tocc = T.gtocc;
+            T.tstart = T.graw;
+            T.tcount.clear();
+            for (int t = 0; t < T.ngtype; ++t) T.tcount.push_back(T.graw[t + 1] - T.graw[t]);
+            T.tirrep.assign(T.ngtype, 0);
+            T.ntype = T.ngtype;
+            T.nstr = T.tstart.back();
+        }
+    } else {
+        // spatial symmetry: irrep of every raw string (the strings of a GAS type in
+        // ascending order: mixed radix over the GAS spaces, space 0 fastest)
+        std::vector<std::vector<uint8_t>> irr(2);
+        std::vector<std::vector<int>> cnt(2);           // [gtype * 8 + irrep]
+        for (int s = 0; s < 2; ++s) {
+            auto &T = c->sp[s];
+            irr[s].resize(size_t(T.graw.back()));
+            cnt[s].assign(size_t(T.ngtype) * 8, 0);
+            for (int gt = 0; gt < T.ngtype; ++gt) {
+                std::vector<std::vector<int>> sub(G);   // irreps of the sub-strings of each space
+                for (int g = 0; g < G; ++g) {
+                    const int m = c->gas_norb[g], k = T.gtocc[size_t(gt) * G + g];
+                    uint64_t x = (uint64_t(1) << k) - 1;
+                    for (uint64_t q = 0; q < binom(m, k); ++q) {
+                        int ir = 0;
+                        for (int p = 0; p < m; ++p)
+                            if ((x >> p) & 1u) ir ^= c->orbsym[c->gas.first[g] + p];
+                        sub[g].push_back(ir);
+                        if (x == 0) break;
+                        const uint64_t lo = x & (~x + 1), r = x + lo;
+                        x = (((r ^ x) >> 2) / lo) | r;
+                    }
+                }
+                for (int raw = T.graw[gt]; raw < T.graw[gt + 1]; ++raw) {
+                    uint32_t rem = uint32_t(raw - T.graw[gt]);
+                    int ir = 0;
+                    for (int g = 0; g < G; ++g) {
+                        const uint32_t base = uint32_t(sub[g].size());
+                        ir ^= sub[g][rem % base];
+                        rem /= base;
+                    }
+                    irr[s][size_t(raw)] = uint8_t(ir);
+                    ++cnt[s][size_t(gt) * 8 + ir];
+                }
+            }
+        }
+        // types (GAS type, irrep) with strings, kept when they pair with a type of the
+        // other spin: GAS bounds and irreps multiplying to the target
+        std::vector<char> tkeep[2] = {std::vector<char>(size_t(c->sp[0].ngtype) * 8, 0),
+                                      std::vector<char>(size_t(c->sp[1].ngtype) * 8, 0)};
+        for (int a = 0; a < c->sp[0].ngtype; ++a)
+            for (int b = 0; b < c->sp[1].ngtype; ++b) {
+                if (!pair_allowed(c, &c->sp[0].gtocc[size_t(a) * G], &c->sp[1].gtocc[size_t(b) * G])) continue;
+                for (int ia = 0; ia < 8; ++ia) {
+                    const int ib = ia ^ c->target;
+                    if (cnt[0][size_t(a) * 8 + ia] > 0 && cnt[1][size_t(b) * 8 + ib] > 0)
+                        tkeep[0][size_t(a) * 8 + ia] = tkeep[1][size_t(b) * 8 + ib] = 1;
+                }
+            }
+        for (int s = 0; s < 2; ++s) {
+            auto &T = c->sp[s];
+            T.tstart.assign(1, 0);
+            std::vector<int> tid(size_t(T.ngtype) * 8, -1);
+            for (int gt = 0; gt < T.ngtype; ++gt)
+                for (int ir = 0; ir < 8; ++ir) {
+                    if (!tkeep[s][size_t(gt) * 8 + ir]) continue;
+                    tid[size_t(gt) * 8 + ir] = int(T.tcount.size());
+                    for (int g = 0; g < G; ++g) T.tocc.push_back(T.gtocc[size_t(gt) * G + g]);
+                    T.tirrep.push_back(ir);
+                    T.tcount.push_back(cnt[s][size_t(gt) * 8 + ir]);
+                    T.tstart.push_back(T.tstart.back() + T.tcount.back());
+                }
+            T.ntype = int(T.tcount.size());
+            T.nstr = T.tstart.back();
+            if (T.nstr > (1 << 21) - 1) {
                 cis_set_error(c, CISIGMA_EUNSUPPORTED, "init: more than 2^21-1 strings of one spin");
                 free_ctx(c);
                 return CISIGMA_EUNSUPPORTED;
             }
-            T.tstart.push_back(T.tstart.back() + int(cnt));
+            // raw -> string index: strings of a type in ascending raw (= bitmask) order
+            T.remap.assign(size_t(T.graw.back()), -1);
+            std::vector<int> fill(T.tstart.begin(), T.tstart.end() - 1);
+            for (int gt = 0; gt < T.ngtype; ++gt)
+                for (int raw = T.graw[gt]; raw < T.graw[gt + 1]; ++raw) {
+                    const int t = tid[size_t(gt) * 8 + irr[s][size_t(raw)]];
+                    if (t >= 0) T.remap[size_t(raw)] = fill[size_t(t)]++;
+                }
         }
-        T.ntype = int(T.tcount.size());
-        T.nstr = T.tstart.back();
     }
     // blocks in alpha-type-major order
     {
@@ -1272,7 +1416,7 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
         int64_t off = 0;
         for (int a = 0; a < A.ntype; ++a)
             for (int b = 0; b < B.ntype; ++b)
-                if (pair_allowed(c, &A.tocc[size_t(a) * G], &B.tocc[size_t(b) * G])) {
+                if (block_allowed(c, a, b)) {
                     L.boff[size_t(a) * B.ntype + b] = off;
                     L.blk_a.push_back(a);
                     L.blk_b.push_back(b);
@@ -1287,7 +1431,7 @@ CIS_API int cisigma_init(cisigma_ctx **out, int norb, int nalpha, int nbeta, con
             return CISIGMA_EINVAL;
         }
     }
-    c->cas = (c->sp[0].ntype == 1 && c->sp[1].ntype == 1);
+    c->cas = !c->sym && c->sp[0].ntype == 1 && c->sp[1].ntype == 1;
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he == hipSuccess) he = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);

@@ -31,7 +31,17 @@ struct SpinTables {
     std::vector<int> tocc;        // ntype x ngas
     std::vector<int> tcount;      // strings per type
     std::vector<int> tstart;      // ntype + 1
-    std::vector<uint64_t> tkey;   // sorted type keys
+    std::vector<int> tirrep;      // irrep of each type (0 without spatial symmetry)
+    // GAS-level types (occupation tuples) and the raw numbering of their strings:
+    // the strings of GAS type g, in ascending bitmask order, are raw indices
+    // graw[g] .. graw[g+1]-1.  Without spatial symmetry the types are the GAS
+    // types and the raw index is the string index; with it a type is (GAS type,
+    // irrep) and remap[raw] is the string index (-1: the string is in no type).
+    int ngtype = 0;
+    std::vector<int> gtocc;       // ngtype x ngas
+    std::vector<uint64_t> gkey;   // sorted GAS type keys
+    std::vector<int> graw;        // ngtype + 1
+    std::vector<int> remap;       // [graw[ngtype]] (spatial symmetry only)
     int nstr = 0;
     int nexc = 0;                 // single excitations per string: nel*(n-nel)
     // pair (two-electron same-spin) lists over (nel-2)-electron strings K
@@ -43,9 +53,10 @@ struct SpinTables {
     uint32_t *d_exc = nullptr;    // [nstr][nexc] packed single excitations
     uint32_t *d_pairs = nullptr;  // [nK][npv] packed pair entries
     int *d_pair_inv = nullptr;    // [nstr][nel(nel-1)/2] rows K*npv+e producing each string (one type only)
-    uint64_t *d_tkey = nullptr;   // [ntype]
-    int *d_tstart = nullptr;      // [ntype+1]
-    uint32_t *d_radix = nullptr;  // [ntype][ngas]
+    uint64_t *d_gkey = nullptr;   // [ngtype]
+    int *d_graw = nullptr;        // [ngtype+1]
+    uint32_t *d_radix = nullptr;  // [ngtype][ngas] mixed-radix digit weights of the raw rank
+    int *d_remap = nullptr;       // raw index -> string index (spatial symmetry only)
     // per-string diagonal pieces (FP64): sum_{p in I} h_pp + 1/2 sum_{p,q in I} ((pp|qq) - (pq|qp))
     double *d_adiag = nullptr;    // [nstr]
 };
@@ -171,6 +182,9 @@ struct Workspace {
 
 struct cisigma_ctx {
     int n = 0, na = 0, nb = 0;
+    int sym = 0;                   // spatial symmetry (cisigma_init_sym)
+    int orbsym[32] = {0};          // irrep of each orbital (0..7, products as XOR)
+    int target = 0;                // irrep of the space
     cis::GasDesc gas{};
     std::vector<int> gas_norb, gas_min, gas_max;
     cis::SpinTables sp[2];

@@ -313,8 +313,8 @@ hipError_t sigma_ab_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStrea
     a.bstr = B.d_str;
     a.atype = A.d_stype;
     a.btype = B.d_stype;
-    a.astart = A.d_tstart;
-    a.bstart = B.d_tstart;
+    a.astart = ctx->d_tstart[0];
+    a.bstart = ctx->d_tstart[1];
     a.seg = L.d_seg;
     a.ld = L.d_ld;
     a.tile_u = L.d_tile_u;

@@ -13,6 +13,9 @@
 //   drive the same-spin two-electron part of sigma (sigma_1 / sigma_2 of Eq. 8).
 #include "internal.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace cis {
 namespace {
 
@@ -49,10 +52,11 @@ __device__ __forceinline__ uint32_t colex_unrank(uint32_t r, int k, int m) {
 }
 
 struct TypeView {
-    const uint64_t *key;
-    const int *start;
+    const uint64_t *key;     // GAS type keys (sorted)
+    const int *start;        // first raw index of each GAS type
     const uint32_t *radix;
     int ntype;
+    const int *remap;        // raw index -> string index (spatial symmetry), or nullptr
 };
 
 // index of string x in the spin's string list, or -1
@@ -69,7 +73,8 @@ __device__ int string_index(uint32_t x, const GasDesc &g, const TypeView &tv) {
     if (t < 0) return -1;
     uint32_t r = 0;
     for (int s = 0; s < g.ngas; ++s) r += colex_rank((x & g.mask[s]) >> g.first[s]) * tv.radix[t * g.ngas + s];
-    return tv.start[t] + int(r);
+    const int raw = tv.start[t] + int(r);
+    return tv.remap ? tv.remap[raw] : raw;
 }
 
 __global__ void k_unrank(uint32_t *str, int *stype, int t, int start, int count, GasDesc g, const int *occ,
@@ -228,35 +233,74 @@ hipError_t build_string_tables(cisigma_ctx *ctx, int spin) {
     SpinTables &T = ctx->sp[spin];
     const GasDesc &g = ctx->gas;
     int G = g.ngas;
-    // host-side per-type radix
-    std::vector<uint32_t> radix(size_t(T.ntype) * G);
-    for (int t = 0; t < T.ntype; ++t) {
+    // host-side per-GAS-type radix of the raw rank
+    std::vector<uint32_t> radix(size_t(std::max(T.ngtype, 1)) * G, 0);
+    for (int t = 0; t < T.ngtype; ++t) {
         uint64_t r = 1;
         for (int s = 0; s < G; ++s) {
             radix[size_t(t) * G + s] = uint32_t(r);
-            r *= binom_host(__builtin_popcount(g.mask[s]), T.tocc[size_t(t) * G + s]);
+            r *= binom_host(__builtin_popcount(g.mask[s]), T.gtocc[size_t(t) * G + s]);
         }
     }
     size_t ns = size_t(T.nstr > 0 ? T.nstr : 1);
     CIS_TRY(hipMalloc(&T.d_str, ns * sizeof(uint32_t)));
     CIS_TRY(hipMalloc(&T.d_stype, ns * sizeof(int)));
-    CIS_TRY(hipMalloc(&T.d_tkey, size_t(T.ntype > 0 ? T.ntype : 1) * sizeof(uint64_t)));
-    CIS_TRY(hipMalloc(&T.d_tstart, size_t(T.ntype + 1) * sizeof(int)));
-    CIS_TRY(hipMalloc(&T.d_radix, size_t(T.ntype > 0 ? T.ntype : 1) * G * sizeof(uint32_t)));
-    CIS_TRY(hipMemcpy(T.d_tkey, T.tkey.data(), T.ntype * sizeof(uint64_t), hipMemcpyHostToDevice));
-    CIS_TRY(hipMemcpy(T.d_tstart, T.tstart.data(), (T.ntype + 1) * sizeof(int), hipMemcpyHostToDevice));
+    CIS_TRY(hipMalloc(&T.d_gkey, size_t(T.ngtype > 0 ? T.ngtype : 1) * sizeof(uint64_t)));
+    CIS_TRY(hipMalloc(&T.d_graw, size_t(T.ngtype + 1) * sizeof(int)));
+    CIS_TRY(hipMalloc(&T.d_radix, radix.size() * sizeof(uint32_t)));
+    if (T.ngtype > 0) CIS_TRY(hipMemcpy(T.d_gkey, T.gkey.data(), T.ngtype * sizeof(uint64_t), hipMemcpyHostToDevice));
+    CIS_TRY(hipMemcpy(T.d_graw, T.graw.data(), (T.ngtype + 1) * sizeof(int), hipMemcpyHostToDevice));
     CIS_TRY(hipMemcpy(T.d_radix, radix.data(), radix.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     int *d_occ = nullptr;
     CIS_TRY(hipMalloc(&d_occ, size_t(T.ntype > 0 ? T.ntype : 1) * G * sizeof(int)));
-    CIS_TRY(hipMemcpy(d_occ, T.tocc.data(), T.tocc.size() * sizeof(int), hipMemcpyHostToDevice));
-    for (int t = 0; t < T.ntype; ++t) {
-        int cnt = T.tcount[t];
-        if (cnt == 0) continue;
-        hipLaunchKernelGGL(k_unrank, dim3((cnt + 255) / 256), dim3(256), 0, ctx->stream, T.d_str, T.d_stype, t,
-                           T.tstart[t], cnt, g, d_occ + t * G, T.d_radix + t * G);
-        CIS_TRY(hipGetLastError());
+    if (!ctx->sym) {
+        // the strings of each type by their mixed-radix rank on the device
+        CIS_TRY(hipMemcpy(d_occ, T.tocc.data(), T.tocc.size() * sizeof(int), hipMemcpyHostToDevice));
+        for (int t = 0; t < T.ntype; ++t) {
+            int cnt = T.tcount[t];
+            if (cnt == 0) continue;
+            hipLaunchKernelGGL(k_unrank, dim3((cnt + 255) / 256), dim3(256), 0, ctx->stream, T.d_str, T.d_stype, t,
+                               T.tstart[t], cnt, g, d_occ + t * G, T.d_radix + t * G);
+            CIS_TRY(hipGetLastError());
+        }
+    } else {
+        // spatial symmetry: the strings of each (GAS type, irrep) type, in order, from the
+        // host enumeration of the raw strings, and the raw -> string index map
+        std::vector<uint32_t> str(ns, 0);
+        std::vector<int> stype(ns, 0);
+        for (int gt = 0; gt < T.ngtype; ++gt) {
+            std::vector<std::vector<uint32_t>> sub(G);
+            for (int s2 = 0; s2 < G; ++s2) {
+                const int m = __builtin_popcount(g.mask[s2]), k = T.gtocc[size_t(gt) * G + s2];
+                uint64_t x = (uint64_t(1) << k) - 1;
+                for (uint64_t c = 0; c < binom_host(m, k); ++c) {
+                    sub[s2].push_back(uint32_t(x) << g.first[s2]);
+                    if (x == 0) break;
+                    const uint64_t lo = x & (~x + 1), r = x + lo;
+                    x = (((r ^ x) >> 2) / lo) | r;
+                }
+            }
+            for (int raw = T.graw[gt]; raw < T.graw[gt + 1]; ++raw) {
+                const int idx = T.remap[raw];
+                if (idx < 0) continue;
+                uint32_t rem = uint32_t(raw - T.graw[gt]), x = 0;
+                for (int s2 = 0; s2 < G; ++s2) {
+                    const uint32_t base = uint32_t(sub[s2].size());
+                    x |= sub[s2][rem % base];
+                    rem /= base;
+                }
+                str[idx] = x;
+            }
+        }
+        for (int t = 0; t < T.ntype; ++t)
+            for (int i = T.tstart[t]; i < T.tstart[t + 1]; ++i) stype[i] = t;
+        CIS_TRY(hipMemcpy(T.d_str, str.data(), size_t(T.nstr) * sizeof(uint32_t), hipMemcpyHostToDevice));
+        CIS_TRY(hipMemcpy(T.d_stype, stype.data(), size_t(T.nstr) * sizeof(int), hipMemcpyHostToDevice));
+        CIS_TRY(hipMalloc(&T.d_remap, std::max<size_t>(T.remap.size(), 1) * sizeof(int)));
+        if (!T.remap.empty())
+            CIS_TRY(hipMemcpy(T.d_remap, T.remap.data(), T.remap.size() * sizeof(int), hipMemcpyHostToDevice));
     }
-    TypeView tv{T.d_tkey, T.d_tstart, T.d_radix, T.ntype};
+    TypeView tv{T.d_gkey, T.d_graw, T.d_radix, T.ngtype, T.d_remap};
     // single-excitation lists
     T.nexc = T.nel * (g.n - T.nel);
     if (T.nexc > 0 && T.nstr > 0) {
