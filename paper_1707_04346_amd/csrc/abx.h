@@ -103,6 +103,50 @@ __device__ __forceinline__ void abx_scatter(const T *W, T *sig, const uint32_t (
     *d = *d + carry;
 }
 
+// The same for a tile whose plan uses only its first n (1..EW, uniform) entries
+// per lane: the others are neither read nor written.
+template <typename T, int EW, int TS = (sizeof(T) == 4 ? 0 : 3)>
+__device__ __forceinline__ void abx_scatter_n(const T *W, T *sig, const uint32_t (&w)[EW], uint32_t hdr,
+                                              uint32_t spare, int n) {
+    const char *wb = reinterpret_cast<const char *>(W);
+    char *sb = reinterpret_cast<char *>(sig);
+    T val[EW], old[EW];
+    uint32_t t[EW];
+#pragma unroll
+    for (int q = 0; q < EW; ++q) {
+        if (q >= n) break;
+        t[q] = (w[q] >> 16) << TS;
+        val[q] = flip_if(*reinterpret_cast<const T *>(wb + (w[q] & 0xfffeu)), w[q]);
+        old[q] = *reinterpret_cast<const T *>(sb + t[q]);
+    }
+    T run = 0;
+    bool any_start = (hdr & 1u) != 0;
+    uint32_t last = spare;
+#pragma unroll
+    for (int q = 0; q < EW; ++q) {
+        if (q >= n) break;
+        const bool st = q == 0 ? (hdr & 1u) != 0 : t[q - 1] != spare;
+        any_start = any_start || st;
+        run = st ? val[q] : run + val[q];
+        *reinterpret_cast<T *>(sb + t[q]) = old[q] + run;
+        last = t[q];
+    }
+    const T tail = last != spare ? T(0) : run;
+    const T carry = carry3<T>(tail, any_start ? 1 : 0);
+    T *d = reinterpret_cast<T *>(sb + (hdr & ~3u));
+    *d = *d + carry;
+}
+
+// plan words of the first n entries and the header (the header stays at index EW)
+template <int EW>
+__device__ __forceinline__ void abx_plan_load_n(__amdgpu_buffer_rsrc_t pr, uint32_t pl, uint32_t soff,
+                                                uint32_t (&w)[EW], uint32_t &hdr, int n) {
+#pragma unroll
+    for (int q = 0; q < EW; ++q)
+        if (q < n) w[q] = buffer_ld_u32(pr, pl + q * 256u, soff);
+    hdr = buffer_ld_u32(pr, pl + EW * 256u, soff);
+}
+
 template <int EW>
 __device__ __forceinline__ void abx_plan_load(__amdgpu_buffer_rsrc_t pr, uint32_t pl, uint32_t soff, uint32_t (&w)[EW],
                                               uint32_t &hdr) {

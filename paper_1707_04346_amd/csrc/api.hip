@@ -479,8 +479,11 @@ bool plan_fits(const PlanTiles &pt, int ew) {
     return true;
 }
 
-// plan words of every tile for entry count ew, appended to out[FP64], out[FP32]
-void plan_emit(const PlanSpec &ps, const PlanTiles &pt, int ew, std::vector<uint32_t> (&out)[2]) {
+// plan words of every tile for entry count ew, appended to out[FP64], out[FP32];
+// with widths, tile t spreads its entries over widths[t] <= ew entries per lane
+// (the remaining words of each lane are padding; the header stays at index ew)
+void plan_emit(const PlanSpec &ps, const PlanTiles &pt, int ew, std::vector<uint32_t> (&out)[2],
+               const std::vector<int> *widths = nullptr) {
     const size_t per_wave = size_t(ew + 1) * 64, per_tile = 4 * per_wave;
     std::vector<std::pair<size_t, size_t>> rg;
     for (int es_i = 0; es_i < 2; ++es_i) {
@@ -490,7 +493,8 @@ void plan_emit(const PlanSpec &ps, const PlanTiles &pt, int ew, std::vector<uint
         PL.resize(base0 + per_tile * pt.tiles.size());
         for (size_t t = 0; t < pt.tiles.size(); ++t) {
             const auto &tile = pt.tiles[t];
-            plan_ranges(tile, ew, rg);
+            const int w = widths ? (*widths)[t] : ew;
+            plan_ranges(tile, w, rg);
             for (int wv = 0; wv < 4; ++wv) {
                 const size_t base = base0 + (t * 4 + wv) * per_wave;
                 const size_t i = wv < int(rg.size()) ? rg[wv].first : 0, j = wv < int(rg.size()) ? rg[wv].second : 0;
@@ -499,16 +503,16 @@ void plan_emit(const PlanSpec &ps, const PlanTiles &pt, int ew, std::vector<uint
                     const uint32_t unit = ps.unit[es_i];                         // slot field unit, bytes
                     uint32_t hdr = spare | 1u;
                     for (int q = 0; q < ew; ++q) {
-                        const size_t e = i + size_t(lane) * ew + q;
+                        const size_t e = i + size_t(lane) * w + q;
                         uint32_t word = (spare / unit) << 16;                    // padding: W element 0, discard slot
-                        if (e < j) {
+                        if (q < w && e < j) {
                             const PlanItem &it = tile[e];
                             const uint32_t slot = it.end ? it.tgt * es : spare;
                             word = ((slot / unit) << 16) | (it.widx * es) | it.neg;
                             if (q == 0 && !it.start) {
                                 // continued group: its end in this lane takes the carry
                                 hdr = spare;
-                                for (size_t f = e; f < i + size_t(lane + 1) * ew && f < j; ++f)
+                                for (size_t f = e; f < i + size_t(lane + 1) * w && f < j; ++f)
                                     if (tile[f].end) { hdr = tile[f].tgt * es; break; }
                             }
                         }
@@ -790,12 +794,18 @@ int build_gas_owner(cisigma_ctx *c) {
         if (ew == 0) continue;
         std::vector<uint32_t> plan[2], act;
         int tile0 = 0;
+        std::vector<std::pair<size_t, size_t>> rgw;
         for (size_t k = 0; k < units.size(); ++k) {
-            plan_emit(specs[k], pts[k], ew, plan);
+            // each tile at the fewest entries per lane that hold it (the kernel reads no more)
+            std::vector<int> widths(pts[k].tiles.size(), ew);
+            for (size_t t = 0; t < widths.size(); ++t)
+                for (int w = 1; w < ew; ++w)
+                    if (plan_ranges(pts[k].tiles[t], w, rgw)) { widths[t] = w; break; }
+            plan_emit(specs[k], pts[k], ew, plan, &widths);
             units[k].act0 = int(act.size() / 4);
             units[k].nact = int(uact[k].size());
             for (size_t t = 0; t < uact[k].size(); ++t) {
-                act.push_back(uint32_t(tile0 + int(t)));
+                act.push_back(uint32_t(tile0 + int(t)) | (uint32_t(widths[t]) << 24));
                 act.push_back(uact[k][t][1]);
                 act.push_back(uact[k][t][2]);
                 act.push_back(uact[k][t][3]);
