@@ -54,6 +54,8 @@ def sigma3_min_products(spec):
     per block from the occupation types alone; returns (products, ndet)."""
     import math
     n, na, nb = spec["norb"], spec["nalpha"], spec["nbeta"]
+    if spec.get("orbsym") is not None:
+        return _sigma3_min_products_sym(spec)
     gn, mn, mx = spec["gas"] if spec["gas"] else ([n], [na + nb], [na + nb])
     G = len(gn)
 
@@ -102,6 +104,41 @@ def sigma3_min_products(spec):
             ndet += nd
             tot += nd * sum(ca * cb for sa, ca in moves(ta) for sb, cb in moves(tb) if allowed(sa, sb))
     return tot, ndet
+
+
+def _sigma3_min_products_sym(spec):
+    """sigma3_min_products for a CAS with orbital irreps (D2h products = XOR):
+    an (alpha excitation i <- j, beta excitation k <- l) product of a
+    determinant of the space has its source in the space exactly when the
+    irreps of i, j, k, l multiply to the totally symmetric one (the same rule
+    that leaves (ij|kl) nonzero).  With h(I, g) the single excitations of
+    string I (E_kk included) whose two orbitals multiply to g, the count is
+    sum over irreps a, g of H_alpha[a][g] H_beta[a ^ target][g], H[a][g] the sum
+    of h over the strings of irrep a."""
+    import itertools
+    n, na, nb = spec["norb"], spec["nalpha"], spec["nbeta"]
+    sym, tgt = spec["orbsym"], spec.get("target", 0)
+
+    def hist(ne):
+        H = [[0] * 8 for _ in range(8)]
+        cnt = [0] * 8
+        for occ in itertools.combinations(range(n), ne):
+            irr = 0
+            for p in occ:
+                irr ^= sym[p]
+            cnt[irr] += 1
+            occ_set = set(occ)
+            for j in occ:
+                for i in range(n):
+                    if i == j or i not in occ_set:
+                        H[irr][sym[i] ^ sym[j]] += 1
+        return H, cnt
+
+    Ha, ca = hist(na)
+    Hb, cb = hist(nb)
+    prod = sum(Ha[a][g] * Hb[a ^ tgt][g] for a in range(8) for g in range(8))
+    ndet = sum(ca[a] * cb[a ^ tgt] for a in range(8))
+    return prod, ndet
 
 
 def same_spin_floors(spec, ndet, w):
@@ -168,7 +205,8 @@ def cpu_baseline(spec, h, g, C_dev, target_s, gpu_sigmas):
     same vector).  Returns (baseline, errors, one-thread sigma builds/s)."""
     import numpy as np
     import oracle
-    sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
+    sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"], orbsym=spec.get("orbsym"),
+                      target=spec.get("target", 0))
     c = C_dev.double().cpu().numpy()
     rng = np.random.default_rng(7)
     nrows, done, t_used = 64, 0, 0.0
@@ -323,7 +361,8 @@ def cpu_leg_energy_check(spec, h, g, vecs, energies, nrows, seed, full_space=Tru
     sector may lie between its roots."""
     import numpy as np
     import oracle
-    sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
+    sp = oracle.Space(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"], orbsym=spec.get("orbsym"),
+                      target=spec.get("target", 0))
     rng = np.random.default_rng(seed)
     rows = np.unique(rng.integers(0, sp.ndet, nrows))
     out = []
@@ -390,10 +429,12 @@ def extra_workload(name, cis, torch, si, steps, warmup, fp64):
     sigma_3 kernel's fraction of the matrix-core peak on the method's own work
     (the sparse minimum of sigma3_min_products)."""
     spec = si.WORKLOADS[name]
-    h, g = si.integrals(spec["norb"], spec["nchol"], 0)
+    h, g = si.integrals(spec["norb"], spec["nchol"], 0, orbsym=spec.get("orbsym"))
     t0 = time.perf_counter()
-    ctx = cis.Context(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"])
-    out = {"ndet": ctx.ndet, "init_seconds": time.perf_counter() - t0, "gas": spec["gas"]}
+    ctx = cis.Context(spec["norb"], spec["nalpha"], spec["nbeta"], h, g, gas=spec["gas"],
+                      orbsym=spec.get("orbsym"), target=spec.get("target", 0))
+    out = {"ndet": ctx.ndet, "init_seconds": time.perf_counter() - t0, "gas": spec["gas"],
+           "orbsym": spec.get("orbsym"), "target": spec.get("target")}
     prod, nd = sigma3_min_products(spec)
     assert nd == ctx.ndet
     out["sigma3_min_flops"] = 2.0 * prod
@@ -437,7 +478,7 @@ def main():
                     help="let cisigma_autotune pick the launch parameters before timing (its report goes to extra)")
     ap.add_argument("--check-rows", type=int, default=10000,
                     help="random rows of the oracle's sigma per Davidson eigenvector (energy check)")
-    ap.add_argument("--extra-workloads", default="gas20,cas18",
+    ap.add_argument("--extra-workloads", default="gas20,cas18,cas16_d2h",
                     help="comma list of other configurations whose sigma is timed into extra.workloads ('' for none)")
     ap.add_argument("--extra-steps", type=int, default=3, help="timed sigma builds per extra workload")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -453,9 +494,9 @@ def main():
 
     spec = si.WORKLOADS[args.workload]
     n, na, nb = spec["norb"], spec["nalpha"], spec["nbeta"]
-    h, g = si.integrals(n, spec["nchol"], 0)
+    h, g = si.integrals(n, spec["nchol"], 0, orbsym=spec.get("orbsym"))
     t0 = time.perf_counter()
-    ctx = cis.Context(n, na, nb, h, g, gas=spec["gas"])
+    ctx = cis.Context(n, na, nb, h, g, gas=spec["gas"], orbsym=spec.get("orbsym"), target=spec.get("target", 0))
     init_s = time.perf_counter() - t0
     log(f"init {args.workload}: ndet={ctx.ndet} in {init_s:.2f} s")
 
@@ -477,7 +518,7 @@ def main():
              "fp32_path": {"ab_owner_computes": bool(path32 & cis.PATH_AB_OWNER),
                            "same_spin_materialised": bool(path32 & cis.PATH_SS_MATERIALISED)}}
     # M_S = 0 sector (n_alpha = n_beta, one block): the beta-beta pass is replaced by a transpose
-    sector = na == nb and spec["gas"] is None
+    sector = na == nb and spec["gas"] is None and spec.get("orbsym") is None
     if sector:
         dtp, ppp, _, _ = time_sigma(ctx, cis, torch, "fp32", args.steps, 1, parity=1)
         extra.update({"fp32_even_sector_sigma_per_s": args.steps / dtp,
@@ -514,7 +555,7 @@ def main():
                 "issued_flops": issued, "issued_frac": issued / ab_s / 1e12 / PEAK["fp32"],
                 "avg_launch_ms": pp32["sigma_ab"]}
     extra["sigma_ab_tflops_fp32"] = achieved
-    if spec["gas"] is None:
+    if spec["gas"] is None and spec.get("orbsym") is None:
         # same-spin passes against their floors: t / max(HBM floor, VALU floor); the
         # counter bytes (when the committed summary matches the kernel source) beside them
         ss = same_spin_floors(spec, ctx.ndet, 4)
@@ -533,7 +574,7 @@ def main():
         extra["sigma_ab_frac_fp64"] = extra["sigma_ab_tflops_fp64"] / PEAK["fp64"]
 
     # NEXT: spin-summed 1- and 2-particle density matrices (one-block spaces, n <= 16)
-    if spec["gas"] is None and n <= 16 and not args.no_rdm:
+    if spec["gas"] is None and spec.get("orbsym") is None and n <= 16 and not args.no_rdm:
         extra["rdm"] = time_rdm(ctx, torch, n, na, nb, ctx.ndet)
         log(f"rdm: {extra['rdm']}")
 
@@ -579,6 +620,7 @@ def main():
 
     cfg = {"workload": f"{args.workload}: {n} orbitals, {na} alpha + {nb} beta electrons"
                        + (f", GAS {spec['gas']}" if spec["gas"] else " (CAS)")
+                       + (f", orbital irreps {spec['orbsym']} target {spec['target']}" if spec.get("orbsym") else "")
                        + f", {ndet} determinants, seeded synthetic integrals (P={spec['nchol']})",
            "ndet": ndet, "norb": n, "nalpha": na, "nbeta": nb}
     line = {
