@@ -75,7 +75,15 @@ extern "C" {
 #define CISIGMA_OPT_RESID_TOL 5    /* residual-norm threshold; default sqrt(tol) (mixed: max(sqrt(tol), 1e-5)) */
 #define CISIGMA_OPT_VERBOSE 6      /* print one line per Davidson iteration to stderr when nonzero */
 #define CISIGMA_OPT_PROFILE 7      /* nonzero: time every pass of cisigma_apply with HIP events (resets the totals) */
-#define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels */
+#define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels;
+                                      2: for one-block spaces, the owner-computes units of the GAS form
+                                      in place of the one-block owner kernel (rebuilds the unit tables) */
+#define CISIGMA_OPT_UNIT_COLS 18   /* owner-computes units (GAS spaces, one-block spaces whose sigma row is
+                                      longer than the LDS, or path 2): at most this many sigma columns per
+                                      unit, 64..65536; 0 (default): as many as the LDS holds.  Rows are cut
+                                      at beta-type ends (GAS) or at the occupation classes of the two
+                                      highest orbitals (one-block), and inside a piece only when it alone
+                                      is longer.  Rebuilds the unit tables */
 #define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products: at most this many columns per chunk
                                       (a positive multiple of 64); 0 (default): as many as fit in memory */
 #define CISIGMA_OPT_OVERLAP 12     /* nonzero: cisigma_apply runs the beta-beta pass on a second
@@ -90,8 +98,9 @@ extern "C" {
                                       0 (default) most source tiles per row first, 1 alpha-type order,
                                       2 most total work first, 3 heavy and light alternating; set by
                                       cisigma_autotune per precision */
-#define CISIGMA_OPT_SS_SPLIT 17     /* column split of the grid of the same-spin kernels that scatter with
-                                      atomics (GAS spaces), 1..64; 0 (default): a heuristic; set by
+#define CISIGMA_OPT_SS_SPLIT 17     /* column split of the grid of the same-spin pair-product kernel of
+                                      spaces with several types (GAS or point-group symmetry; row-store
+                                      or atomic form), 1..64; 0 (default): a heuristic; set by
                                       cisigma_autotune */
 #define CISIGMA_OPT_LOW_MEMORY 15   /* nonzero: the mixed-precision Davidson frees the FP32 sigma workspace
                                       before each FP64 refinement and the FP64 one after it, so only one is
@@ -387,8 +396,11 @@ int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls);
 /*
  * cisigma_last_path -- which kernels the most recent cisigma_apply of dtype
  * used, as CISIGMA_PATH_* flags in *flags (0 before any apply).  One-block
- * (CAS) spaces normally take both fast paths; GAS spaces and shapes outside
- * the fast kernels' range use the general scatter kernels (no flags).
+ * (CAS) and GAS spaces, with or without point-group symmetry, normally take
+ * the materialised same-spin form; sigma_3 takes an owner-computes kernel
+ * except with point-group symmetry.  Shapes outside the fast kernels' range,
+ * spaces whose stored rows do not fit in memory, and CISIGMA_OPT_SIGMA_PATH = 1
+ * use the general scatter kernels (flag clear).
  */
 #define CISIGMA_PATH_AB_OWNER 1          /* sigma_3 by the owner-computes kernel (no global atomics) */
 #define CISIGMA_PATH_SS_MATERIALISED 2   /* same-spin parts by materialised pair products + gather */
@@ -403,7 +415,9 @@ int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags);
  *   shape[2]  scatter-plan entries per lane and tile
  *   shape[3]  0: no owner-computes kernel ran (general kernel); 1: one-block
  *             kernel with the own row in a k step; 2: one-block kernel with the
- *             own row as the rank-1 start of the accumulators; 3: GAS units
+ *             own row as the rank-1 start of the accumulators; 3: units of
+ *             the GAS form (four waves); 4: units of a one-block space with
+ *             its sigma row split, eight-wave form (FP32)
  * shape is a host int[4], written.  EINVAL for NULL arguments or a bad dtype.
  */
 int cisigma_last_shape(const cisigma_ctx *ctx, int dtype, int *shape);

@@ -124,7 +124,7 @@ void free_ctx(cisigma_ctx *c) {
         (void)hipFree(T.d_str); (void)hipFree(T.d_stype); (void)hipFree(T.d_exc); (void)hipFree(T.d_pairs);
         (void)hipFree(T.d_gkey); (void)hipFree(T.d_graw); (void)hipFree(T.d_radix); (void)hipFree(T.d_adiag);
         (void)hipFree(T.d_remap);
-        (void)hipFree(T.d_pair_inv);
+        (void)hipFree(T.d_pair_inv); (void)hipFree(T.d_yoff); (void)hipFree(T.d_ycol); (void)hipFree(T.d_klist);
         auto &L = c->pl[s];
         (void)hipFree(L.d_seg); (void)hipFree(L.d_ld); (void)hipFree(L.d_tile_u); (void)hipFree(L.d_tile_c0);
         (void)hipFree(c->d_tstart[s]);
@@ -583,24 +583,31 @@ int build_scatter_plan(cisigma_ctx *c) {
 // by source type (the source type of an excitation depends only on ta, since
 // spaces are contiguous orbital ranges), then the string itself; per alpha type
 // the 32-column source tiles (one beta type each) with the k steps whose
-// gathered rows have a block with that beta type and the row blocks whose
-// pairs move a source of that beta type into a block of ta.  Without a compiled
-// kernel for the shape (or when the tables do not fit) the general kernel runs.
-int build_gas_owner(cisigma_ctx *c) {
+// gathered rows have a block with that beta type.  Per unit (alpha type x
+// column range that fits the LDS) the tiles that reach the range, each with the
+// 16-row W blocks its plan entries read.  Without a compiled kernel for the
+// shape (or when the tables do not fit) the general kernel runs.
+//
+// One-block spaces come here when their sigma row is too long for the one-block
+// kernel (or on request, CISIGMA_OPT_SIGMA_PATH = 2).  Their units split the row
+// at the occupations of the two highest orbitals t1 = n-2 < t2 = n-1: in colex
+// order the strings with a given occupation of (t2, t1) are one contiguous
+// range.  A single excitation E_kl keeps both occupations unless k or l is t1
+// or t2, so the W rows are grouped, each group on whole 16-row blocks, as
+//   pairs that keep both (k, l < t1; (t1,t1), (t2,t2); and (t2,t1), which
+//   only swaps an electron between t1 and t2), then (t1, l < t1), then
+//   (t2, l < t1),
+// and a source tile of another class than the unit's multiplies only the
+// blocks that lead into it (one or two instead of all).
+int build_gas_owner(cisigma_ctx *c, bool one_block) {
     constexpr int WS = 33;
-    // its tables group an alpha string's excitations by source type per type; with
-    // spatial symmetry the source irrep depends on the orbitals, not on the type
-    if (c->sym) return CISIGMA_OK;
     auto &G = c->go;
     const auto &A = c->sp[0], &B = c->sp[1];
     const int n = c->n, ng = c->gas.ngas;
     // one-block spaces come here only when the one-block owner kernel has no plan
-    // (more than 16 orbitals, or a sigma row longer than its LDS)
-    if ((c->cas && c->plan.ew > 0) || c->na == 0 || c->nb == 0 || A.nexc == 0 || B.nexc == 0) return CISIGMA_OK;
-    const int rb = (c->npair + 15) / 16, mp = 16 * rb;
-    const int ks = (A.nexc + 1 + 3) / 4, kp = 4 * ks;
-    if (ks > 32 || rb > 32 || B.ntype > 255 || size_t(mp) * WS * 8 >= 65536) return CISIGMA_OK;
-    if (cis::sigma_ab_gas_width(ks, rb, 1) == 0) return CISIGMA_OK;
+    // (more than 16 orbitals, or a sigma row longer than its LDS), or on request
+    if ((c->cas && c->plan.ew > 0 && !one_block) || c->na == 0 || c->nb == 0 || A.nexc == 0 || B.nexc == 0)
+        return CISIGMA_OK;
     std::vector<int> space(n, 0);
     for (int g = 0; g < ng; ++g)
         for (int o = 0; o < n; ++o)
@@ -608,11 +615,60 @@ int build_gas_owner(cisigma_ctx *c) {
     std::vector<std::pair<int, int>> pairs;
     for (int k = 0; k < n; ++k)
         for (int l = 0; l <= k; ++l) pairs.push_back({k, l});
-    std::stable_sort(pairs.begin(), pairs.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
-        return std::make_pair(space[x.first], space[x.second]) < std::make_pair(space[y.first], space[y.second]);
-    });
     std::vector<int> row_of(c->npair);
-    for (int r = 0; r < c->npair; ++r) row_of[cis::pair_ge(pairs[r].first, pairs[r].second)] = r;
+    int nrows = 0;
+    const bool classes = c->cas && n >= 3;
+    if (classes) {
+        const int t1 = n - 2, t2 = n - 1;
+        auto group = [&](int k, int l) { return k < t1 || k == l || (k == t2 && l == t1) ? 0 : k == t1 ? 1 : 2; };
+        for (int g = 0; g < 3; ++g) {
+            for (const auto &pr : pairs)
+                if (group(pr.first, pr.second) == g) row_of[cis::pair_ge(pr.first, pr.second)] = nrows++;
+            nrows = (nrows + 15) / 16 * 16;
+        }
+        // Placement for the eight-wave unit kernel, whose producing waves take three
+        // runs of w = ceil(blocks / 3) row blocks: the (t2, l) block ends the first
+        // run, the (t1, l) block ends the last, and (t2, t1) takes the last row of the
+        // second run, so that a source tile of the other t2 class (it needs only the
+        // (t2, l) block and (t2, t1)) keeps two SIMDs busy instead of one.
+        const int nb = nrows / 16, w = (nb + 2) / 3;
+        if (t1 <= 16 && nb >= 6 && 2 * w - 1 < nb - 1) {
+            std::vector<int> inner_rows;   // rows of the inner blocks in order, the swap slot held back
+            const int b17 = w - 1, b16 = nb - 1, bsw = 2 * w - 1;
+            for (int b = 0; b < nb; ++b)
+                if (b != b17 && b != b16)
+                    for (int r = 0; r < 16; ++r)
+                        if (!(b == bsw && r == 15)) inner_rows.push_back(16 * b + r);
+            size_t q = 0;
+            int r16 = 16 * b16, r17 = 16 * b17;
+            bool fits = true;
+            for (const auto &pr : pairs) {
+                const int k = pr.first, l = pr.second, idx = cis::pair_ge(k, l);
+                if (k == t2 && l == t1) row_of[idx] = 16 * bsw + 15;
+                else if (group(k, l) == 0) { if (q < inner_rows.size()) row_of[idx] = inner_rows[q++]; else fits = false; }
+                else if (group(k, l) == 1) row_of[idx] = r16++;
+                else row_of[idx] = r17++;
+            }
+            if (!fits || r16 > 16 * b16 + 16 || r17 > 16 * b17 + 16) {   // back to the grouped order
+                nrows = 0;
+                for (int g = 0; g < 3; ++g) {
+                    for (const auto &pr : pairs)
+                        if (group(pr.first, pr.second) == g) row_of[cis::pair_ge(pr.first, pr.second)] = nrows++;
+                    nrows = (nrows + 15) / 16 * 16;
+                }
+            }
+        }
+    } else {
+        std::stable_sort(pairs.begin(), pairs.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            return std::make_pair(space[x.first], space[x.second]) < std::make_pair(space[y.first], space[y.second]);
+        });
+        for (int r = 0; r < c->npair; ++r) row_of[cis::pair_ge(pairs[r].first, pairs[r].second)] = r;
+        nrows = c->npair;
+    }
+    const int rb = (nrows + 15) / 16, mp = 16 * rb;
+    const int ks = (A.nexc + 1 + 3) / 4, kp = 4 * ks;
+    if (ks > 32 || rb > 32 || B.ntype > 255 || size_t(mp) * WS * 8 >= 65536) return CISIGMA_OK;
+    if (cis::sigma_ab_gas_width(ks, rb, 1) == 0) return CISIGMA_OK;
     // type moved by one electron from space `from` to space `to` (-1: no such type)
     auto moved = [&](const cis::SpinTables &S, int t, int from, int to) {
         if (from == to) return t;
@@ -627,9 +683,20 @@ int build_gas_owner(cisigma_ctx *c) {
     auto allowed = [&](int ta, int tb) { return ta >= 0 && tb >= 0 && c->lay.boff[size_t(ta) * B.ntype + tb] >= 0; };
     std::vector<int> gsize(ng, 0);
     for (int o = 0; o < n; ++o) ++gsize[space[o]];
-    // gathered-row slots of each alpha type
+    // gathered-row slots of each alpha type.  With spatial symmetry the source type
+    // of an excitation depends on its orbitals' irreps, not on the type alone: the
+    // slots then follow the excitation list (source "any", -3), every k step is
+    // multiplied, and the tiles and row blocks come from the plans alone.
     std::vector<int> slot(size_t(A.ntype) * kp, -1), slot_src(size_t(A.ntype) * kp, -1);
-    for (int ta = 0; ta < A.ntype; ++ta) {
+    for (int ta = 0; ta < A.ntype && c->sym; ++ta) {
+        for (int q = 0; q < A.nexc; ++q) {
+            slot[size_t(ta) * kp + q] = q;
+            slot_src[size_t(ta) * kp + q] = -3;
+        }
+        slot[size_t(ta) * kp + A.nexc] = -2;
+        slot_src[size_t(ta) * kp + A.nexc] = ta;
+    }
+    for (int ta = 0; ta < A.ntype && !c->sym; ++ta) {
         std::vector<int> occ_space, vir_space;   // GAS space of the i-th occupied / virtual orbital
         for (int g = 0; g < ng; ++g) {
             const int occ = A.tocc[size_t(ta) * ng + g];
@@ -668,12 +735,19 @@ int build_gas_owner(cisigma_ctx *c) {
     for (int ta = 0; ta < A.ntype; ++ta) {
         std::vector<uint32_t> kmask(B.ntype, 0), rmask(B.ntype, 0);
         for (int u2 = 0; u2 < B.ntype; ++u2) {
-            for (int q = 0; q < kp; ++q)
-                if (allowed(slot_src[size_t(ta) * kp + q], u2)) kmask[u2] |= 1u << (q / 4);
-            for (int r = 0; r < c->npair; ++r) {
-                const int sk = space[pairs[r].first], sl = space[pairs[r].second];
+            for (int q = 0; q < kp; ++q) {
+                const int src = slot_src[size_t(ta) * kp + q];
+                if (src == -3 || allowed(src, u2)) kmask[u2] |= 1u << (q / 4);
+            }
+            if (c->sym) {
+                rmask[u2] = rb >= 32 ? 0xffffffffu : (1u << rb) - 1u;   // narrowed per tile by the plans
+                continue;
+            }
+            for (const auto &pr : pairs) {
+                const int sk = space[pr.first], sl = space[pr.second];
                 // E_kl or E_lk on a source of type u2 moves one electron between the two spaces
-                if (allowed(ta, moved(B, u2, sl, sk)) || allowed(ta, moved(B, u2, sk, sl))) rmask[u2] |= 1u << (r / 16);
+                if (allowed(ta, moved(B, u2, sl, sk)) || allowed(ta, moved(B, u2, sk, sl)))
+                    rmask[u2] |= 1u << (row_of[cis::pair_ge(pr.first, pr.second)] / 16);
             }
         }
         for (size_t t = 0; t < tu.size(); ++t)
@@ -684,8 +758,9 @@ int build_gas_owner(cisigma_ctx *c) {
     std::vector<double> g64(size_t(n) * n * mp, 0.0);
     std::vector<float> g32(g64.size(), 0.0f);
     for (int ij = 0; ij < n * n; ++ij)
-        for (int r = 0; r < c->npair; ++r) {
-            const double v = c->g[(size_t(ij) * n + pairs[r].first) * n + pairs[r].second];
+        for (const auto &pr : pairs) {
+            const int r = row_of[cis::pair_ge(pr.first, pr.second)];
+            const double v = c->g[(size_t(ij) * n + pr.first) * n + pr.second];
             g64[size_t(ij) * mp + r] = v;
             g32[size_t(ij) * mp + r] = float(v);
         }
@@ -698,13 +773,45 @@ int build_gas_owner(cisigma_ctx *c) {
     const int ntb = B.ntype;
     int64_t ldmax = 0;
     for (int v : c->pl[0].ld) ldmax = std::max<int64_t>(ldmax, v);
+    // where units may end: the ends of the beta types (GAS; in compact columns per
+    // alpha type) or of the top-orbital classes (one-block), cut further only
+    // where a piece alone is longer than a unit may be
+    std::vector<int> class_end;
+    if (classes) {
+        auto cls = [&](int Jb) { return int((str[Jb] >> (n - 2)) & 3u); };
+        for (int Jb = 1; Jb <= B.nstr; ++Jb) {
+            if (Jb < B.nstr && cls(Jb) < cls(Jb - 1)) { class_end.clear(); break; }   // not colex: plain cuts
+            if (Jb == B.nstr || cls(Jb) != cls(Jb - 1)) class_end.push_back(Jb);
+        }
+    }
+    auto cuts_of = [&](int ta, int cap) {
+        std::vector<int> ends;
+        if (classes) {
+            ends = class_end;
+        } else {
+            for (int u = 0; u < ntb; ++u)
+                if (coff[size_t(ta) * ntb + u] >= 0) ends.push_back(coff[size_t(ta) * ntb + u] + B.tcount[u]);
+        }
+        if (ends.empty() || ends.back() != ncols[ta]) ends = {ncols[ta]};
+        std::vector<int> cut{0};
+        int lo = 0, hi = 0;
+        for (int e : ends) {
+            if (e - lo <= cap) { hi = e; continue; }
+            if (hi > lo) { cut.push_back(hi); lo = hi; }
+            while (e - lo > cap) { lo += cap; cut.push_back(lo); }
+            hi = e;
+        }
+        if (hi > lo) cut.push_back(hi);
+        return cut;
+    };
     for (int d = 0; d < 2; ++d) {
         const size_t es = d == 0 ? 8 : 4;
-        // the kernel addresses C with 32-bit byte offsets (its zero row included)
-        if ((uint64_t(c->pl[0].size) + uint64_t(ldmax)) * es >= (uint64_t(1) << 31)) continue;
+        // the kernel addresses C with 32-bit element offsets (its zero row included)
+        if (uint64_t(c->pl[0].size) + uint64_t(ldmax) >= (uint64_t(1) << 32)) continue;
         const size_t fixed = (size_t(16) * rb * WS + 64) * es + size_t(4) * kp * ntb;
         if (fixed >= 160 * 1024) continue;
-        const int cmax = int(std::min<size_t>((160 * 1024 - fixed) / es, 65536 - 64 - 1));
+        int cmax = int(std::min<size_t>((160 * 1024 - fixed) / es, 65536 - 64 - 1));
+        if (c->unit_cols > 0) cmax = std::min(cmax, c->unit_cols);
         std::vector<cis::GasUnit> units;
         std::vector<PlanSpec> specs;
         std::vector<PlanTiles> pts;
@@ -712,8 +819,9 @@ int build_gas_owner(cisigma_ctx *c) {
         int need = 1;
         for (int ta = 0; ta < A.ntype; ++ta) {
             if (tact[ta].empty() || A.tcount[ta] == 0) continue;
-            for (int lo = 0; lo < ncols[ta]; lo += cmax) {
-                const int hi = std::min(ncols[ta], lo + cmax);
+            const std::vector<int> cut = cuts_of(ta, cmax);
+            for (size_t ci = 0; ci + 1 < cut.size(); ++ci) {
+                const int lo = cut[ci], hi = cut[ci + 1];
                 const auto &ta_tiles = tact[ta];
                 PlanSpec ps;
                 ps.ntile = int(ta_tiles.size());
@@ -734,12 +842,16 @@ int build_gas_owner(cisigma_ctx *c) {
                 PlanTiles pt;
                 rc = plan_items(c, ps, exc, str, pt);
                 if (rc) return rc;
-                // keep the tiles with at least one target in the range
+                // keep the tiles with at least one target in the range, each with the
+                // W row blocks its entries read (the only ones it multiplies)
                 std::vector<std::array<uint32_t, 4>> keep;
                 PlanTiles kept;
                 for (size_t t = 0; t < pt.tiles.size(); ++t)
                     if (!pt.tiles[t].empty()) {
+                        uint32_t used = 0;
+                        for (const auto &it : pt.tiles[t]) used |= 1u << (it.widx / WS / 16);
                         keep.push_back(ta_tiles[t]);
+                        keep.back()[2] = used;
                         kept.tiles.push_back(std::move(pt.tiles[t]));
                     }
                 if (keep.empty()) continue;
@@ -755,13 +867,16 @@ int build_gas_owner(cisigma_ctx *c) {
             }
         }
         if (units.empty()) continue;
-        // splitting rows repeats the products of every tile that reaches several
-        // units: give the precision to the general kernel when that more than
-        // doubles them
+        // splitting rows repeats the gathers of every tile that reaches several
+        // units, and its products where they lead into several: give the
+        // precision to the general kernel when the row-block products more than
+        // double
         {
             double split = 0, whole = 0;
-            for (size_t k = 0; k < units.size(); ++k) split += double(uact[k].size()) * A.tcount[units[k].ta];
-            for (int ta = 0; ta < A.ntype; ++ta) whole += double(tact[ta].size()) * A.tcount[ta];
+            for (size_t k = 0; k < units.size(); ++k)
+                for (const auto &e : uact[k]) split += double(__builtin_popcount(e[2])) * A.tcount[units[k].ta];
+            for (int ta = 0; ta < A.ntype; ++ta)
+                for (const auto &e : tact[ta]) whole += double(__builtin_popcount(e[2])) * A.tcount[ta];
             if (split > 2.0 * whole) continue;
         }
         // longest rows of work first (one launch covers every unit; the longest workgroups start first)
@@ -839,6 +954,122 @@ int build_gas_owner(cisigma_ctx *c) {
     return CISIGMA_OK;
 }
 
+// Same-spin tables of spaces with several types (GAS occupation types or
+// irreps).  (1) Pair lists: many entries of a K lead out of the space (GAS
+// bounds, irreps), so each K's entries in the space are moved to the front of
+// its list (the inverse table follows) and the K are grouped by that count
+// into buckets, each launched with the smallest compiled pair-kernel shape that
+// holds its count.  (2) Rows of the materialised products: the product row of
+// pair entry (K, e) is the padded sigma row of the string J = K + e, so the
+// gather of string I sums the rows of its occupied pairs element by element, as
+// for one-block spaces; rows follow the entries in (K, e) order.  Only when
+// every spin with pairs has at most 64 occupied pairs per string; otherwise
+// the same-spin parts stay on the atomic kernels.
+int build_same_spin_rows(cisigma_ctx *c) {
+    if (c->cas) return CISIGMA_OK;
+    for (int s = 0; s < 2; ++s) {
+        auto &S = c->sp[s];
+        if (S.nel < 2 || S.nstr == 0 || S.nK == 0 || !S.d_pairs) continue;
+        std::vector<uint32_t> pairs(size_t(S.nK) * S.npv);
+        HIP_OR_FAIL(c, hipMemcpy(pairs.data(), S.d_pairs, pairs.size() * 4, hipMemcpyDeviceToHost), "init: pair lists");
+        std::vector<int> newpos(pairs.size()), count(S.nK, 0);
+        for (int K = 0; K < S.nK; ++K) {
+            uint32_t *row = pairs.data() + size_t(K) * S.npv;
+            int *np = newpos.data() + size_t(K) * S.npv;
+            std::vector<uint32_t> in, out;
+            for (int e = 0; e < S.npv; ++e) {
+                if (row[e] != cis::kPairNone) { np[e] = int(in.size()); in.push_back(row[e]); }
+            }
+            count[K] = int(in.size());
+            int q = count[K];
+            for (int e = 0; e < S.npv; ++e)
+                if (row[e] == cis::kPairNone) np[e] = q++;
+            for (int e = 0; e < S.npv; ++e) row[e] = e < count[K] ? in[e] : cis::kPairNone;
+        }
+        // buckets: K ordered by the shape that holds its count
+        std::vector<std::pair<int, int>> shape_of(S.nK, {-1, -1});
+        bool ok = true;
+        for (int K = 0; K < S.nK && ok; ++K)
+            if (count[K] > 0) ok = cis::same_spin_shape_for(count[K], &shape_of[K].first, &shape_of[K].second);
+        if (!ok) continue;   // keep the plain lists
+        HIP_OR_FAIL(c, hipMemcpy(S.d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice), "init: pair lists");
+        if (S.d_pair_inv) {
+            const size_t per = size_t(S.nel) * (S.nel - 1) / 2;
+            std::vector<int> inv(size_t(S.nstr) * per);
+            HIP_OR_FAIL(c, hipMemcpy(inv.data(), S.d_pair_inv, inv.size() * 4, hipMemcpyDeviceToHost), "init: pair lists");
+            for (int &v : inv)
+                if (v >= 0) v = (v / S.npv) * S.npv + newpos[size_t(v)];
+            HIP_OR_FAIL(c, hipMemcpy(S.d_pair_inv, inv.data(), inv.size() * 4, hipMemcpyHostToDevice), "init: pair lists");
+        }
+        std::vector<std::pair<int, int>> shapes;
+        for (int K = 0; K < S.nK; ++K)
+            if (count[K] > 0 && std::find(shapes.begin(), shapes.end(), shape_of[K]) == shapes.end())
+                shapes.push_back(shape_of[K]);
+        std::sort(shapes.begin(), shapes.end(), [](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+            return 16 * x.second * 4 * x.first > 16 * y.second * 4 * y.first;   // heaviest buckets first
+        });
+        std::vector<int> klist;
+        S.bk_ks.clear(); S.bk_mbl.clear(); S.bk_start.assign(1, 0);
+        for (const auto &sh : shapes) {
+            for (int K = 0; K < S.nK; ++K)
+                if (count[K] > 0 && shape_of[K] == sh) klist.push_back(K);
+            S.bk_ks.push_back(sh.first);
+            S.bk_mbl.push_back(sh.second);
+            S.bk_start.push_back(int(klist.size()));
+        }
+        if (klist.empty()) klist.push_back(0);
+        HIP_OR_FAIL(c, upload(&S.d_klist, klist), "init: pair lists");
+    }
+    for (int s = 0; s < 2; ++s) {
+        const auto &S = c->sp[s];
+        if (S.nel < 2 || S.nstr == 0) continue;
+        if (S.nel * (S.nel - 1) / 2 > 64 || !S.d_pair_inv || !S.d_pairs || !S.d_klist) return CISIGMA_OK;
+    }
+    for (int s = 0; s < 2; ++s) {
+        auto &S = c->sp[s];
+        if (S.nel < 2 || S.nstr == 0) continue;
+        const auto &L = c->pl[s];
+        const int nto = c->sp[1 - s].ntype;
+        std::vector<int> ycol(size_t(S.ntype) * nto, -1);
+        std::vector<int64_t> rowlen(S.ntype, 0);
+        for (int t = 0; t < S.ntype; ++t)
+            for (int u = 0; u < nto; ++u)
+                if (L.seg[size_t(t) * nto + u] >= 0) {
+                    ycol[size_t(t) * nto + u] = int(rowlen[t]);
+                    rowlen[t] += L.ld[u];
+                }
+        std::vector<uint32_t> pairs(size_t(S.nK) * S.npv);
+        std::vector<int> stype(S.nstr);
+        HIP_OR_FAIL(c, hipMemcpy(pairs.data(), S.d_pairs, pairs.size() * 4, hipMemcpyDeviceToHost), "init: same-spin rows");
+        HIP_OR_FAIL(c, hipMemcpy(stype.data(), S.d_stype, stype.size() * 4, hipMemcpyDeviceToHost), "init: same-spin rows");
+        std::vector<int64_t> yoff(pairs.size(), -1);
+        int64_t tot = 0;
+        for (size_t i = 0; i < pairs.size(); ++i) {
+            if (pairs[i] == cis::kPairNone) continue;
+            yoff[i] = tot;
+            tot += rowlen[stype[pairs[i] >> 11]];
+        }
+        HIP_OR_FAIL(c, upload(&S.d_yoff, yoff), "init: same-spin rows");
+        HIP_OR_FAIL(c, upload(&S.d_ycol, ycol), "init: same-spin rows");
+        S.ny = tot;
+    }
+    return CISIGMA_OK;
+}
+
+// elements of the materialised same-spin rows of a space with several types
+// (the larger spin; the passes reuse one buffer), 0: none
+int64_t ys_rows_elems(const cisigma_ctx *c) {
+    if (c->cas) return 0;
+    int64_t m = 0;
+    for (int s = 0; s < 2; ++s) {
+        const auto &S = c->sp[s];
+        if (S.nel < 2 || S.nstr == 0) continue;
+        if (S.ny == 0) return 0;
+        m = std::max(m, S.ny);
+    }
+    return m;
+}
+
 // bytes of one alpha-major (*na) and one beta-major (*nb) layout copy of a
 // dtype's workspace; one-block spaces (and GAS spaces with owner tables) add
 // one zero row after the copy (rows the owner-computes sigma_3 and the
@@ -900,6 +1131,14 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
         else
             W.ys = nullptr;
     }
+    // several types: all rows at once when they fit in half of what is free
+    const int64_t ny = ys_rows_elems(c);
+    if (ny > 0 && hipMemGetInfo(&fr, &tot) == hipSuccess) {
+        if (size_t(ny) * es <= fr / 2 && hipMalloc(&W.ys, size_t(ny) * es) == hipSuccess)
+            W.ys_chunk = 0;
+        else
+            W.ys = nullptr;
+    }
     if (!c->side) {
         HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking), "apply: side stream");
         HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming), "apply: side stream");
@@ -921,7 +1160,7 @@ namespace {
 int apply_sigma_ws(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStream_t s, const Workspace &W,
                    bool own) {
     // one-type spins with room for the materialised same-spin rows avoid global atomics there
-    const bool mat = c->cas && c->ab_mode == 0 && W.ys != nullptr;
+    const bool mat = c->ab_mode != 1 && W.ys != nullptr;   // W.ys only where the form applies
     hipEvent_t ev[CISIGMA_NPASS + 1];
     const bool prof = own && c->profile;
     if (prof) {
@@ -1027,6 +1266,8 @@ int apply_sigma_noalloc(cisigma_ctx *c, const void *C, void *sigma, int dtype, h
             W.ys_chunk = int(chunk);
         }
     }
+    const int64_t ny = ys_rows_elems(c);
+    if (ny > 0 && size_t(ny) * es <= kNoallocScratchBytes - copies) W.ys = base + copies;
     W.ready = true;
     HIP_OR_FAIL(c, launch_fill(W.cp, int64_t(na / es), dtype, s), "apply_noalloc: clear");
     HIP_OR_FAIL(c, launch_fill(W.ct, int64_t(nb / es), dtype, s), "apply_noalloc: clear");
@@ -1070,6 +1311,26 @@ int gas_set_unit_order(cisigma_ctx *c, int d, int order) {
                 "unit order");
     c->unit_order[d] = order;
     return CISIGMA_OK;
+}
+
+// Drops the owner-computes unit tables and builds them again (after a change of
+// the unit width or of the one-block request), keeping each precision's unit order.
+int rebuild_gas_owner(cisigma_ctx *c) {
+    HIP_OR_FAIL(c, hipDeviceSynchronize(), "owner units");
+    drop_graphs(c);
+    GasOwner &G = c->go;
+    (void)hipFree(G.d_slot); (void)hipFree(G.d_coff); (void)hipFree(G.d_g32); (void)hipFree(G.d_g64);
+    for (int d = 0; d < 2; ++d) {
+        (void)hipFree(G.d_act[d]);
+        (void)hipFree(G.d_units[d]);
+        (void)hipFree(G.plan[d].d_entries[0]);
+        (void)hipFree(G.plan[d].d_entries[1]);
+    }
+    G = GasOwner{};
+    int rc = build_gas_owner(c, c->ab_mode == 2);
+    for (int d = 0; d < 2 && rc == CISIGMA_OK; ++d)
+        if (c->unit_order[d]) rc = gas_set_unit_order(c, d, c->unit_order[d]);
+    return rc;
 }
 
 bool workspace_fits(cisigma_ctx *c, int dtype) {
@@ -1470,7 +1731,8 @@ CIS_API int cisigma_init_sym(cisigma_ctx **out, int norb, int nalpha, int nbeta,
     }
     if (!rc) rc = build_active_tiles(c);
     if (!rc) rc = build_scatter_plan(c);
-    if (!rc) rc = build_gas_owner(c);
+    if (!rc) rc = build_gas_owner(c, false);
+    if (!rc) rc = build_same_spin_rows(c);
     if (rc) {
         std::fprintf(stderr, "cisigma_init: %s\n", c->err.c_str());
         free_ctx(c);
@@ -1613,10 +1875,12 @@ CIS_API int cisigma_autotune(cisigma_ctx *ctx, int dtype, int reps, char *report
         std::snprintf(line, sizeof line, "gas_unit_order -> %d\n", best);
         rep += line;
     }
-    // knob 2: column split of the same-spin atomic kernels (spaces without the materialised form)
-    // (the workspace exists now: the materialised form is used exactly when its rows were allocated)
-    const bool atomic_ss = !(ctx->cas && ctx->ab_mode == 0 && ctx->ws[d].ys != nullptr);
-    if (atomic_ss && (ctx->sp[0].nel >= 2 || ctx->sp[1].nel >= 2)) {
+    // knob 2: column split of the grid of the same-spin kernel of spaces with several
+    // types (atomic or row-store form); one-block spaces with their rows stored use
+    // their own kernel.  (The workspace exists now: rows are stored exactly when
+    // they were allocated.)
+    const bool split_used = !(ctx->cas && ctx->ab_mode != 1 && ctx->ws[d].ys != nullptr);
+    if (split_used && (ctx->sp[0].nel >= 2 || ctx->sp[1].nel >= 2)) {
         int best = 0;
         float best_ms = 0;
         const int cands[] = {0, 1, 2, 4, 8, 16, 32};
@@ -1691,11 +1955,19 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
         case CISIGMA_OPT_VERBOSE:
             ctx->verbose = int(value);
             return CISIGMA_OK;
-        case CISIGMA_OPT_SIGMA_PATH:
+        case CISIGMA_OPT_SIGMA_PATH: {
             cis::drop_graphs(ctx);
-            if (value != 0 && value != 1) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0 or 1");
+            if (value != 0 && value != 1 && value != 2)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0, 1 or 2");
+            const bool rebuild = ctx->cas && (value == 2) != (ctx->ab_mode == 2);
             ctx->ab_mode = int(value);
-            return CISIGMA_OK;
+            return rebuild ? cis::rebuild_gas_owner(ctx) : CISIGMA_OK;
+        }
+        case CISIGMA_OPT_UNIT_COLS:
+            if (value < 0 || value > 65536 || value != std::floor(value) || (value > 0 && value < 64))
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit columns must be 0 or 64..65536");
+            ctx->unit_cols = int(value);
+            return cis::rebuild_gas_owner(ctx);
         case CISIGMA_OPT_SS_CHUNK:
             cis::drop_graphs(ctx);
             if (value < 0 || value > (1 << 30) || value != std::floor(value) || int64_t(value) % cis::kTileCols)

@@ -52,7 +52,18 @@ struct SpinTables {
     int *d_stype = nullptr;       // [nstr] type of each string
     uint32_t *d_exc = nullptr;    // [nstr][nexc] packed single excitations
     uint32_t *d_pairs = nullptr;  // [nK][npv] packed pair entries
-    int *d_pair_inv = nullptr;    // [nstr][nel(nel-1)/2] rows K*npv+e producing each string (one type only)
+    int *d_pair_inv = nullptr;    // [nstr][nel(nel-1)/2] rows K*npv+e producing each string
+    // materialised same-spin rows of spaces with several types: the row of pair
+    // entry (K, e), which produces string J, is J's padded sigma row (the blocks
+    // allowed with J's type, concatenated); ny = 0: no such rows
+    int64_t ny = 0;               // elements of all rows
+    int64_t *d_yoff = nullptr;    // [nK][npv] first element of each entry's row (-1: no string)
+    int *d_ycol = nullptr;        // [ntype][ntype_other] offset of each block in a row (-1: not allowed)
+    // spaces with several types: the entries of each K whose string is in the space
+    // come first in its pair list, and the K are grouped by that count into
+    // buckets of one compiled pair-kernel shape each (K without entries in none)
+    std::vector<int> bk_ks, bk_mbl, bk_start;   // per bucket: shape, first position in d_klist (+ end)
+    int *d_klist = nullptr;                     // K indices, bucket by bucket
     uint64_t *d_gkey = nullptr;   // [ngtype]
     int *d_graw = nullptr;        // [ngtype+1]
     uint32_t *d_radix = nullptr;  // [ngtype][ngas] mixed-radix digit weights of the raw rank
@@ -238,7 +249,8 @@ struct cisigma_ctx {
     int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]
     int last_shape[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // owner-computes sigma_3 shape of the last apply
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
-    int ab_mode = 0;
+    int ab_mode = 0;               // CISIGMA_OPT_SIGMA_PATH
+    int unit_cols = 0;             // CISIGMA_OPT_UNIT_COLS (0: what the LDS holds)
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)
     int spin_parity = 0;   // M_S = 0 sector: C(Ib, Ia) = p C(Ia, Ib) assumed (0: none)
     // captured apply graphs (CISIGMA_OPT_GRAPH)
@@ -294,6 +306,9 @@ hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *
 // whether the same-spin pair count npv has compiled MFMA kernels (else a plain
 // atomic kernel serves it and the materialised form is not used)
 bool same_spin_materialisable(int npv);
+// smallest compiled same-spin pair-kernel shape (k steps, 16-row blocks) for
+// lists of `count` pairs; false when none is compiled
+bool same_spin_shape_for(int count, int *ks, int *mbl);
 // caller vector -> alpha-major and beta-major padded copies
 hipError_t launch_scatter_in(const cisigma_ctx *ctx, const void *C, void *cp, void *ct, int dtype, hipStream_t s);
 // sigma = alpha-major accumulator + transpose of the beta-major accumulator
@@ -338,6 +353,7 @@ bool workspace_fits(cisigma_ctx *ctx, int dtype);
 // row first (as built), 1 alpha type order, 2 most total work first, 3 heavy
 // and light alternating; rewrites the device unit table
 int gas_set_unit_order(cisigma_ctx *ctx, int d, int order);
+int rebuild_gas_owner(cisigma_ctx *ctx);
 int release_workspace(cisigma_ctx *ctx, int dtype);
 
 }  // namespace cis

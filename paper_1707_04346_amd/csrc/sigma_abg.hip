@@ -1,6 +1,7 @@
 // sigma_abg.hip -- owner-computes form of the alpha-beta part sigma_3 (Eq. 8)
-// for GAS spaces (Sec. 3.1 occupation types), and for one-block spaces whose
-// sigma row is too long for the one-block kernel.  The contraction and the
+// for spaces with several string types (GAS occupation types and point-group
+// irreps, Sec. 3.1), and for one-block spaces whose sigma row is too long for
+// the one-block kernel.  The contraction and the
 // beta-side scatter are those of the one-block form (abx.h); what differs is
 // which source tiles, k steps and W rows each alpha type needs, and that a
 // sigma row holds only the columns of the blocks allowed with the type.
@@ -43,8 +44,9 @@ struct AbgArgs {
     const int *coff;             // [nta][ntb] first compact column of each allowed block (-1: not allowed)
     const int *units;            // [nunits][8]: ta, lo, hi, act0, nact, first alpha string, first workgroup
     const uint32_t *plan;
-    uint32_t cp_bytes, plan_bytes, zero_off;
-    int anexc, n, npair, mp, ntb, nunits;
+    uint32_t plan_bytes, zero_off;   // zero_off: element index of the zero row (C may exceed 4 GB)
+    int ld0;                         // row stride of one-block spaces (the eight-wave unit kernel)
+    int anexc, n, mp, ntb, nunits;   // mp: W rows (pair rows with gaps; unused rows have zero integrals)
     int nvirt;                   // the longest unit row (LDS layout)
 };
 
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *W = reinterpret_cast<T *>(smem_raw);                // [MP][WS]
     T *sig = W + MP * kAbxWS;                              // [nvirt + 64]
-    uint32_t *rowoff = reinterpret_cast<uint32_t *>(sig + p.nvirt + 64);   // [ntb][KP] byte offsets
+    uint32_t *rowoff = reinterpret_cast<uint32_t *>(sig + p.nvirt + 64);   // [ntb][KP] element offsets
 
     int ui = 0;                                            // this workgroup's unit (uniform)
     while (ui + 1 < p.nunits && int(blockIdx.x) >= p.units[8 * (ui + 1) + 6]) ++ui;
@@ -100,7 +102,7 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
             const int64_t s = p.seg[int64_t(t2) * p.ntb + u];
             if (s >= 0) off = uint32_t(s + int64_t(Ja - p.astart[t2]) * p.ld[u]);
         }
-        rowoff[idx] = off * uint32_t(sizeof(T));
+        rowoff[idx] = off;
     }
     // A fragments: row m (grouped pair order) = 16*(rb0 + r) + lane%16, gathered row 4t + lane/16
     T A[RBW][KS];
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         for (int r = 0; r < RBW; ++r) {
             const int m = (rb0 + r) * 16 + (lane & 15);
             T val = 0;
-            if (r < nrb && m < p.npair) {
+            if (r < nrb && m < p.mp) {
                 if (g) {
                     val = sg * g[m];
                 } else if (e == -2) {
@@ -139,21 +141,22 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
 
     const int nact = U[4];
     if (nact > 0) {
-        const __amdgpu_buffer_rsrc_t cr = buffer_of(p.cp, p.cp_bytes), pr = buffer_of(p.plan, p.plan_bytes);
-        const uint32_t colb = uint32_t(cb * 16 + (lane & 15)) * uint32_t(sizeof(T));
+        const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
+        const T *cl = p.cp + (cb * 16 + (lane & 15));   // this lane's column of the item's first column
         const uint32_t pl = uint32_t(wave * PW + lane) * 4u;
         const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
         const uint4 *act = p.act + U[3];
         T bc[KS], bn[KS];
         acc_t acc[RBW], acc2[RBW];
         // gathered rows of an item for every k step: one LDS offset read each
-        // (only the k steps the item multiplies: the others read the zero row anyway)
+        // (only the k steps the item multiplies: the others read the zero row anyway);
+        // 32-bit element offsets on a 64-bit base, so C may exceed 4 GB
         auto load = [&](const uint4 &e, T (&b)[KS]) {
             const uint32_t *ro = rowoff + (e.w & 255u) * KP + (lane >> 4);
-            const uint32_t soff = (e.w >> 8) * uint32_t(sizeof(T));
+            const T *src = cl + (e.w >> 8);
 #pragma unroll
             for (int t = 0; t < KS; ++t) {
-                if ((e.y >> t) & 1u) buffer_ld(b[t], cr, ro[4 * t] + colb, soff);
+                if ((e.y >> t) & 1u) b[t] = src[ro[4 * t]];
                 else b[t] = T(0);
             }
         };
@@ -249,6 +252,166 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     }
 }
 
+// ---- one-block spaces whose sigma row is split into units (FP32) --------------
+//
+// The eight-wave form of the one-block kernel (roles split by SIMD: waves 3 and
+// 7 scatter, the other six multiply, two W buffers, one barrier per item) over
+// the unit tables above: a workgroup owns the columns [lo, hi) of Ia's row, and
+// walks its unit's items (source tiles that reach the range) with their row-block
+// masks; a producing wave multiplies only its row blocks in the item's mask.
+// Gathered rows: Ia's single excitations in list order, then Ia itself (its
+// k slot carries sum_{j in Ia} (jj|kl)), then zero rows; 32-bit element offsets
+// on a 64-bit base, so C may exceed 4 GB.
+template <typename T, int KS, int RB, int EW>
+__global__ __launch_bounds__(512, 1) void k_sigma_ab_gw(AbgArgs<T> p) {
+    using M = Mfma<T>;
+    using acc_t = typename M::acc_t;
+    constexpr int RBW = (RB + 2) / 3;
+    constexpr int MP = 16 * RB;
+    constexpr int PW = (EW + 1) * 64;
+    constexpr int PT = 4 * PW;
+    constexpr int TS = sizeof(T) == 4 ? 2 : 3;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *W0 = reinterpret_cast<T *>(smem_raw);               // [2][MP][WS]
+    T *W1 = W0 + MP * kAbxWS;
+    T *sig = W1 + MP * kAbxWS;                             // [nvirt + 64]
+
+    int ui = 0;
+    while (ui + 1 < p.nunits && int(blockIdx.x) >= p.units[8 * (ui + 1) + 6]) ++ui;
+    const int *U = p.units + 8 * ui;
+    const int ulo = U[1], ncol = U[2] - U[1];
+    const int Ia = U[5] + (int(blockIdx.x) - U[6]);
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    T *srow = p.sp + int64_t(Ia) * p.ld0 + ulo;
+    for (int x = tid; x < ncol; x += 512) sig[x] = srow[x];
+    __syncthreads();                                       // the sigma row is in LDS
+    const int nact = U[4];
+    const uint4 *act = p.act + U[3];
+    if (nact > 0) {
+        if ((wave & 3) != 3) {
+            const int m = (wave >> 2) * 3 + (wave & 3);        // 0..5
+            const int cb = m & 1, rb0 = (m >> 1) * RBW;
+            const int nrb = RB - rb0 < RBW ? RB - rb0 : RBW;
+            T A[RBW][KS];
+            uint32_t boff[KS];                                 // element offsets of the gathered rows
+            const uint32_t xa = p.astr[Ia];
+#pragma unroll
+            for (int t = 0; t < KS; ++t) {
+                const int q = 4 * t + (lane >> 4);
+                uint32_t off = p.zero_off;
+                const T *g = nullptr;
+                T sg = 0;
+                bool self = false;
+                if (q < p.anexc) {
+                    const uint32_t w = p.aexc[int64_t(Ia) * p.anexc + q];
+                    if (w != kExcNone) {
+                        off = (w >> 11) * uint32_t(p.ld0);
+                        const int i = (w >> 6) & 31, j = (w >> 1) & 31;
+                        g = p.g + int64_t(i * p.n + j) * p.mp;
+                        sg = (w & 1) ? T(-1) : T(1);
+                    }
+                } else if (q == p.anexc) {
+                    off = uint32_t(Ia) * uint32_t(p.ld0);
+                    self = true;
+                }
+                boff[t] = off;
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) {
+                    const int mr = (rb0 + r) * 16 + (lane & 15);
+                    T val = 0;
+                    if (r < nrb && mr < p.mp) {
+                        if (g) {
+                            val = sg * g[mr];
+                        } else if (self) {
+                            for (uint32_t b = xa; b; b &= b - 1) {
+                                const int j = __ffs(b) - 1;
+                                val += p.g[int64_t(j * p.n + j) * p.mp + mr];
+                            }
+                        }
+                    }
+                    A[r][t] = val;
+                }
+            }
+            const T *cl = p.cp + (cb * 16 + (lane & 15));
+            T b[KS];
+            acc_t acc[RBW];
+            // W of item e on the matrix cores (its active row blocks only); as each
+            // k step is consumed its register is reloaded with the rows of item nx
+            auto products = [&](const uint4 &e, const uint4 &nx) {
+                const uint32_t rm = e.z >> rb0;
+                const T *src = cl + (nx.w >> 8);
+#pragma unroll
+                for (int r = 0; r < RBW; ++r) acc[r] = acc_t{0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+#pragma unroll
+                    for (int r = 0; r < RBW; ++r)
+                        if (r < nrb && ((rm >> r) & 1u)) acc[r] = M::op(A[r][t], b[t], acc[r]);
+                    b[t] = src[boff[t]];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            auto store_w = [&](T *W, uint32_t rmask) {
+                const uint32_t rm = rmask >> rb0;
+#pragma unroll
+                for (int r = 0; r < RBW; ++r)
+                    if (r < nrb && ((rm >> r) & 1u))
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
+            };
+            {
+                const T *src = cl + (act[0].w >> 8);
+#pragma unroll
+                for (int t = 0; t < KS; ++t) b[t] = src[boff[t]];
+            }
+            const uint4 e0 = act[0];
+            products(e0, act[nact > 1 ? 1 : 0]);
+            store_w(W0, e0.z);
+            __syncthreads();                                   // W of item 0 ready
+            for (int i = 0; i < nact; ++i) {
+                if (i + 1 < nact) {
+                    const uint4 e1 = act[i + 1];
+                    products(e1, act[i + 2 < nact ? i + 2 : nact - 1]);
+                    store_w((i + 1) & 1 ? W1 : W0, e1.z);
+                }
+                __syncthreads();
+            }
+        } else {
+            const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
+            const int sw = wave >> 2;                          // plan ranges sw and sw + 2
+            const uint32_t pl0 = uint32_t(sw * PW + lane) * 4u, pl1 = uint32_t((sw + 2) * PW + lane) * 4u;
+            const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
+            uint32_t pa0[EW], ha0, pa1[EW], ha1, pb0[EW], hb0, pb1[EW], hb1;
+            auto plan_of = [&](int i, uint32_t (&w0)[EW], uint32_t &h0, uint32_t (&w1)[EW], uint32_t &h1) {
+                const uint32_t x = act[i].x;
+                const int n = int(x >> 24);
+                abx_plan_load_n<EW>(pr, pl0, (x & 0xffffffu) * (PT * 4u), w0, h0, n);
+                abx_plan_load_n<EW>(pr, pl1, (x & 0xffffffu) * (PT * 4u), w1, h1, n);
+                return n;
+            };
+            int na = plan_of(0, pa0, ha0, pa1, ha1), nb = 0;
+            __syncthreads();                                   // W of item 0 ready
+            for (int i = 0; i < nact; i += 2) {
+                const T *Wc = W0;                              // item i (even) is in W0
+                if (i + 1 < nact) nb = plan_of(i + 1, pb0, hb0, pb1, hb1);
+                abx_scatter_n<T, EW, TS>(Wc, sig, pa0, ha0, spare, na);
+                abx_scatter_n<T, EW, TS>(Wc, sig, pa1, ha1, spare, na);
+                __syncthreads();
+                if (i + 1 < nact) {
+                    if (i + 2 < nact) na = plan_of(i + 2, pa0, ha0, pa1, ha1);
+                    abx_scatter_n<T, EW, TS>(W1, sig, pb0, hb0, spare, nb);
+                    abx_scatter_n<T, EW, TS>(W1, sig, pb1, hb1, spare, nb);
+                    __syncthreads();
+                }
+            }
+        }
+    }
+    __syncthreads();                                       // every scatter into the row done
+    for (int x = tid; x < ncol; x += 512) srow[x] = sig[x];
+}
+
 template <typename T>
 size_t abg_lds(int nvirt, int rb, int ks, int ntb) {
     return (size_t(16) * rb * kAbxWS + nvirt + 64) * sizeof(T) + size_t(4) * ks * ntb * sizeof(uint32_t);
@@ -265,11 +428,29 @@ hipError_t run_abg(const AbgArgs<T> &a, int na, hipStream_t s) {
     return hipGetLastError();
 }
 
-// compiled (KS, RB, EW) shapes of the GAS kernel: small test spaces, GAS(20,20)
-// 6/8/6 and CAS(18,18) (whose sigma row is too long for the one-block kernel)
+template <typename T, int KS, int RB, int EW>
+hipError_t run_abgw(const AbgArgs<T> &a, int na, hipStream_t s) {
+    const size_t lds = (size_t(2) * 16 * RB * kAbxWS + a.nvirt + 64) * sizeof(T);
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_gw<T, KS, RB, EW>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sigma_ab_gw<T, KS, RB, EW>), dim3(na), dim3(512), lds, s, a);
+    return hipGetLastError();
+}
+
+// compiled (KS, RB, EW) shapes of the eight-wave unit kernel (FP32, one-block
+// spaces): CAS(8,8) and CAS(10,10) split into units for the tests, CAS(18,18)
+#define CIS_ABGW_SHAPES(X) X(5, 4, 4) X(5, 4, 16) X(7, 5, 4) X(7, 5, 16) X(21, 11, 8) X(21, 11, 12) X(21, 11, 16)
+
+// compiled (KS, RB, EW) shapes of the GAS kernel: small test spaces (GAS, one-block
+// CAS(8,8) and CAS(10,10) split into units, CAS(8,8) with point-group symmetry),
+// GAS(20,20) 6/8/6, CAS(18,18) (whose sigma row is too long for the one-block
+// kernel) and CAS(16,16) with point-group symmetry
 #define CIS_ABG_SHAPES(X) \
-    X(3, 2, 4) X(3, 2, 16) X(4, 2, 4) X(4, 2, 16) X(4, 3, 4) X(4, 3, 16) X(26, 14, 16) \
-    X(21, 11, 8) X(21, 11, 12) X(21, 11, 16)
+    X(3, 2, 4) X(3, 2, 16) X(4, 2, 4) X(4, 2, 16) X(4, 3, 4) X(4, 3, 16) X(5, 3, 4) X(5, 3, 16) X(5, 4, 4) \
+    X(5, 4, 16) X(7, 5, 4) X(7, 5, 16) X(26, 14, 16) X(21, 11, 8) X(21, 11, 12) X(21, 11, 16) X(17, 9, 4) \
+    X(17, 9, 8) X(17, 9, 16)
 
 int gas_width_for(int ks, int rb, int need) {
     int best = 0;
@@ -289,9 +470,9 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     const auto &L = ctx->pl[0];
     int64_t ldmax = 0;
     for (int v : L.ld) ldmax = std::max<int64_t>(ldmax, v);
-    const uint64_t cpb = (uint64_t(L.size) + uint64_t(ldmax)) * sizeof(T);
+    const uint64_t cpe = uint64_t(L.size) + uint64_t(ldmax);   // elements of C with its zero row
     const uint64_t plb = uint64_t(G.plan[d].ntile) * 4 * (G.plan[d].ew + 1) * 64 * sizeof(uint32_t);
-    if (cpb >= (uint64_t(1) << 31) || plb >= (uint64_t(1) << 31)) return false;
+    if (cpe >= (uint64_t(1) << 32) || plb >= (uint64_t(1) << 31)) return false;
     bool shape = false;
 #define CIS_HAS(K, R, E) shape = shape || (G.ks == K && G.rb == R && G.plan[d].ew == E);
     CIS_ABG_SHAPES(CIS_HAS)
@@ -311,12 +492,10 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.slot = G.d_slot;
     a.coff = G.d_coff;
     a.plan = plan;
-    a.cp_bytes = uint32_t(cpb);
     a.plan_bytes = uint32_t(plb);
     a.zero_off = uint32_t(L.size);
     a.anexc = A.nexc;
     a.n = ctx->n;
-    a.npair = ctx->npair;
     a.mp = 16 * G.rb;
     a.ntb = ctx->sp[1].ntype;
     a.act = reinterpret_cast<const uint4 *>(G.d_act[d]);
@@ -324,6 +503,22 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.nunits = int(G.units[d].size());
     a.nvirt = G.maxcols[d];
     int *kshape = const_cast<cisigma_ctx *>(ctx)->last_shape[sizeof(T) == 4];
+    // one-block FP32: the eight-wave form when its two W buffers and the row fit
+    if constexpr (sizeof(T) == 4) {
+      if (ctx->cas && (size_t(2) * 16 * G.rb * kAbxWS + a.nvirt + 64) * sizeof(T) <= 160 * 1024) {
+        a.ld0 = L.ld[0];
+        bool ran = false;
+#define CIS_RUNW(K, R, E)                                               \
+    if (!ran && G.ks == K && G.rb == R && G.plan[d].ew == E) {          \
+        *err = run_abgw<T, K, R, E>(a, G.nblocks[d], s);                \
+        kshape[0] = K; kshape[1] = R; kshape[2] = E; kshape[3] = 4;     \
+        ran = true;                                                     \
+    }
+        CIS_ABGW_SHAPES(CIS_RUNW)
+#undef CIS_RUNW
+        if (ran) return true;
+      }
+    }
 #define CIS_RUN(K, R, E)                                                \
     if (G.ks == K && G.rb == R && G.plan[d].ew == E) {                  \
         *err = run_abg<T, K, R, E>(a, G.nblocks[d], s);                 \

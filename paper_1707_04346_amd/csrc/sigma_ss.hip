@@ -39,16 +39,24 @@ struct SsArgs {
     const int *ld;              // [nto]
     const int *tile_u, *tile_c0;
     int npv, nK, nps, nto, ntiles;
-    // store mode: rows K*npv+P of Ys (row stride ldy) over tiles [tile_begin, tile_end),
+    // chunk store mode: rows K*npv+P of Ys (row stride ldy) over tiles [tile_begin, tile_end),
     // column c stored at c - col_begin
     T *Ys;
     int64_t ldy;
     int tile_begin, tile_end, col_begin;
     int ysplit;                 // column split of the grid (0: heuristic)
+    // row store mode: the product row of pair entry (K, P) for column type u goes to
+    // Ys + yoff[K*npv+P] + ycol[type(K+P)][u] (the padded sigma row of K+P)
+    const int64_t *yoff;
+    const int *ycol;
+    const int *klist;           // K of each workgroup (nullptr: K = blockIdx.x)
 };
 
-template <typename T, int KS, int MBL, bool STORE>
+// MODE 0: accumulate into Y with atomics; 1: store column chunks of rows
+// K*npv+P; 2: store each product row into the row of its pair entry
+template <typename T, int KS, int MBL, int MODE>
 __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
+    constexpr bool STORE = MODE == 1;
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
     using vec_t = typename M::vec_t;
@@ -63,7 +71,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     int *pid = rowJ + NE;
     int *neg = pid + NE;
 
-    const int K = blockIdx.x;
+    const int K = p.klist ? p.klist[blockIdx.x] : int(blockIdx.x);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     __shared__ int any_valid;
     __shared__ unsigned long long colmask;   // column types some row of this K is allowed with
@@ -139,8 +147,14 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
                     int64_t o = -1;
                     if (J >= 0) {
                         int tj = p.stype[J];
-                        int64_t s = p.seg[int64_t(tj) * p.nto + u];
-                        if (s >= 0) o = s + int64_t(J - p.sstart[tj]) * p.ld[u];
+                        if (MODE == 2) {
+                            const int yc = p.ycol[int64_t(tj) * p.nto + u];
+                            const int64_t yo = p.yoff[int64_t(K) * p.npv + P];
+                            if (yc >= 0 && yo >= 0) o = yo + yc;
+                        } else {
+                            int64_t s = p.seg[int64_t(tj) * p.nto + u];
+                            if (s >= 0) o = s + int64_t(J - p.sstart[tj]) * p.ld[u];
+                        }
                     }
                     ooff[rb][i] = o;
                 }
@@ -172,6 +186,18 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
 #pragma unroll
                     for (int v = 0; v < VEC; ++v) o[v] = acc[rb][v][i];
                     *reinterpret_cast<vec_t *>(p.Ys + (int64_t(K) * p.npv + P) * p.ldy + (col - p.col_begin)) = o;
+                }
+        } else if (MODE == 2) {
+            // plain stores: each (pair entry, column) element has one producer
+#pragma unroll
+            for (int rb = 0; rb < MBL; ++rb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (ooff[rb][i] < 0) continue;
+                    vec_t o;
+#pragma unroll
+                    for (int v = 0; v < VEC; ++v) o[v] = acc[rb][v][i];
+                    __builtin_nontemporal_store(o, reinterpret_cast<vec_t *>(p.Ys + ooff[rb][i] + col));
                 }
         } else {
 #pragma unroll
@@ -333,6 +359,46 @@ __global__ __launch_bounds__(256) void k_pair_gather(const T *__restrict__ Ys, i
     }
 }
 
+// Spaces with several types: out row I (type t) = sum over the occupied pairs
+// of I of the stored rows of the pair entries producing I, block by block of
+// the column types allowed with t (each row holds the padded blocks of t,
+// concatenated in column-type order).  Writes every element of the row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_pair_gather_rows(const T *__restrict__ Ys, const int64_t *__restrict__ yoff,
+                                                          const int *__restrict__ ycol, const int *__restrict__ inv,
+                                                          int per, const int *__restrict__ stype,
+                                                          const int *__restrict__ sstart, const int64_t *__restrict__ seg,
+                                                          const int *__restrict__ ld, int nto, T *__restrict__ out) {
+    using vec_t = typename Mfma<T>::vec_t;
+    constexpr int VEC = 16 / sizeof(T);
+    __shared__ int64_t rows[64];
+    const int I = blockIdx.x;
+    const int t = stype[I], ri = I - sstart[t];
+    for (int q = threadIdx.x; q < per; q += blockDim.x) {
+        const int e = inv[int64_t(I) * per + q];
+        rows[q] = e >= 0 ? yoff[e] : -1;
+    }
+    __syncthreads();
+    for (int u = 0; u < nto; ++u) {
+        const int yc = ycol[int64_t(t) * nto + u];
+        if (yc < 0) continue;
+        T *dst = out + seg[int64_t(t) * nto + u] + int64_t(ri) * ld[u];
+        for (int c = int(threadIdx.x) * VEC; c < ld[u]; c += int(blockDim.x) * VEC) {
+            vec_t acc = vec_t{}, acc2 = vec_t{};
+            int q = 0;
+            for (; q + 2 <= per; q += 2) {
+                if (rows[q] >= 0)
+                    acc += __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + rows[q] + yc + c));
+                if (rows[q + 1] >= 0)
+                    acc2 += __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + rows[q + 1] + yc + c));
+            }
+            if (q < per && rows[q] >= 0)
+                acc += __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(Ys + rows[q] + yc + c));
+            *reinterpret_cast<vec_t *>(dst + c) = acc + acc2;
+        }
+    }
+}
+
 // one-electron same-spin part for strings with a single electron:
 // Y(I, :) += h_qq X(I, :) (q the occupied orbital) + sum_{J = a+_l a_q I... } s h_kl X(J, :)
 template <typename T>
@@ -402,12 +468,13 @@ __global__ __launch_bounds__(kTileCols) void k_sigma_ss_direct(SsArgs<T> p) {
     }
 }
 
-template <typename T, int KS, int MBL, bool STORE>
+template <typename T, int KS, int MBL, int MODE>
 hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
+    constexpr bool STORE = MODE == 1;
     constexpr int KP = 4 * KS, MP = 16 * MBL;
     constexpr int NE = KP > MP ? KP : MP;
     size_t lds = size_t(MP) * (KP + 1) * sizeof(T) + 3 * NE * sizeof(int);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ss<T, KS, MBL, STORE>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ss<T, KS, MBL, MODE>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
     constexpr int TW = 16 * (16 / sizeof(T));
@@ -415,7 +482,7 @@ hipError_t run_ss(const SsArgs<T> &a, hipStream_t s) {
     int ysplit = 1;
     while (int64_t(a.nK) * ysplit < 2048 && 4 * ysplit < items) ysplit *= 2;
     if (a.ysplit > 0) ysplit = a.ysplit;
-    hipLaunchKernelGGL((k_sigma_ss<T, KS, MBL, STORE>), dim3(a.nK, ysplit), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_sigma_ss<T, KS, MBL, MODE>), dim3(a.nK, ysplit), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
@@ -451,12 +518,25 @@ bool ss_shape_compiled(int npv) {
     return npv <= 0;
 }
 
-template <typename T, bool STORE>
+// (KS, MBL) of the compiled pair-kernel shapes, smallest first
+#define CIS_SS_SHAPES(X) \
+    X(1, 1) X(2, 1) X(3, 1) X(4, 1) X(4, 2) X(6, 2) X(7, 2) X(9, 3) X(12, 3) X(14, 4) X(17, 5) X(20, 5) X(23, 6) \
+    X(27, 7) X(30, 8) X(34, 9) X(39, 10) X(43, 11)
+
+template <typename T, int MODE>
+hipError_t dispatch_ss_shape(const SsArgs<T> &a, int ks, int mbl, hipStream_t s) {
+#define CIS_SSB(K, MB) if (ks == K && mbl == MB) return run_ss<T, K, MB, MODE>(a, s);
+    CIS_SS_SHAPES(CIS_SSB)
+#undef CIS_SSB
+    return hipErrorInvalidValue;
+}
+
+template <typename T, int MODE>
 hipError_t dispatch_ss(const SsArgs<T> &a, hipStream_t s) {
     const int ks = (a.npv + 3) / 4;
     const int mbl = (a.npv + 15) / 16;
     // (KS, MBL) pairs for npv = C(m, 2), m = empty orbitals + 2
-#define CIS_SS(K, MB) if (ks == K && mbl == MB) return run_ss<T, K, MB, STORE>(a, s);
+#define CIS_SS(K, MB) if (ks == K && mbl == MB) return run_ss<T, K, MB, MODE>(a, s);
     CIS_SS(1, 1) CIS_SS(2, 1) CIS_SS(3, 1) CIS_SS(4, 1) CIS_SS(4, 2) CIS_SS(6, 2) CIS_SS(7, 2) CIS_SS(9, 3)
     CIS_SS(12, 3) CIS_SS(14, 4) CIS_SS(17, 5) CIS_SS(20, 5) CIS_SS(23, 6) CIS_SS(27, 7) CIS_SS(30, 8)
     CIS_SS(34, 9) CIS_SS(39, 10) CIS_SS(43, 11)
@@ -500,15 +580,43 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
     a.nto = ctx->sp[other].ntype;
     a.ntiles = L.ntiles;
     a.ysplit = ctx->ss_split;
+    // spaces with several types: one launch per bucket of K (pairs in the space first)
+    auto buckets = [&](auto mode) -> hipError_t {
+        constexpr int MODE = decltype(mode)::value;
+        for (size_t b = 0; b + 1 < S.bk_start.size(); ++b) {
+            SsArgs<T> ab = a;
+            ab.klist = S.d_klist + S.bk_start[b];
+            ab.nK = S.bk_start[b + 1] - S.bk_start[b];
+            if (ab.nK == 0) continue;
+            hipError_t e = dispatch_ss_shape<T, MODE>(ab, S.bk_ks[b], S.bk_mbl[b], s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const bool bucketed = !ctx->cas && S.d_klist != nullptr;
     if (!Ys) {
-        if (ss_shape_compiled(S.npv)) return dispatch_ss<T, false>(a, s);
+        if (bucketed) return buckets(std::integral_constant<int, 0>{});
+        if (ss_shape_compiled(S.npv)) return dispatch_ss<T, 0>(a, s);
         int ysplit = 1;
         while (int64_t(S.nK) * ysplit < 2048 && ysplit < L.ntiles) ysplit *= 2;
         hipLaunchKernelGGL((k_sigma_ss_direct<T>), dim3(S.nK, ysplit), dim3(kTileCols), 0, s, a);
         return hipGetLastError();
     }
-    // materialised form, one column chunk at a time: store rows K*npv+P, then gather per string
     const int per = S.nel * (S.nel - 1) / 2;
+    if (!ctx->cas) {
+        // several types: every product row into the row of its pair entry, then the gather
+        if (S.ny == 0) return hipErrorInvalidValue;
+        a.Ys = static_cast<T *>(Ys);
+        a.yoff = S.d_yoff;
+        a.ycol = S.d_ycol;
+        hipError_t e = bucketed ? buckets(std::integral_constant<int, 2>{}) : dispatch_ss<T, 2>(a, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_pair_gather_rows<T>), dim3(S.nstr), dim3(256), 0, s, static_cast<const T *>(Ys),
+                           S.d_yoff, S.d_ycol, S.d_pair_inv, per, S.d_stype, ctx->d_tstart[spin], L.d_seg, L.d_ld,
+                           a.nto, static_cast<T *>(Y));
+        return hipGetLastError();
+    }
+    // materialised form, one column chunk at a time: store rows K*npv+P, then gather per string
     const int64_t ld = L.ld[0];
     const uint64_t x_bytes = (uint64_t(S.nstr) + 1) * uint64_t(ld) * sizeof(T);   // the zero row included
     for (int c0 = 0; c0 < ld; c0 += chunk) {
@@ -536,7 +644,7 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
             a.col_begin = c0;
             a.tile_begin = c0 / kTileCols;
             a.tile_end = c1 / kTileCols;
-            e = dispatch_ss<T, true>(a, s);
+            e = dispatch_ss<T, 1>(a, s);
         }
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_pair_gather<T>), dim3(S.nstr), dim3(256), 0, s, static_cast<const T *>(Ys),
@@ -556,5 +664,15 @@ hipError_t launch_sigma_same_spin(const cisigma_ctx *ctx, int spin, const void *
 }
 
 bool same_spin_materialisable(int npv) { return ss_shape_compiled(npv); }
+
+bool same_spin_shape_for(int count, int *ks, int *mbl) {
+    const int need_k = (count + 3) / 4, need_m = (count + 15) / 16;
+    int best = -1;
+#define CIS_PICK(K, MB) \
+    if (K >= need_k && MB >= need_m && (best < 0 || 16 * MB * 4 * K < best)) { best = 16 * MB * 4 * K; *ks = K; *mbl = MB; }
+    CIS_SS_SHAPES(CIS_PICK)
+#undef CIS_PICK
+    return best >= 0;
+}
 
 }  // namespace cis

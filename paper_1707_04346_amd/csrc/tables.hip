@@ -320,8 +320,9 @@ hipError_t build_string_tables(cisigma_ctx *ctx, int spin) {
                            T.nK, T.nel - 2, T.npv, g, tv);
         CIS_TRY(hipGetLastError());
     }
-    // inverse pair table (single-type spins only: the materialised same-spin path)
-    if (T.nel >= 2 && T.ntype == 1) {
+    // inverse pair table (the gather of the materialised same-spin path: at most
+    // 64 occupied pairs per string)
+    if (T.nel >= 2 && T.nel * (T.nel - 1) / 2 <= 64) {
         int per = T.nel * (T.nel - 1) / 2;
         int64_t tot = int64_t(T.nstr) * per;
         CIS_TRY(hipMalloc(&T.d_pair_inv, size_t(tot) * sizeof(int)));

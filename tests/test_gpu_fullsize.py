@@ -120,8 +120,10 @@ def test_gas20_sampled_rows(dtype):
     S = torch.empty_like(C)
     ctx.apply(C, S)
     torch.cuda.synchronize()
-    # the owner-computes GAS kernel in both precisions (FP64: long sigma rows split over several units)
-    assert ctx.last_path(_cis().FP32 if dtype == torch.float32 else _cis().FP64) == _cis().PATH_AB_OWNER
+    # the owner-computes GAS kernel in both precisions (FP64: long sigma rows split over
+    # several units), the same-spin parts as stored pair-product rows plus a gather
+    assert ctx.last_path(_cis().FP32 if dtype == torch.float32 else _cis().FP64) == \
+        _cis().PATH_AB_OWNER | _cis().PATH_SS_MATERIALISED
     got = S[torch.tensor(rows, device="cuda")].double().cpu().numpy()
     want = ref.sigma_rows(rows, c)
     err = rel(got, want)

@@ -308,15 +308,18 @@ def test_rank1_self_row_cas14_sampled(dtype):
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
 def test_gas_takes_the_owner_path(case, dtype):
     """GAS spaces run the owner-computes sigma_3 kernel with per-type source
-    tiles (same-spin parts on the general kernels), and stay exact."""
+    tiles and the same-spin parts as stored pair-product rows plus a gather (no
+    atomics anywhere), stay exact, and repeat bit for bit."""
     cis = _cis()
     norb, na, nb, gas = case
     ctx, ref = make(norb, na, nb, gas=gas, seed=16)
     c = si.ci_vector(ctx.ndet, 17)
     s = gpu_sigma(ctx, c, dtype)
-    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) == cis.PATH_AB_OWNER
+    assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) == \
+        cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
     tol = TOL64 if dtype == torch.float64 else TOL32
     assert rel(s, ref.sigma(c)) <= tol
+    assert np.array_equal(gpu_sigma(ctx, c, dtype), s)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
@@ -331,3 +334,48 @@ def test_gas_general_path_matches_oracle(dtype):
         assert ctx.last_path(cis.FP32 if dtype == torch.float32 else cis.FP64) == 0
         tol = TOL64 if dtype == torch.float64 else TOL32
         assert rel(s, ref.sigma(c)) <= tol
+
+
+# One-block spaces on the owner-computes units of the GAS form (path 2): sigma
+# rows cut at the occupation classes of the two highest orbitals, and inside a
+# class where the unit width asks for it; W rows grouped so that a source tile
+# of another class multiplies only the row blocks leading into the unit.  This
+# is the form CAS(18,18) runs at full size.  (norb, na, nb, gas), unit width,
+# expected (k steps, row blocks); GAS rows are cut at beta-type ends.
+UNITS = [((8, 4, 4, None), 0, (5, 4)), ((8, 4, 4, None), 64, (5, 4)), ((10, 5, 5, None), 64, (7, 5)),
+         ((10, 5, 5, None), 128, (7, 5)), ((7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])), 64, None)]
+
+
+@pytest.mark.parametrize("case,cols,shape", UNITS,
+                         ids=[f"{_ids(c)}_w{w}" for c, w, _ in UNITS])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_owner_units_match_oracle(case, cols, shape, dtype):
+    cis = _cis()
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, gas=gas, seed=23)
+    if gas is None:
+        ctx.set_option(cis.OPT_SIGMA_PATH, 2)
+    if cols:
+        ctx.set_option(cis.OPT_UNIT_COLS, cols)
+    c = si.ci_vector(ctx.ndet, 24)
+    s = gpu_sigma(ctx, c, dtype)
+    dt = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert ctx.last_path(dt) & cis.PATH_AB_OWNER
+    got = ctx.last_shape(dt)
+    # FP32 one-block rows: the eight-wave unit kernel; otherwise the four-wave GAS form
+    assert got[3] == (4 if gas is None and dtype == torch.float32 else 3), got
+    if shape is not None:
+        assert got[:2] == shape, got
+    tol = TOL64 if dtype == torch.float64 else TOL32
+    assert rel(s, ref.sigma(c)) <= tol
+    assert np.array_equal(gpu_sigma(ctx, c, dtype), s)   # one writer per target: bitwise repeatable
+
+
+def test_unit_cols_option_rejects_bad_values():
+    cis = _cis()
+    ctx, _ = make(6, 3, 3, seed=1)
+    for bad in (-1, 1, 63, 70000, 100.5):
+        with pytest.raises(Exception):
+            ctx.set_option(cis.OPT_UNIT_COLS, bad)
+    with pytest.raises(Exception):
+        ctx.set_option(cis.OPT_SIGMA_PATH, 3)

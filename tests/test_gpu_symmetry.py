@@ -175,3 +175,30 @@ def test_cas16_d2h_sampled_rows(dtype):
     want = ref.sigma_rows(rows, c)
     ctx.close()
     assert rel(got, want) <= TOL[dtype]
+
+
+OWNER_CASES = [CASES[0], CASES[1], CASES[2], CASES[5]]
+
+
+@pytest.mark.parametrize("case", OWNER_CASES, ids=[_ids(c) for c in OWNER_CASES])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_symmetric_spaces_take_the_owner_paths(case, dtype):
+    """Spaces with irreps run sigma_3 on the owner-computes units (every k step
+    multiplied, tiles and row blocks from the plans) and the same-spin parts as
+    stored pair-product rows: no atomics, bit-identical repeats."""
+    cis = _cis()
+    norb, na, nb, orbsym, target, gas = case
+    ctx, ref = make(norb, na, nb, orbsym, target, gas, seed=31)
+    c = si.ci_vector(ctx.ndet, 32)
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S1, S2 = torch.empty_like(C), torch.empty_like(C)
+    ctx.apply(C, S1)
+    ctx.apply(C, S2)
+    torch.cuda.synchronize()
+    prec = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert ctx.last_path(prec) == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
+    assert ctx.last_shape(prec)[3] == 3
+    got = S1.double().cpu().numpy()
+    assert rel(got, ref.sigma(c)) <= TOL[dtype]
+    assert torch.equal(S1, S2)
+
