@@ -504,7 +504,11 @@ void plan_emit(const PlanSpec &ps, const PlanTiles &pt, int ew, std::vector<uint
                     uint32_t hdr = spare | 1u;
                     for (int q = 0; q < ew; ++q) {
                         const size_t e = i + size_t(lane) * w + q;
-                        uint32_t word = (spare / unit) << 16;                    // padding: W element 0, discard slot
+                        // padding: the discard slot, and W element (0, 32) -- the tile's pad
+                        // column, which kernels that run padding entries keep at zero (a
+                        // padding entry may follow the part of a group that continues in
+                        // the next lane, when the tile's width is below ew)
+                        uint32_t word = ((spare / unit) << 16) | (32u * es);   // column 32 of the 33-wide W rows
                         if (q < w && e < j) {
                             const PlanItem &it = tile[e];
                             const uint32_t slot = it.end ? it.tgt * es : spare;

@@ -16,6 +16,18 @@
 namespace cis {
 namespace {
 
+// Unit and item tables are the same for every lane: reading them through
+// readfirstlane keeps the values in scalar registers, so plan loads take them as
+// scalar offsets and the row-block and k-step masks become scalar branches
+// (read as per-lane values they turned every plan load into a loop over lanes
+// and every masked MFMA into a masked one)
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return uint32_t(__builtin_amdgcn_readfirstlane(int(v))); }
+__device__ __forceinline__ uint4 uni_ld(const uint4 *p) {
+    const uint4 v = *p;
+    return make_uint4(uni(v.x), uni(v.y), uni(v.z), uni(v.w));
+}
+
 // ---- GAS spaces: owner-computes with per-type source tiles ---------------------
 //
 // Units: an alpha type ta and a range [lo, hi) of its compact columns (the
@@ -66,10 +78,10 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     uint32_t *rowoff = reinterpret_cast<uint32_t *>(sig + p.nvirt + 64);   // [ntb][KP] element offsets
 
     int ui = 0;                                            // this workgroup's unit (uniform)
-    while (ui + 1 < p.nunits && int(blockIdx.x) >= p.units[8 * (ui + 1) + 6]) ++ui;
-    const int *U = p.units + 8 * ui;
-    const int ulo = U[1], uhi = U[2], ncol = uhi - ulo;
-    const int Ia = U[5] + (int(blockIdx.x) - U[6]);
+    while (ui + 1 < p.nunits && int(blockIdx.x) >= uni(p.units[8 * (ui + 1) + 6])) ++ui;
+    const int *U = p.units + 8 * uni(ui);
+    const int ulo = uni(U[1]), uhi = uni(U[2]), ncol = uhi - ulo;
+    const int Ia = uni(U[5]) + (int(blockIdx.x) - uni(U[6]));
     const int ta = p.atype[Ia], ra = Ia - p.astart[ta];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cb = wave & 1, grp = wave >> 1;
@@ -139,13 +151,13 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     }
     __syncthreads();
 
-    const int nact = U[4];
+    const int nact = uni(U[4]);
     if (nact > 0) {
         const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
         const T *cl = p.cp + (cb * 16 + (lane & 15));   // this lane's column of the item's first column
         const uint32_t pl = uint32_t(wave * PW + lane) * 4u;
         const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
-        const uint4 *act = p.act + U[3];
+        const uint4 *act = p.act + uni(U[3]);
         T bc[KS], bn[KS];
         acc_t acc[RBW], acc2[RBW];
         // gathered rows of an item for every k step: one LDS offset read each
@@ -208,9 +220,9 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
                         W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
         };
         // items i + 1 and i + 2 are read one iteration ahead of their use
-        uint4 e1 = act[nact > 1 ? 1 : 0], e2 = act[nact > 2 ? 2 : nact - 1];
+        uint4 e1 = uni_ld(act + (nact > 1 ? 1 : 0)), e2 = uni_ld(act + (nact > 2 ? 2 : nact - 1));
         {
-            const uint4 e0 = act[0];
+            const uint4 e0 = uni_ld(act);
             load(e0, bc);
             load(e1, bn);
             products(e0.y, e0.z);
@@ -218,12 +230,13 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         }
         // act .x: plan tile | its entries per lane << 24
         uint32_t pw_[EW], ph, nw_[EW], nh;
-        int pn = int(act[0].x >> 24), nn = 0;
-        abx_plan_load_n<EW>(pr, pl, (act[0].x & 0xffffffu) * (PT * 4u), pw_, ph, pn);
+        const uint32_t x0 = uni(act[0].x);
+        int pn = int(x0 >> 24), nn = 0;
+        abx_plan_load_n<EW>(pr, pl, (x0 & 0xffffffu) * (PT * 4u), pw_, ph, pn);
         __syncthreads();
         for (int i = 0; i < nact; ++i) {
             const bool more = i + 1 < nact;
-            const uint4 e3 = act[i + 3 < nact ? i + 3 : nact - 1];
+            const uint4 e3 = uni_ld(act + (i + 3 < nact ? i + 3 : nact - 1));
 #pragma unroll
             for (int t = 0; t < KS; ++t) bc[t] = bn[t];          // rows of item i + 1
             load(e2, bn);                                        // item i + 2, in flight for a whole item
@@ -277,17 +290,18 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_gw(AbgArgs<T> p) {
     T *sig = W1 + MP * kAbxWS;                             // [nvirt + 64]
 
     int ui = 0;
-    while (ui + 1 < p.nunits && int(blockIdx.x) >= p.units[8 * (ui + 1) + 6]) ++ui;
-    const int *U = p.units + 8 * ui;
-    const int ulo = U[1], ncol = U[2] - U[1];
-    const int Ia = U[5] + (int(blockIdx.x) - U[6]);
+    while (ui + 1 < p.nunits && int(blockIdx.x) >= uni(p.units[8 * (ui + 1) + 6])) ++ui;
+    const int *U = p.units + 8 * uni(ui);
+    const int ulo = uni(U[1]), ncol = uni(U[2]) - ulo;
+    const int Ia = uni(U[5]) + (int(blockIdx.x) - uni(U[6]));
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     T *srow = p.sp + int64_t(Ia) * p.ld0 + ulo;
     for (int x = tid; x < ncol; x += 512) sig[x] = srow[x];
+    for (int r = tid; r < 2 * MP; r += 512) W0[r * kAbxWS + kAbxNT] = T(0);   // pad column: plan padding reads it
     __syncthreads();                                       // the sigma row is in LDS
-    const int nact = U[4];
-    const uint4 *act = p.act + U[3];
+    const int nact = uni(U[4]);
+    const uint4 *act = p.act + uni(U[3]);
     if (nact > 0) {
         if ((wave & 3) != 3) {
             const int m = (wave >> 2) * 3 + (wave & 3);        // 0..5
@@ -362,18 +376,18 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_gw(AbgArgs<T> p) {
                             W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
             };
             {
-                const T *src = cl + (act[0].w >> 8);
+                const T *src = cl + (uni(act[0].w) >> 8);
 #pragma unroll
                 for (int t = 0; t < KS; ++t) b[t] = src[boff[t]];
             }
-            const uint4 e0 = act[0];
-            products(e0, act[nact > 1 ? 1 : 0]);
+            const uint4 e0 = uni_ld(act);
+            products(e0, uni_ld(act + (nact > 1 ? 1 : 0)));
             store_w(W0, e0.z);
             __syncthreads();                                   // W of item 0 ready
             for (int i = 0; i < nact; ++i) {
                 if (i + 1 < nact) {
-                    const uint4 e1 = act[i + 1];
-                    products(e1, act[i + 2 < nact ? i + 2 : nact - 1]);
+                    const uint4 e1 = uni_ld(act + i + 1);
+                    products(e1, uni_ld(act + (i + 2 < nact ? i + 2 : nact - 1)));
                     store_w((i + 1) & 1 ? W1 : W0, e1.z);
                 }
                 __syncthreads();
@@ -384,25 +398,38 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_gw(AbgArgs<T> p) {
             const uint32_t pl0 = uint32_t(sw * PW + lane) * 4u, pl1 = uint32_t((sw + 2) * PW + lane) * 4u;
             const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
             uint32_t pa0[EW], ha0, pa1[EW], ha1, pb0[EW], hb0, pb1[EW], hb1;
+            // every plan word is loaded (the words past a tile's width are padding
+            // entries); the scatter of a tile of at most 4 entries per lane takes the
+            // 4-entry form.  Loads and scatters whose length varies per tile became
+            // branches that waited for each load (measured at CAS(18,18) FP32: 1.68 s
+            // that way, 1.32 s with every tile at full width)
             auto plan_of = [&](int i, uint32_t (&w0)[EW], uint32_t &h0, uint32_t (&w1)[EW], uint32_t &h1) {
-                const uint32_t x = act[i].x;
-                const int n = int(x >> 24);
-                abx_plan_load_n<EW>(pr, pl0, (x & 0xffffffu) * (PT * 4u), w0, h0, n);
-                abx_plan_load_n<EW>(pr, pl1, (x & 0xffffffu) * (PT * 4u), w1, h1, n);
-                return n;
+                const uint32_t x = uni(act[i].x);
+                abx_plan_load<EW>(pr, pl0, (x & 0xffffffu) * (PT * 4u), w0, h0);
+                abx_plan_load<EW>(pr, pl1, (x & 0xffffffu) * (PT * 4u), w1, h1);
+                return int(x >> 24);
+            };
+            auto scatter = [&](const T *Wt, const uint32_t (&w)[EW], uint32_t h, int n) {
+                if constexpr (EW > 4) {
+                    if (n <= 4) {
+                        const uint32_t w4[4] = {w[0], w[1], w[2], w[3]};
+                        abx_scatter<T, 4, TS>(Wt, sig, w4, h, spare);
+                        return;
+                    }
+                }
+                abx_scatter<T, EW, TS>(Wt, sig, w, h, spare);
             };
             int na = plan_of(0, pa0, ha0, pa1, ha1), nb = 0;
             __syncthreads();                                   // W of item 0 ready
             for (int i = 0; i < nact; i += 2) {
-                const T *Wc = W0;                              // item i (even) is in W0
                 if (i + 1 < nact) nb = plan_of(i + 1, pb0, hb0, pb1, hb1);
-                abx_scatter_n<T, EW, TS>(Wc, sig, pa0, ha0, spare, na);
-                abx_scatter_n<T, EW, TS>(Wc, sig, pa1, ha1, spare, na);
+                scatter(W0, pa0, ha0, na);                     // item i (even) is in W0
+                scatter(W0, pa1, ha1, na);
                 __syncthreads();
                 if (i + 1 < nact) {
                     if (i + 2 < nact) na = plan_of(i + 2, pa0, ha0, pa1, ha1);
-                    abx_scatter_n<T, EW, TS>(W1, sig, pb0, hb0, spare, nb);
-                    abx_scatter_n<T, EW, TS>(W1, sig, pb1, hb1, spare, nb);
+                    scatter(W1, pb0, hb0, nb);
+                    scatter(W1, pb1, hb1, nb);
                     __syncthreads();
                 }
             }

@@ -196,6 +196,7 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_x(AbxArgs<T> p) {
     const int64_t rowoff = int64_t(Ia) * p.ld;
     for (int c = tid * VEC; c < p.ld; c += 512 * VEC)
         *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
+    for (int r = tid; r < MP; r += 512) W[r * kAbxWS + kAbxNT] = T(0);   // pad column: plan padding reads it
     const int ntile = p.ld / kAbxNT;
     if ((wave & 3) != 3) {
         const int m = (wave >> 2) * 3 + (wave & 3);        // 0..5
@@ -290,6 +291,7 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
     const int64_t rowoff = int64_t(Ia) * p.ld;
     for (int c = tid * VEC; c < p.ld; c += 512 * VEC)
         *reinterpret_cast<vec_t *>(sig + c) = *reinterpret_cast<const vec_t *>(p.sp + rowoff + c);
+    for (int r = tid; r < 2 * MP; r += 512) W0[r * kAbxWS + kAbxNT] = T(0);   // pad column: plan padding reads it
     const int ntile = p.ld / kAbxNT;
     __syncthreads();                           // the sigma row is in LDS
     if ((wave & 3) != 3) {
