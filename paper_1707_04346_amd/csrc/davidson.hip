@@ -150,6 +150,81 @@ __global__ __launch_bounds__(256) void k_subtract_multi(const T *X, int64_t sx, 
     }
 }
 
+// T_j -= sum_i c[j * nx + i] X_i for j < NY (one pass over X, as k_subtract_multi), with
+// per-block partial sums of |T_j|^2 before the update and of T_j . T_k (k <= j)
+// of the stored (rounded) results: partial[b][v], v < NY + NY(NY+1)/2
+template <typename T, int NY>
+__global__ __launch_bounds__(256) void k_subtract_gram(const T *X, int64_t sx, int nx, const double *c, T *Tv,
+                                                       int64_t st, int64_t N, double *partial) {
+    constexpr int NV = NY + NY * (NY + 1) / 2;
+    __shared__ double cs[NY * 512];
+    __shared__ double sh[4][NV];
+    for (int i = threadIdx.x; i < NY * nx; i += blockDim.x) cs[i] = c[i];
+    __syncthreads();
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) acc[v] = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double v[NY];
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+            v[j] = double(Tv[j * st + n]);
+            acc[j] += v[j] * v[j];
+        }
+#pragma unroll 8
+        for (int i = 0; i < nx; ++i) {
+            const double xv = double(X[i * sx + n]);
+#pragma unroll
+            for (int j = 0; j < NY; ++j) v[j] -= cs[j * nx + i] * xv;
+        }
+        double u[NY];
+#pragma unroll
+        for (int j = 0; j < NY; ++j) {
+            const T r = T(v[j]);
+            Tv[j * st + n] = r;
+            u[j] = double(r);
+        }
+        int q = NY;
+#pragma unroll
+        for (int j = 0; j < NY; ++j)
+#pragma unroll
+            for (int k = 0; k <= j; ++k) acc[q++] += u[j] * u[k];
+    }
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double x = acc[v];
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (l == 0) sh[w][v] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV)
+        partial[int64_t(blockIdx.x) * NV + threadIdx.x] =
+            sh[0][threadIdx.x] + sh[1][threadIdx.x] + sh[2][threadIdx.x] + sh[3][threadIdx.x];
+}
+
+// D_j = sum_{k < NY} w[j * NY + k] T_k for j < nd (FP64 combination, one rounding)
+template <typename T, int NY>
+__global__ __launch_bounds__(256) void k_combine_new(const T *Tv, int64_t st, const double *w, int nd, T *D,
+                                                     int64_t sd, int64_t N) {
+    __shared__ double ws[NY * NY];
+    for (int i = threadIdx.x; i < nd * NY; i += blockDim.x) ws[i] = w[i];
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        double t[NY];
+#pragma unroll
+        for (int k = 0; k < NY; ++k) t[k] = double(Tv[k * st + n]);
+        for (int j = 0; j < nd; ++j) {
+            double a = 0;
+#pragma unroll
+            for (int k = 0; k < NY; ++k) a += ws[j * NY + k] * t[k];
+            D[j * sd + n] = T(a);
+        }
+    }
+}
+
 // out[i] = sum over the nb blocks of partial[b][i]: one wave per output
 __global__ __launch_bounds__(64) void k_reduce_partials(const double *partial, int nb, int nx, double *out) {
     const int i = blockIdx.x;
@@ -166,7 +241,8 @@ __global__ __launch_bounds__(64) void k_reduce_partials(const double *partial, i
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int64_t sv, int m, int nr,
                                                     const double *y, const double *theta, const double *hd,
-                                                    double *xout, T *sout, T *tout, int64_t N, double *partial) {
+                                                    double *xout, T *sout, T *tout, int64_t N, double *partial,
+                                                    int want_x) {
     __shared__ double sh[8];
     __shared__ double ys[R][512];
     __shared__ double th[R];
@@ -212,8 +288,10 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
                 if (r >= nr) break;
                 const double res = s[r][u] - th[r] * x[r][u];
                 rr[r] += res * res;
-                xout[r * N + n] = x[r][u];
-                sout[r * N + n] = T(s[r][u]);
+                if (want_x) {                  // the Ritz vectors and their sigma: only when asked
+                    xout[r * N + n] = x[r][u];
+                    sout[r * N + n] = T(s[r][u]);
+                }
                 double dd = th[r] - h;
                 if (fabs(dd) < 1e-8) dd = dd < 0 ? -1e-8 : 1e-8;
                 tout[r * N + n] = T(res / dd);
@@ -445,6 +523,55 @@ hipError_t subtract_multi(Dev &d, const T *X, int64_t sx, int nx, const double *
     return hipGetLastError();
 }
 
+// T_j -= sum_i c[j * nx + i] X_i for j < ny <= kMultiY; returns on the host the
+// squared norms before the update (pre[j]) and the Gram matrix of the results
+// (gram[j * ny + k], both triangles)
+template <typename T>
+hipError_t subtract_gram(Dev &d, const T *X, int64_t sx, int nx, const double *host_c, int ny, T *Tv, int64_t st,
+                         int64_t N, double *pre, double *gram) {
+    const int g = d.grid(N);
+    const int nv = ny + ny * (ny + 1) / 2;
+    hipError_t e = hipSuccess;
+    if (nx > 0) e = hipMemcpyAsync(d.dvec, host_c, size_t(nx) * ny * sizeof(double), hipMemcpyHostToDevice, d.s);
+    if (e != hipSuccess) return e;
+    switch (ny) {
+        case 1: hipLaunchKernelGGL((k_subtract_gram<T, 1>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
+        case 2: hipLaunchKernelGGL((k_subtract_gram<T, 2>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
+        case 3: hipLaunchKernelGGL((k_subtract_gram<T, 3>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
+        case 4: hipLaunchKernelGGL((k_subtract_gram<T, 4>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
+        default: return hipErrorInvalidValue;
+    }
+    hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(64), 0, d.s, d.partial, g, nv, d.dvec);
+    std::vector<double> out(nv);
+    e = hipMemcpyAsync(out.data(), d.dvec, size_t(nv) * sizeof(double), hipMemcpyDeviceToHost, d.s);
+    if (e == hipSuccess) e = hipStreamSynchronize(d.s);
+    if (e != hipSuccess) return e;
+    int q = ny;
+    for (int j = 0; j < ny; ++j) {
+        pre[j] = out[j];
+        for (int k = 0; k <= j; ++k, ++q) gram[size_t(j) * ny + k] = gram[size_t(k) * ny + j] = out[q];
+    }
+    return hipSuccess;
+}
+
+// D_j = sum_k w[j * ny + k] T_k for j < nd, ny <= kMultiY (host coefficients)
+template <typename T>
+hipError_t combine_new(Dev &d, const T *Tv, int64_t st, int ny, const double *host_w, int nd, T *D, int64_t sd,
+                       int64_t N) {
+    if (nd == 0) return hipSuccess;
+    const int g = d.grid(N);
+    hipError_t e = hipMemcpyAsync(d.dvec, host_w, size_t(nd) * ny * sizeof(double), hipMemcpyHostToDevice, d.s);
+    if (e != hipSuccess) return e;
+    switch (ny) {
+        case 1: hipLaunchKernelGGL((k_combine_new<T, 1>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
+        case 2: hipLaunchKernelGGL((k_combine_new<T, 2>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
+        case 3: hipLaunchKernelGGL((k_combine_new<T, 3>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
+        case 4: hipLaunchKernelGGL((k_combine_new<T, 4>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T>
 int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, cisigma_stats *stats) {
     auto t0 = std::chrono::steady_clock::now();
@@ -664,9 +791,13 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         if (dtype == CISIGMA_FP32) ++nsig32; else ++nsig64;
         return r;
     };
-    // Ritz vectors (FP64), their sigma and corrections for all roots from the
-    // eigenvectors Yv (m x m, column r = root r); optionally the residual norms
-    auto ritz_all = [&](int mm, const std::vector<double> &Yv, bool norms) -> hipError_t {
+    // Ritz vectors (FP64) and their sigma (when want_x: they are read only by the
+    // FP64 refinement, a plain collapse and the output), and the corrections, for
+    // all roots from the eigenvectors Yv (m x m, column r = root r); optionally the
+    // residual norms.  x_fresh: X64 and SX hold the Ritz vectors of the basis as it is.
+    bool x_fresh = false;
+    auto ritz_all = [&](int mm, const std::vector<double> &Yv, bool norms, bool want_x) -> hipError_t {
+        x_fresh = want_x;
         for (int r0 = 0; r0 < nroots; r0 += kRitzRoots) {
             const int nr = std::min(kRitzRoots, nroots - r0);
             std::vector<double> yy(size_t(nr) * mm + nr);
@@ -677,7 +808,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL((k_ritz_multi<T, kRitzRoots>), dim3(g), dim3(256), 0, d.s, B, S, N, mm, nr, d.ybuf,
                                d.ybuf + size_t(nr) * mm, hd, X64 + int64_t(r0) * N, SX + int64_t(r0) * N,
-                               TB + int64_t(r0) * N, N, d.partial);
+                               TB + int64_t(r0) * N, N, d.partial, want_x ? 1 : 0);
             if (norms) {
                 std::vector<double> part(size_t(nr) * g);
                 e = hipMemcpyAsync(part.data(), d.partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, d.s);
@@ -717,8 +848,8 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         ++iter;
         ++since_ref;
         for (int r = 0; r < nroots; ++r) theta[r] = w[r];
-        // Ritz vectors and residual norms
-        DV_TRY(ritz_all(m, Y, true));
+        // residual norms and corrections (the Ritz vectors themselves when needed below)
+        DV_TRY(ritz_all(m, Y, true, false));
         bool all_ok = true;
         for (int r = 0; r < nroots; ++r)
             if (!(std::fabs(theta[r] - theta_old[r]) <= tol && rnorm[r] <= rtol)) all_ok = false;
@@ -732,6 +863,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         bool refined_now = false;
         if (mixed && (all_ok || (ctx->refine_every > 0 && since_ref >= ctx->refine_every) || iter >= ctx->max_iter)) {
             // FP64 refinement: rebuild sigma of the Ritz vectors in FP64
+            if (!x_fresh) DV_TRY(ritz_all(m, Y, false, true));
             refined_now = true;
             ++nref;
             since_ref = 0;
@@ -801,12 +933,15 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
                 for (int j = 0; j < m; ++j) Gm2[size_t(i) * m + j] = G[size_t(i) * max_space + j];
             sym_eig(Gm2, m, w, Y);
             for (int r = 0; r < nroots; ++r) theta[r] = w[r];
-            DV_TRY(ritz_all(m, Y, false));
+            DV_TRY(ritz_all(m, Y, false, true));
         } else if (!mixed) {
             if (all_ok) { converged = true; break; }
         }
         if (iter >= ctx->max_iter) break;
         bool collapsed = refined_now;
+        // a collapse changes the basis: the Ritz vectors of this iteration are kept
+        // first (the plain collapse reads them, and a later exit returns them)
+        if (!refined_now && m + nroots > max_space && !x_fresh) DV_TRY(ritz_all(m, Y, false, true));
         if (!refined_now && m + nroots > max_space && thick && prev_ok && mprev <= m) {
             // thick restart: the current Ritz vectors plus the orthonormalised
             // remainder of the previous ones, B <- B Q and S <- S Q in place,
@@ -887,8 +1022,9 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             prev_ok = true;
         }
         DV_TRY(pspace_correct(theta));
-        // (3) corrections, orthogonalised against the basis (CGS2, all corrections
-        // in one pass over the basis) and then against each other
+        // (3) corrections, orthogonalised against the basis (classical Gram-Schmidt,
+        // all corrections in one pass over the basis, repeated when cancellation asks
+        // for it) and then against each other
         nnew = 0;
         bool any_open = false;
         for (int r = 0; r < nroots; ++r) any_open = any_open || refined_now || rnorm[r] > rtol;
@@ -899,32 +1035,86 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             cand.push_back(r);
         }
         const int nc = int(cand.size());
-        for (int j = 0; j < nc; ++j) {
-            T *t = B + int64_t(m + j) * N;
-            DV_TRY(hipMemcpyAsync(t, TB + int64_t(cand[j]) * N, N * es, hipMemcpyDeviceToDevice, d.s));
-            if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
-        }
-        if (nc > 0 && m > 0) {
-            std::vector<double> cc(size_t(m) * nc);
-            for (int pass = 0; pass < 2; ++pass) {
-                DV_TRY(dots_multi(d, B, N, m, B + int64_t(m) * N, N, nc, N, cc.data()));
-                DV_TRY(subtract_multi(d, B, N, m, cc.data(), nc, B + int64_t(m) * N, N, N));
+        if (nc > 0 && nc <= kMultiY) {
+            // the corrections in TB slots 0..nc-1 (cand is increasing: cand[j] >= j)
+            for (int j = 0; j < nc; ++j) {
+                T *t = TB + int64_t(j) * N;
+                if (cand[j] != j)
+                    DV_TRY(hipMemcpyAsync(t, TB + int64_t(cand[j]) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+                if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
             }
-        }
-        for (int j = 0; j < nc; ++j) {
-            T *t = B + int64_t(m + j) * N;
-            for (int pass = 0; pass < 2 && nnew > 0; ++pass) {
-                DV_TRY(dots(d, B + int64_t(m) * N, N, nnew, t, N, col.data()));
-                DV_TRY(hipMemcpyAsync(d.dvec, col.data(), nnew * sizeof(double), hipMemcpyHostToDevice, d.s));
-                hipLaunchKernelGGL((k_subtract<T>), dim3(g), dim3(256), 0, d.s, B + int64_t(m) * N, N, nnew, d.dvec, t, N);
+            // orthogonalised against the basis: one classical Gram-Schmidt pass, a
+            // second one only when a correction lost more than half of its squared
+            // norm to the first (the DGKS criterion); the same pass returns the Gram
+            // matrix of the results
+            std::vector<double> cc(size_t(std::max(m, 1)) * nc), pre(nc), pre2(nc), gram(size_t(nc) * nc);
+            if (m > 0) DV_TRY(dots_multi(d, B, N, m, TB, N, nc, N, cc.data()));
+            DV_TRY(subtract_gram(d, B, N, m, cc.data(), nc, TB, N, N, pre.data(), gram.data()));
+            bool again = false;
+            for (int j = 0; j < nc; ++j) again = again || gram[size_t(j) * nc + j] < 0.5 * pre[j];
+            if (again && m > 0) {
+                DV_TRY(dots_multi(d, B, N, m, TB, N, nc, N, cc.data()));
+                DV_TRY(subtract_gram(d, B, N, m, cc.data(), nc, TB, N, N, pre2.data(), gram.data()));
             }
-            double tt;
-            DV_TRY(dots(d, t, N, 1, t, N, &tt));
-            const double nt = std::sqrt(tt);
-            if (!(nt > 1e-12)) continue;
-            T *dst = B + int64_t(m + nnew) * N;
-            hipLaunchKernelGGL((k_scale_copy<T, T>), dim3(g), dim3(256), 0, d.s, t, dst, 1.0 / nt, N);
-            ++nnew;
+            // orthonormalised among themselves: Cholesky factor R of the Gram matrix
+            // (G = R^T R), dropping a correction whose remaining norm is <= 1e-12;
+            // the new basis vectors are T R^-1 over the kept ones, in one pass
+            std::vector<double> R(size_t(nc) * nc, 0.0);
+            std::vector<int> kept;
+            for (int j = 0; j < nc; ++j) {
+                for (size_t a = 0; a < kept.size(); ++a) {
+                    const int k = kept[a];
+                    double v = gram[size_t(k) * nc + j];
+                    for (size_t b = 0; b < a; ++b) v -= R[size_t(kept[b]) * nc + k] * R[size_t(kept[b]) * nc + j];
+                    R[size_t(k) * nc + j] = v / R[size_t(k) * nc + k];
+                }
+                double v = gram[size_t(j) * nc + j];
+                for (int k : kept) v -= R[size_t(k) * nc + j] * R[size_t(k) * nc + j];
+                if (!(v > 1e-24)) continue;
+                R[size_t(j) * nc + j] = std::sqrt(v);
+                kept.push_back(j);
+            }
+            const int nk = int(kept.size());
+            std::vector<double> wts(size_t(std::max(nk, 1)) * nc, 0.0);   // new vector a = sum_k T_k wts[a][k]
+            for (int a = 0; a < nk; ++a) {
+                std::vector<double> x(nk, 0.0);
+                for (int b = a; b >= 0; --b) {
+                    double v = b == a ? 1.0 : 0.0;
+                    for (int c2 = b + 1; c2 <= a; ++c2) v -= R[size_t(kept[b]) * nc + kept[c2]] * x[c2];
+                    x[b] = v / R[size_t(kept[b]) * nc + kept[b]];
+                }
+                for (int b = 0; b <= a; ++b) wts[size_t(a) * nc + kept[b]] = x[b];
+            }
+            DV_TRY(combine_new(d, TB, N, nc, wts.data(), nk, B + int64_t(m) * N, N, N));
+            nnew = nk;
+        } else {
+            for (int j = 0; j < nc; ++j) {
+                T *t = B + int64_t(m + j) * N;
+                DV_TRY(hipMemcpyAsync(t, TB + int64_t(cand[j]) * N, N * es, hipMemcpyDeviceToDevice, d.s));
+                if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
+            }
+            if (nc > 0 && m > 0) {
+                std::vector<double> cc(size_t(m) * nc);
+                for (int pass = 0; pass < 2; ++pass) {
+                    DV_TRY(dots_multi(d, B, N, m, B + int64_t(m) * N, N, nc, N, cc.data()));
+                    DV_TRY(subtract_multi(d, B, N, m, cc.data(), nc, B + int64_t(m) * N, N, N));
+                }
+            }
+            for (int j = 0; j < nc; ++j) {
+                T *t = B + int64_t(m + j) * N;
+                for (int pass = 0; pass < 2 && nnew > 0; ++pass) {
+                    DV_TRY(dots(d, B + int64_t(m) * N, N, nnew, t, N, col.data()));
+                    DV_TRY(hipMemcpyAsync(d.dvec, col.data(), nnew * sizeof(double), hipMemcpyHostToDevice, d.s));
+                    hipLaunchKernelGGL((k_subtract<T>), dim3(g), dim3(256), 0, d.s, B + int64_t(m) * N, N, nnew, d.dvec, t, N);
+                }
+                double tt;
+                DV_TRY(dots(d, t, N, 1, t, N, &tt));
+                const double nt = std::sqrt(tt);
+                if (!(nt > 1e-12)) continue;
+                T *dst = B + int64_t(m + nnew) * N;
+                hipLaunchKernelGGL((k_scale_copy<T, T>), dim3(g), dim3(256), 0, d.s, t, dst, 1.0 / nt, N);
+                ++nnew;
+            }
         }
         if (nnew == 0) {
             // every correction vanished: the residuals lie in the basis (a basis
@@ -938,6 +1128,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             stalled = false;
         }
     }
+    if (vecs && !x_fresh) DV_TRY(ritz_all(m, Y, false, true));   // no collapse since the last eigensolve
     DV_TRY(hipStreamSynchronize(d.s));
     for (int r = 0; r < nroots; ++r) energies[r] = (mixed && have_rq) ? erq[r] : theta[r];
     double rfinal = 0;
