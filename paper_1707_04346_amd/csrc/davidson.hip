@@ -238,11 +238,14 @@ __global__ __launch_bounds__(64) void k_reduce_partials(const double *partial, i
 // Ritz vectors, their sigma, residual-norm partials and preconditioned
 // corrections of up to R roots in one pass over the basis (B and S are read
 // once for all roots).  y: [nr][m] root-major coefficients, theta: [nr].
-template <typename T, int R>
+// (WX: also write the Ritz vectors and their sigma.  R = the roots of the pass, so
+// the accumulators fit in 128 registers: four waves per SIMD keep the 1,024
+// workgroups of a pass resident at once; at 133 registers a quarter of them ran
+// as a second round and the pass took ~1.6x)
+template <typename T, int R, bool WX>
 __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int64_t sv, int m, int nr,
                                                     const double *y, const double *theta, const double *hd,
-                                                    double *xout, T *sout, T *tout, int64_t N, double *partial,
-                                                    int want_x) {
+                                                    double *xout, T *sout, T *tout, int64_t N, double *partial) {
     __shared__ double sh[8];
     __shared__ double ys[R][512];
     __shared__ double th[R];
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
                 if (r >= nr) break;
                 const double res = s[r][u] - th[r] * x[r][u];
                 rr[r] += res * res;
-                if (want_x) {                  // the Ritz vectors and their sigma: only when asked
+                if (WX) {                      // the Ritz vectors and their sigma: only when asked
                     xout[r * N + n] = x[r][u];
                     sout[r * N + n] = T(s[r][u]);
                 }
@@ -806,9 +809,22 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int r = 0; r < nr; ++r) yy[size_t(nr) * mm + r] = theta[r0 + r];
             hipError_t e = hipMemcpyAsync(d.ybuf, yy.data(), yy.size() * sizeof(double), hipMemcpyHostToDevice, d.s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((k_ritz_multi<T, kRitzRoots>), dim3(g), dim3(256), 0, d.s, B, S, N, mm, nr, d.ybuf,
-                               d.ybuf + size_t(nr) * mm, hd, X64 + int64_t(r0) * N, SX + int64_t(r0) * N,
-                               TB + int64_t(r0) * N, N, d.partial, want_x ? 1 : 0);
+#define CIS_RITZ(RR, WXX)                                                                                       \
+    hipLaunchKernelGGL((k_ritz_multi<T, RR, WXX>), dim3(g), dim3(256), 0, d.s, B, S, N, mm, nr, d.ybuf,             \
+                       d.ybuf + size_t(nr) * mm, hd, X64 + int64_t(r0) * N, SX + int64_t(r0) * N,                 \
+                       TB + int64_t(r0) * N, N, d.partial)
+            static_assert(kRitzRoots == 4, "one instantiation per root count");
+            switch (nr * 2 + (want_x ? 1 : 0)) {
+                case 2: CIS_RITZ(1, false); break;
+                case 3: CIS_RITZ(1, true); break;
+                case 4: CIS_RITZ(2, false); break;
+                case 5: CIS_RITZ(2, true); break;
+                case 6: CIS_RITZ(3, false); break;
+                case 7: CIS_RITZ(3, true); break;
+                case 8: CIS_RITZ(4, false); break;
+                default: CIS_RITZ(4, true); break;
+            }
+#undef CIS_RITZ
             if (norms) {
                 std::vector<double> part(size_t(nr) * g);
                 e = hipMemcpyAsync(part.data(), d.partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, d.s);
