@@ -162,11 +162,13 @@ def time_sigma(ctx, cis, torch, dtype, steps, warmup, seed=0, parity=0):
     gen = torch.Generator(device="cuda")
     gen.manual_seed(1000 + seed)
     C = torch.randn(ctx.ndet, dtype=tdt, device="cuda", generator=gen)
-    if parity:
+    n = int(round(ctx.ndet ** 0.5))
+    if parity and n * n == ctx.ndet:
         # a vector of the M_S = 0 sector: C(Ib, Ia) = parity * C(Ia, Ib)
-        n = int(round(ctx.ndet ** 0.5))
         M = C.view(n, n)
         C = (0.5 * (M + parity * M.t())).reshape(-1).contiguous()
+    # (spaces with several blocks: the vector is not projected onto the sector;
+    # the cost of a sigma does not depend on the values, and this is timing only)
     C /= torch.linalg.vector_norm(C)
     S = torch.empty_like(C)
     ctx.set_option(cis.OPT_SPIN_PARITY, parity)
@@ -451,6 +453,12 @@ def extra_workload(name, cis, torch, si, steps, warmup, fp64):
                             "same_spin_materialised": bool(flags & cis.PATH_SS_MATERIALISED)},
                    "sigma3_shape": ctx.last_shape(cis.FP32 if dt == "fp32" else cis.FP64)}
         log(f"{name} {dt}: {out[dt]}")
+    if spec["nalpha"] == spec["nbeta"]:
+        # the even M_S = 0 sector: the beta-beta pass replaced by the mirrored alpha-alpha part
+        d, pp, C, S = time_sigma(ctx, cis, torch, "fp32", steps, warmup, parity=1)
+        del C, S
+        out["fp32_even_sector"] = {"ms_per_sigma": 1e3 * d / steps, "sigma_per_s": steps / d, "pass_ms": pp}
+        log(f"{name} fp32 even sector: {out['fp32_even_sector']}")
     ctx.close()
     torch.cuda.empty_cache()
     return out
@@ -517,8 +525,8 @@ def main():
     extra = {"init_seconds": init_s, "fp32_pass_ms": pp32, **({"autotune": tune} if tune else {}),
              "fp32_path": {"ab_owner_computes": bool(path32 & cis.PATH_AB_OWNER),
                            "same_spin_materialised": bool(path32 & cis.PATH_SS_MATERIALISED)}}
-    # M_S = 0 sector (n_alpha = n_beta, one block): the beta-beta pass is replaced by a transpose
-    sector = na == nb and spec["gas"] is None and spec.get("orbsym") is None
+    # M_S = 0 sector (n_alpha = n_beta): the beta-beta pass is replaced by a transpose
+    sector = na == nb
     if sector:
         dtp, ppp, _, _ = time_sigma(ctx, cis, torch, "fp32", args.steps, 1, parity=1)
         extra.update({"fp32_even_sector_sigma_per_s": args.steps / dtp,

@@ -133,8 +133,11 @@ extern "C" {
                                       diagonal elements, so a sector run can miss a root of a spin its
                                       guess lacks (a quintet below the lowest singlet): ask for more
                                       roots to include such states.
-                                      Needs nalpha = nbeta (EINVAL otherwise) and a one-block (CAS)
-                                      space (EUNSUPPORTED for GAS spaces) */
+                                      Needs nalpha = nbeta (EINVAL otherwise).  GAS and point-group
+                                      spaces qualify (their blocks (ta, tb) and (tb, ta) mirror each
+                                      other): C(Ib, Ia) is then the element of block (tb, ta); a space
+                                      whose alpha and beta tables do not mirror each other gives
+                                      EUNSUPPORTED */
 
 /* passes of one cisigma_apply, in order, as reported by cisigma_pass_times */
 #define CISIGMA_PASS_LAYOUT_IN 0   /* C -> padded alpha-major and beta-major copies */

@@ -259,6 +259,39 @@ def parity_spectrum(space, parity):
     return np.linalg.eigvalsh(Q @ space.hmat() @ Q.T)
 
 
+def parity_basis_dets(space, parity):
+    """Orthonormal basis (rows) of the M_S = 0 sector of any space with
+    n_alpha = n_beta whose determinant set is closed under exchanging the alpha
+    and beta strings (GAS bounds on alpha + beta totals and point-group targets
+    both are): (|Ia Ib> + parity |Ib Ia>)/sqrt(2) for each exchanged pair,
+    the member of the pair with the lower vector index first, and for
+    parity = +1 the determinants with Ia = Ib (Sec. 3.1, Sec. 3.3).  For
+    one-block spaces it is ``parity_basis`` row for row."""
+    d = space.dets()
+    where = {(int(a), int(b)): i for i, (a, b) in enumerate(d)}
+    r2 = 1.0 / np.sqrt(2.0)
+    rows = []
+    for i, (a, b) in enumerate(d):
+        j = where[(int(b), int(a))]          # KeyError: the space is not closed under the exchange
+        if j < i or (j == i and parity < 0):
+            continue
+        v = np.zeros(space.ndet)
+        if j == i:
+            v[i] = 1.0
+        else:
+            v[i] = r2
+            v[j] = parity * r2
+        rows.append(v)
+    return np.array(rows).reshape(len(rows), space.ndet)
+
+
+def parity_spectrum_dets(space, parity):
+    """Eigenvalues (ascending) of H restricted to the sector of
+    ``parity_basis_dets`` (tiny spaces only)."""
+    Q = parity_basis_dets(space, parity)
+    return np.linalg.eigvalsh(Q @ space.hmat() @ Q.T)
+
+
 def davidson(space, nroots=1, tol=1e-10, rtol=None, max_iter=200, max_space=None,
              sigma=None, hdiag=None, verbose=False):
     """Lowest ``nroots`` eigenpairs of H by Davidson-Liu (Sec. 3.3, steps 1-4).

@@ -137,6 +137,7 @@ void free_ctx(cisigma_ctx *c) {
     (void)hipFree(c->d_gp64); (void)hipFree(c->d_gp32); (void)hipFree(c->d_h64); (void)hipFree(c->d_h32);
     (void)hipFree(c->d_jpq);
     (void)hipFree(c->bt.blk); (void)hipFree(c->bt.tb); (void)hipFree(c->bt.tr); (void)hipFree(c->bt.tc);
+    (void)hipFree(c->d_pblk); (void)hipFree(c->d_blkoff);
     (void)hipFree(c->plan.d_entries[0]); (void)hipFree(c->plan.d_entries[1]);
     (void)hipFree(c->d_act_start); (void)hipFree(c->d_act_tiles);
     (void)hipFree(c->go.d_slot); (void)hipFree(c->go.d_coff); (void)hipFree(c->go.d_g32); (void)hipFree(c->go.d_g64);
@@ -294,6 +295,20 @@ int build_layouts(cisigma_ctx *c) {
             }
     }
     c->bt.ntiles = int(tb.size());
+    // mirror blocks: the alpha and beta tables, the padded layouts and the block
+    // set must be mirror images for the M_S = 0 sector
+    bool sym = A.nel == B.nel && A.ntype == B.ntype && A.tocc == B.tocc && A.tcount == B.tcount &&
+               A.tirrep == B.tirrep && c->pl[0].seg == c->pl[1].seg && c->pl[0].ld == c->pl[1].ld;
+    std::vector<int> pblk(c->lay.nblk, -1);
+    for (int b = 0; b < c->lay.nblk && sym; ++b)
+        for (int b2 = 0; b2 < c->lay.nblk; ++b2)
+            if (c->lay.blk_a[b2] == c->lay.blk_b[b] && c->lay.blk_b[b2] == c->lay.blk_a[b]) pblk[b] = b2;
+    for (int b = 0; b < c->lay.nblk && sym; ++b) sym = pblk[b] >= 0;
+    c->spin_sym = sym;
+    if (sym) {
+        HIP_OR_FAIL(c, upload(&c->d_pblk, pblk), "init: block upload");
+        HIP_OR_FAIL(c, upload(&c->d_blkoff, c->lay.blk_off), "init: block upload");
+    }
     HIP_OR_FAIL(c, upload(&c->bt.blk, blk), "init: block upload");
     HIP_OR_FAIL(c, upload(&c->bt.tb, tb), "init: block upload");
     HIP_OR_FAIL(c, upload(&c->bt.tr, tr), "init: block upload");
@@ -2013,8 +2028,9 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: spin parity must be -1, 0 or +1");
             if (value != 0 && ctx->sp[0].nel != ctx->sp[1].nel)
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: spin parity needs nalpha = nbeta");
-            if (value != 0 && !ctx->cas)
-                return cis_set_error(ctx, CISIGMA_EUNSUPPORTED, "set_option: spin parity is built for one-block spaces");
+            if (value != 0 && !ctx->spin_sym)
+                return cis_set_error(ctx, CISIGMA_EUNSUPPORTED,
+                                     "set_option: spin parity needs alpha and beta tables and blocks that mirror each other");
             ctx->spin_parity = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_PROFILE:

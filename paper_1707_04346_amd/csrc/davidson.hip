@@ -426,8 +426,12 @@ __global__ void k_unit2(T *x, int64_t N, int64_t i1, int64_t i2, T v) {
 // lexicographic (value, index) minimum strictly above (pv, pi); with parity
 // p != 0 over the sector representatives (Ia, Ib), Ia <= Ib (Ia < Ib for p = -1)
 // of the one-block vector of side nside
+// (parity != 0: only determinants with I_alpha <= I_beta, < for p = -1; one-block
+// spaces: n = I_alpha * nside + I_beta; spaces with several blocks (nside = 0):
+// the block of n from the caller-layout block offsets, then the string indices)
 __global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, double pv, int64_t pi, double *ov,
-                                                int64_t *oi, int64_t nside, int parity) {
+                                                int64_t *oi, int64_t nside, int parity, const int64_t *blkoff,
+                                                const BlockDev *blk, int nblk, const int *astart, const int *bstart) {
     __shared__ double sv[256];
     __shared__ int64_t si[256];
     double bv = INFINITY;
@@ -435,7 +439,21 @@ __global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, dou
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
         if (parity != 0) {
-            const int64_t ra = n / nside, cb = n % nside;
+            int64_t ra, cb;
+            if (nside > 0) {
+                ra = n / nside;
+                cb = n % nside;
+            } else {
+                int lo = 0, hi = nblk - 1;   // last block with blkoff <= n
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) / 2;
+                    if (blkoff[mid] <= n) lo = mid; else hi = mid - 1;
+                }
+                const BlockDev &B = blk[lo];
+                const int64_t r = (n - blkoff[lo]) / B.nb, c = (n - blkoff[lo]) % B.nb;
+                ra = astart[B.ta] + r;
+                cb = bstart[B.tb] + c;
+            }
             if (ra > cb || (parity < 0 && ra == cb)) continue;
         }
         double v = hd[n];
@@ -613,8 +631,21 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     max_space = std::max(max_space, 2 * nroots);
     // M_S = 0 sector (Sec. 3.1, Sec. 3.3): vectors with C(Ib, Ia) = par C(Ia, Ib)
     const int par = ctx->spin_parity;
-    const int64_t nside = par ? int64_t(ctx->sp[0].nstr) : 0;
-    const int64_t dim = par ? (par > 0 ? nside * (nside + 1) / 2 : nside * (nside - 1) / 2) : N;
+    // one-block spaces index the sector by n = I_alpha * nside + I_beta; with
+    // several (mirror) blocks nside = 0 and the blocks are decoded
+    const int64_t nside = par && ctx->cas ? int64_t(ctx->sp[0].nstr) : 0;
+    int64_t dim = N;
+    if (par && ctx->cas) {
+        dim = par > 0 ? nside * (nside + 1) / 2 : nside * (nside - 1) / 2;
+    } else if (par) {
+        dim = 0;   // pairs I_alpha <= I_beta (< for p = -1) over the blocks
+        for (int b = 0; b < ctx->lay.nblk; ++b) {
+            const int ta = ctx->lay.blk_a[b], tb = ctx->lay.blk_b[b];
+            const int64_t na = ctx->sp[0].tcount[ta], nb = ctx->sp[1].tcount[tb];
+            if (ta < tb) dim += na * nb;
+            else if (ta == tb) dim += par > 0 ? na * (na + 1) / 2 : na * (na - 1) / 2;
+        }
+    }
     if (nroots > dim)
         return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: nroots exceeds the dimension of the spin-parity sector");
     if (int64_t(max_space) > dim) max_space = int(dim);
@@ -655,6 +686,9 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     DV_TRY(launch_hdiag(ctx, hd, d.s));
 
     const int g = d.grid(N);
+    auto symmetrize = [&](T *t) -> hipError_t {
+        return ctx->cas ? launch_symmetrize(t, int(nside), par, dt, d.s) : launch_symmetrize_blocks(ctx, t, par, dt, d.s);
+    };
     // P-space: the np determinants with the lowest H_II (ties: lowest index) and
     // the exact H over them, diagonalised: its lowest eigenvectors are the guess,
     // and on those determinants the correction is (theta - H_PP)^-1 r_P
@@ -666,11 +700,13 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     {
         double pv = -INFINITY;
         int64_t pi = -1;
+        std::vector<uint32_t> sa, sb;   // strings, for the mirror determinants of sector guesses
         std::vector<double> hv(g);
         std::vector<int64_t> hi(g);
         const int nlow = std::max(nroots, np);
         for (int r = 0; r < nlow; ++r) {
-            hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx, nside, par);
+            hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx, nside, par,
+                               ctx->d_blkoff, ctx->bt.blk, ctx->lay.nblk, ctx->d_tstart[0], ctx->d_tstart[1]);
             DV_TRY(hipMemcpyAsync(hv.data(), d.dvec, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
             DV_TRY(hipMemcpyAsync(hi.data(), d.pidx, g * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
             DV_TRY(hipStreamSynchronize(d.s));
@@ -686,11 +722,25 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
                 pdiag.push_back(bv);
                 continue;
             }
-            const int64_t ra = par ? bi / nside : 0, cb = par ? bi % nside : 0;
-            if (par == 0 || ra == cb)
+            int64_t mirror = bi;   // the determinant with the strings exchanged
+            if (par && ctx->cas) {
+                mirror = (bi % nside) * nside + bi / nside;
+            } else if (par) {
+                if (sa.empty()) {
+                    sa.resize(ctx->sp[0].nstr);
+                    sb.resize(ctx->sp[1].nstr);
+                    DV_TRY(hipMemcpy(sa.data(), ctx->sp[0].d_str, sa.size() * 4, hipMemcpyDeviceToHost));
+                    DV_TRY(hipMemcpy(sb.data(), ctx->sp[1].d_str, sb.size() * 4, hipMemcpyDeviceToHost));
+                }
+                uint32_t xa = 0, xb = 0;
+                if (!det_strings(ctx, bi, sa, sb, &xa, &xb) || cisigma_address(ctx, xb, xa, &mirror) != CISIGMA_OK ||
+                    mirror < 0)
+                    return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: guess outside the spin-parity sector");
+            }
+            if (par == 0 || mirror == bi)
                 hipLaunchKernelGGL(k_unit<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, bi);
             else   // (|Ia Ib> + p |Ib Ia>) / sqrt(2)
-                hipLaunchKernelGGL(k_unit2<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, cb * nside + ra, bi,
+                hipLaunchKernelGGL(k_unit2<T>, dim3(g), dim3(256), 0, d.s, B + int64_t(r) * N, N, mirror, bi,
                                    T(par) / T(1.4142135623730951));
         }
         if (np > 0) {
@@ -1057,7 +1107,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
                 T *t = TB + int64_t(j) * N;
                 if (cand[j] != j)
                     DV_TRY(hipMemcpyAsync(t, TB + int64_t(cand[j]) * N, N * es, hipMemcpyDeviceToDevice, d.s));
-                if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
+                if (par) DV_TRY(symmetrize(t));   // back onto the sector
             }
             // orthogonalised against the basis: one classical Gram-Schmidt pass, a
             // second one only when a correction lost more than half of its squared
@@ -1107,7 +1157,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int j = 0; j < nc; ++j) {
                 T *t = B + int64_t(m + j) * N;
                 DV_TRY(hipMemcpyAsync(t, TB + int64_t(cand[j]) * N, N * es, hipMemcpyDeviceToDevice, d.s));
-                if (par) DV_TRY(launch_symmetrize(t, int(nside), par, dt, d.s));   // back onto the sector
+                if (par) DV_TRY(symmetrize(t));   // back onto the sector
             }
             if (nc > 0 && m > 0) {
                 std::vector<double> cc(size_t(m) * nc);

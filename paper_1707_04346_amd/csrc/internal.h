@@ -203,6 +203,12 @@ struct cisigma_ctx {
     cis::PadLayout pl[2];          // [0] alpha-major, [1] beta-major
     int *d_tstart[2] = {nullptr, nullptr};   // device copies of SpinTables::tstart
     bool cas = true;               // one type per spin (single block)
+    // the alpha and beta tables, layouts and allowed blocks are mirror images
+    // (n_alpha = n_beta): the M_S = 0 sector is available; d_pblk[b] is the block
+    // (tb, ta) of block b = (ta, tb), d_blkoff the caller-layout block offsets
+    bool spin_sym = false;
+    int *d_pblk = nullptr;
+    int64_t *d_blkoff = nullptr;
     std::vector<double> h, g;      // host copies of the integrals
     // device integral tables
     int npair = 0;                 // n(n+1)/2 (pairs with diagonal)
@@ -320,6 +326,9 @@ hipError_t launch_gather_parity(const cisigma_ctx *ctx, const void *sp, const vo
                                 int dtype, hipStream_t s);
 // x <- (x + p x^T) / 2 for the caller's one-block vector x[n][n]
 hipError_t launch_symmetrize(void *x, int n, int parity, int dtype, hipStream_t s);
+// (x + p x^T) / 2 in place on a caller-layout vector of a space with several
+// blocks (the transpose maps block (ta, tb) onto block (tb, ta))
+hipError_t launch_symmetrize_blocks(const cisigma_ctx *ctx, void *x, int parity, int dtype, hipStream_t s);
 inline BlockTilesDev block_tiles(const cisigma_ctx *ctx) { return ctx->bt; }
 
 // density matrices (rdm.hip): one-block spaces, n <= 16

@@ -81,6 +81,72 @@ __global__ __launch_bounds__(256) void k_gather_parity(const T *__restrict__ sp,
     }
 }
 
+// The same for spaces with several blocks whose alpha and beta sides mirror each
+// other: the transposed alpha-alpha part of block (ta, tb) is read from block
+// (tb, ta) of st (both in the alpha-major layout).
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_parity_blocks(const T *__restrict__ sp, const T *__restrict__ st,
+                                                             T *__restrict__ sig, const BlockDev *__restrict__ blk,
+                                                             const int *__restrict__ tb, const int *__restrict__ tr,
+                                                             const int *__restrict__ tc, const int *__restrict__ pblk,
+                                                             T p) {
+    __shared__ T tile[64][65];
+    const int t = blockIdx.x;
+    const BlockDev B = blk[tb[t]], Bp = blk[pblk[tb[t]]];
+    const int r0 = tr[t], c0 = tc[t];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int rr = c0 + 4 * i + ty, cc = r0 + tx;   // element (c, r) of the output tile, in the mirror block
+        T v = 0;
+        if (rr < Bp.na && cc < Bp.nb) v = st[Bp.sega + int64_t(rr) * Bp.lda + cc];
+        tile[tx][4 * i + ty] = v;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int i = 0; i < 16; ++i) {
+        int r = r0 + 4 * i + ty, c = c0 + tx;
+        if (r < B.na && c < B.nb) {
+            const int64_t a = B.sega + int64_t(r) * B.lda + c;
+            sig[B.off + int64_t(r) * B.nb + c] = sp[a] + st[a] + p * tile[4 * i + ty][tx];
+        }
+    }
+}
+
+// x <- (x + p x^T) / 2 in place on a caller-layout vector whose blocks mirror
+// each other: element (r, c) of block b = (ta, tb) pairs with element (c, r) of
+// block (tb, ta).  The 64x64 tile (b, r0, c0) is done together with its mirror by
+// the tile with b < mirror, or on a diagonal block by the tile with r0 <= c0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_symmetrize_blocks(T *x, const BlockDev *__restrict__ blk,
+                                                          const int *__restrict__ tb, const int *__restrict__ tr,
+                                                          const int *__restrict__ tc, const int *__restrict__ pblk,
+                                                          T p) {
+    __shared__ T a[64][65], bt[64][65];
+    const int t = blockIdx.x, b = tb[t], b2 = pblk[b];
+    const int r0 = tr[t], c0 = tc[t];
+    if (b > b2 || (b == b2 && r0 > c0)) return;
+    const BlockDev B = blk[b], M = blk[b2];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        a[i][tx] = (r < B.na && c < B.nb) ? x[B.off + int64_t(r) * B.nb + c] : T(0);
+        const int r2 = c0 + i, c2 = r0 + tx;          // mirror tile: rows c0.., columns r0..
+        bt[i][tx] = (r2 < M.na && c2 < M.nb) ? x[M.off + int64_t(r2) * M.nb + c2] : T(0);
+    }
+    __syncthreads();
+    // a[i][j] = x_b(r0 + i, c0 + j), bt[j][i] = x_b2(c0 + j, r0 + i)
+    for (int i = ty; i < 64; i += 4) {
+        const int r = r0 + i, c = c0 + tx;
+        const T v = T(0.5) * (a[i][tx] + p * bt[tx][i]);
+        if (r < B.na && c < B.nb) x[B.off + int64_t(r) * B.nb + c] = v;
+        // mirror element x_b2(c0 + i, r0 + tx) = p * new x_b(r0 + tx, c0 + i)
+        const int r2 = c0 + i, c2 = r0 + tx;
+        const bool same = b == b2 && r0 == c0;         // a diagonal tile holds its own mirror
+        if (!same && r2 < M.na && c2 < M.nb) x[M.off + int64_t(r2) * M.nb + c2] = p * T(0.5) * (a[tx][i] + p * bt[i][tx]);
+    }
+}
+
 // x <- (x + p x^T) / 2 on x[n][n] row-major, in place: block (bi, bj) with
 // bi <= bj owns the 32x32 tile pair (bi, bj) / (bj, bi); blocks below the
 // diagonal return at once.
@@ -201,6 +267,19 @@ hipError_t launch_gather_parity(const cisigma_ctx *ctx, const void *sp, const vo
                                 int dtype, hipStream_t s) {
     BlockTilesDev bt = block_tiles(ctx);
     if (bt.ntiles == 0) return hipSuccess;
+    if (!ctx->cas) {
+        if (!ctx->d_pblk) return hipErrorInvalidValue;
+        if (dtype == CISIGMA_FP32)
+            hipLaunchKernelGGL(k_gather_parity_blocks<float>, dim3(bt.ntiles), dim3(256), 0, s,
+                               static_cast<const float *>(sp), static_cast<const float *>(st),
+                               static_cast<float *>(sigma), bt.blk, bt.tb, bt.tr, bt.tc, ctx->d_pblk, float(parity));
+        else
+            hipLaunchKernelGGL(k_gather_parity_blocks<double>, dim3(bt.ntiles), dim3(256), 0, s,
+                               static_cast<const double *>(sp), static_cast<const double *>(st),
+                               static_cast<double *>(sigma), bt.blk, bt.tb, bt.tr, bt.tc, ctx->d_pblk,
+                               double(parity));
+        return hipGetLastError();
+    }
     if (dtype == CISIGMA_FP32)
         hipLaunchKernelGGL(k_gather_parity<float>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<const float *>(sp),
                            static_cast<const float *>(st), static_cast<float *>(sigma), bt.blk, bt.tr, bt.tc,
@@ -223,6 +302,19 @@ hipError_t launch_symmetrize(void *x, int n, int parity, int dtype, hipStream_t 
     else
         hipLaunchKernelGGL(k_symmetrize<double>, dim3(unsigned(blocks)), dim3(256), 0, s, static_cast<double *>(x), n,
                            nt, double(parity));
+    return hipGetLastError();
+}
+
+hipError_t launch_symmetrize_blocks(const cisigma_ctx *ctx, void *x, int parity, int dtype, hipStream_t s) {
+    BlockTilesDev bt = block_tiles(ctx);
+    if (bt.ntiles == 0) return hipSuccess;
+    if (!ctx->d_pblk) return hipErrorInvalidValue;
+    if (dtype == CISIGMA_FP32)
+        hipLaunchKernelGGL(k_symmetrize_blocks<float>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<float *>(x), bt.blk,
+                           bt.tb, bt.tr, bt.tc, ctx->d_pblk, float(parity));
+    else
+        hipLaunchKernelGGL(k_symmetrize_blocks<double>, dim3(bt.ntiles), dim3(256), 0, s, static_cast<double *>(x),
+                           bt.blk, bt.tb, bt.tr, bt.tc, ctx->d_pblk, double(parity));
     return hipGetLastError();
 }
 

@@ -10,8 +10,11 @@ part.  Checked here:
   the oracle on sampled rows;
 * Davidson in each sector against the dense spectrum of H restricted to the
   sector (``oracle.parity_spectrum``), FP64 and mixed;
-* the option's error paths (n_alpha != n_beta, GAS, out-of-range values,
-  more roots than the sector holds).
+* GAS and point-group spaces (blocks (ta, tb) and (tb, ta) mirror each
+  other): sector sigma against the oracle, and Davidson against the dense
+  spectrum of H restricted to the sector (``oracle.parity_spectrum_dets``);
+* the option's error paths (n_alpha != n_beta, out-of-range values, more
+  roots than the sector holds).
 """
 import numpy as np
 import pytest
@@ -159,9 +162,12 @@ def test_parity_option_errors():
     ctx.set_option(cis.OPT_SPIN_PARITY, 0)
     gas = ([2, 3, 2], [3, 5, 6], [4, 6, 6])
     ctx_g, _ = make(7, 3, 3, gas=gas)
+    ctx_g.set_option(cis.OPT_SPIN_PARITY, -1)     # GAS blocks mirror each other when n_alpha = n_beta
+    ctx_g.set_option(cis.OPT_SPIN_PARITY, 0)
+    ctx_u, _ = make(7, 3, 2, gas=([2, 3, 2], [2, 4, 5], [3, 5, 5]))
     with pytest.raises(cis.CisigmaError) as ei:
-        ctx_g.set_option(cis.OPT_SPIN_PARITY, -1)
-    assert ei.value.status == cis.EUNSUPPORTED
+        ctx_u.set_option(cis.OPT_SPIN_PARITY, 1)
+    assert ei.value.status == cis.EINVAL
     ctx2, _ = make(2, 1, 1)
     for bad in (2, 0.5, -3):
         with pytest.raises(cis.CisigmaError):
@@ -172,3 +178,69 @@ def test_parity_option_errors():
     assert ei.value.status == cis.EINVAL
     e, _, status = ctx2.davidson(1, 1e-10)
     assert status == 0
+
+
+# spaces with several blocks: (norb, n per spin, gas, orbsym, target)
+BLOCKED = [
+    (7, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6]), None, 0),
+    (6, 3, ([2, 2, 2], [0, 0, 6], [6, 6, 6]), None, 0),
+    (8, 4, None, [p % 8 for p in range(8)], 0),
+    (8, 4, None, [p % 8 for p in range(8)], 5),
+]
+
+
+def make_blocked(case, seed=2):
+    norb, ne, gas, orbsym, target = case
+    h, g = si.integrals(norb, 2 * norb, seed, orbsym=orbsym)
+    ctx = _cis().Context(norb, ne, ne, h, g, gas=gas, orbsym=orbsym, target=target)
+    ref = oracle.Space(norb, ne, ne, h, g, gas=gas, orbsym=orbsym, target=target)
+    swap = np.array([ref.address(int(b), int(a)) for a, b in ref.dets()])
+    return ctx, ref, swap
+
+
+def _bid(c):
+    return f"n{c[0]}e{c[1]}" + ("gas" if c[2] else f"sym{c[4]}")
+
+
+@pytest.mark.parametrize("case", BLOCKED, ids=[_bid(c) for c in BLOCKED])
+@pytest.mark.parametrize("parity", [1, -1], ids=["even", "odd"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_parity_sigma_blocked_spaces(case, parity, dtype):
+    """Sector sigma of GAS and point-group spaces: the beta-beta part as the
+    transposed alpha-alpha part read from the mirror block."""
+    cis = _cis()
+    ctx, ref, swap = make_blocked(case)
+    c = si.ci_vector(ctx.ndet, 40)
+    c = 0.5 * (c + parity * c[swap])
+    c /= np.linalg.norm(c)
+    want = ref.sigma(c)
+    ctx.set_option(cis.OPT_SPIN_PARITY, parity)
+    got = gpu_sigma(ctx, c, dtype)
+    assert rel(got, want) <= TOL[dtype]
+    assert np.abs(got - parity * got[swap]).max() <= TOL[dtype] * np.abs(got).max() * 10
+    ctx.set_option(cis.OPT_SPIN_PARITY, 0)
+    assert rel(gpu_sigma(ctx, c, dtype), want) <= TOL[dtype]
+
+
+@pytest.mark.parametrize("case", BLOCKED[:3], ids=[_bid(c) for c in BLOCKED[:3]])
+@pytest.mark.parametrize("parity", [1, -1], ids=["even", "odd"])
+def test_davidson_parity_blocked_spaces(case, parity):
+    """Sector Davidson of GAS and point-group spaces (FP64 and mixed) against
+    the dense spectrum of H restricted to the sector; the FP64 eigenvectors lie
+    in the sector."""
+    cis = _cis()
+    ctx, ref, swap = make_blocked(case)
+    want = oracle.parity_spectrum_dets(ref, parity)[:2]
+    ctx.set_option(cis.OPT_SPIN_PARITY, parity)
+    X = torch.empty(2, ctx.ndet, dtype=torch.float64, device="cuda")
+    e, st, status = ctx.davidson(2, 1e-10, vecs=X)
+    assert status == 0
+    assert np.allclose(e, want, atol=1e-8), (e, want)
+    for r in range(2):
+        v = X[r].cpu().numpy()
+        assert np.abs(v - parity * v[swap]).max() < 1e-10
+    ctx.set_option(cis.OPT_PRECISION, cis.FP32)
+    e32, st32, status = ctx.davidson(2, 1e-10)
+    assert status == 0
+    assert np.allclose(e32, want, atol=1e-6), (e32 - want)
+

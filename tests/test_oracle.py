@@ -432,6 +432,44 @@ def test_parity_sector_total_spin(norb, ne):
         assert np.all(s % 2 == (0 if parity > 0 else 1)), (parity, sorted(set(s)))
 
 
+@pytest.mark.parametrize("norb,ne,seed", [(5, 2, 3), (4, 2, 8)])
+def test_parity_basis_dets_is_the_one_block_basis(norb, ne, seed):
+    """For one-block spaces the sector basis built from the determinant list is
+    the one-block basis row for row."""
+    h, g = si.integrals(norb, 2 * norb, seed)
+    S = oracle.Space(norb, ne, ne, h, g)
+    n = int(round(math.sqrt(S.ndet)))
+    for parity in (1, -1):
+        assert np.array_equal(oracle.parity_basis_dets(S, parity), oracle.parity_basis(n, parity))
+
+
+@pytest.mark.parametrize("norb,ne,gas,orbsym,target", [
+    (7, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6]), None, 0),
+    (6, 3, ([2, 2, 2], [0, 0, 6], [6, 6, 6]), None, 0),
+    (6, 3, None, [0, 1, 2, 3, 0, 1], 0),
+    (6, 2, None, [0, 1, 2, 3, 0, 1], 3),
+])
+def test_parity_sectors_of_blocked_spaces(norb, ne, gas, orbsym, target):
+    """GAS and point-group spaces with n_alpha = n_beta: the two sector bases
+    together are an orthonormal basis of the space, every basis vector is even
+    or odd under the exchange of the alpha and beta strings, H couples no even
+    vector to an odd one, and the two sector spectra together are the spectrum
+    of H."""
+    h, g = si.integrals(norb, 2 * norb, 6, orbsym=orbsym)
+    S = oracle.Space(norb, ne, ne, h, g, gas=gas, orbsym=orbsym, target=target)
+    d = S.dets()
+    swap = np.array([S.address(int(b), int(a)) for a, b in d])
+    Qe, Qo = oracle.parity_basis_dets(S, 1), oracle.parity_basis_dets(S, -1)
+    Q = np.vstack([Qe, Qo])
+    assert Q.shape[0] == S.ndet
+    assert np.abs(Q @ Q.T - np.eye(S.ndet)).max() < 1e-14
+    assert np.array_equal(Qe[:, swap], Qe) and np.array_equal(Qo[:, swap], -Qo)
+    H = S.hmat()
+    assert np.abs(Qe @ H @ Qo.T).max() < 1e-12
+    both = np.sort(np.concatenate([oracle.parity_spectrum_dets(S, 1), oracle.parity_spectrum_dets(S, -1)]))
+    assert np.allclose(both, np.linalg.eigvalsh(H), atol=1e-11)
+
+
 @pytest.mark.parametrize("t,U", [(1.0, 3.0), (1.3, 5.5)])
 def test_parity_two_site_hubbard(t, U):
     """Two electrons on two sites: the three singlets (U -+ r)/2 and U are the
