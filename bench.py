@@ -453,6 +453,14 @@ def extra_workload(name, cis, torch, si, steps, warmup, fp64):
                             "same_spin_materialised": bool(flags & cis.PATH_SS_MATERIALISED)},
                    "sigma3_shape": ctx.last_shape(cis.FP32 if dt == "fp32" else cis.FP64)}
         log(f"{name} {dt}: {out[dt]}")
+    if spec["gas"] is not None or spec.get("orbsym") is not None:
+        # the per-block launch baseline: one launch per owner-computes unit instead of one over all
+        ctx.set_option(cis.OPT_UNIT_LAUNCH, 1)
+        d, pp, C, S = time_sigma(ctx, cis, torch, "fp32", steps, warmup)
+        del C, S
+        ctx.set_option(cis.OPT_UNIT_LAUNCH, 0)
+        out["fp32_one_launch_per_unit"] = {"ms_per_sigma": 1e3 * d / steps, "pass_ms": pp}
+        log(f"{name} fp32 one launch per unit: {out['fp32_one_launch_per_unit']}")
     if spec["nalpha"] == spec["nbeta"]:
         # the even M_S = 0 sector: the beta-beta pass replaced by the mirrored alpha-alpha part
         d, pp, C, S = time_sigma(ctx, cis, torch, "fp32", steps, warmup, parity=1)

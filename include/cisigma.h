@@ -78,12 +78,15 @@ extern "C" {
 #define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels;
                                       2: for one-block spaces, the owner-computes units of the GAS form
                                       in place of the one-block owner kernel (rebuilds the unit tables) */
+#define CISIGMA_OPT_UNIT_LAUNCH 19 /* owner-computes units: 0 (default) one launch over every unit, longest
+                                      rows of work first; 1: one launch per unit, in the same order (the
+                                      per-block launch baseline) */
 #define CISIGMA_OPT_UNIT_COLS 18   /* owner-computes units (GAS spaces, one-block spaces whose sigma row is
                                       longer than the LDS, or path 2): at most this many sigma columns per
                                       unit, 64..65536; 0 (default): as many as the LDS holds.  Rows are cut
                                       at beta-type ends (GAS) or at the occupation classes of the two
                                       highest orbitals (one-block), and inside a piece only when it alone
-                                      is longer.  Rebuilds the unit tables */
+                                      is longer.  Rebuilds the unit tables; set by cisigma_autotune */
 #define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products: at most this many columns per chunk
                                       (a positive multiple of 64); 0 (default): as many as fit in memory */
 #define CISIGMA_OPT_OVERLAP 12     /* nonzero: cisigma_apply runs the beta-beta pass on a second
@@ -308,11 +311,12 @@ int cisigma_hmat_block(cisigma_ctx *ctx, int n, const int64_t *rows, int m, cons
  * space and dtype by timing them (Sec. 3.3: the batches of the GAS partition;
  * here their order on one GPU): for each knob in turn, every candidate value
  * is set and reps applies of a fixed synthetic vector are timed with HIP
- * events; the fastest value stays set.  Knobs: the launch order of the GAS
- * owner-computes units (most source tiles per row first, alpha-type order,
- * most total work first, heavy and light alternating) and the column split of
- * the same-spin kernels that scatter with atomics (GAS spaces).  Results do not
- * depend on the knobs beyond rounding order.
+ * events; the fastest value stays set.  Knobs: the width of the owner-computes
+ * units (CISIGMA_OPT_UNIT_COLS: the LDS, 16384, 8192, 4096 columns; the unit
+ * tables are rebuilt for each), their launch order (most source tiles per row
+ * first, alpha-type order, most total work first, heavy and light alternating)
+ * and the column split of the same-spin pair-product kernel of spaces with
+ * several types.  Results do not depend on the knobs beyond rounding order.
  *   dtype       CISIGMA_FP32 or CISIGMA_FP64: the precision tuned
  *   reps        timed applies per candidate, 1..100
  *   report      host char[report_len] (may be NULL when report_len = 0): one

@@ -949,8 +949,10 @@ int build_gas_owner(cisigma_ctx *c, bool one_block) {
         if (size_t(tile0) * 4 * (ew + 1) * 64 * 4 >= (size_t(1) << 31)) continue;
         std::vector<int> utab;
         int nblk = 0, maxc = 0;
+        G.launch[d].clear();
         for (const auto &un : units) {
             utab.insert(utab.end(), {un.ta, un.lo, un.hi, un.act0, un.nact, A.tstart[un.ta], nblk, 0});
+            G.launch[d].push_back({nblk, A.tcount[un.ta]});
             nblk += A.tcount[un.ta];
             maxc = std::max(maxc, un.hi - un.lo);
         }
@@ -1319,9 +1321,11 @@ int gas_set_unit_order(cisigma_ctx *c, int d, int order) {
     }
     std::vector<int> utab;
     int nblk = 0;
+    G.launch[d].clear();
     for (size_t k : ord) {
         const auto &un = U[k];
         utab.insert(utab.end(), {un.ta, un.lo, un.hi, un.act0, un.nact, A.tstart[un.ta], nblk, 0});
+        G.launch[d].push_back({nblk, A.tcount[un.ta]});
         nblk += A.tcount[un.ta];
     }
     HIP_OR_FAIL(c, hipDeviceSynchronize(), "unit order");
@@ -1876,6 +1880,30 @@ CIS_API int cisigma_autotune(cisigma_ctx *ctx, int dtype, int reps, char *report
         std::snprintf(line, sizeof line, "as set: %.3f ms per sigma\n", double(ms));
         rep += line;
     }
+    // knob 0: unit width (rows cut where a piece is longer than the LDS or than this)
+    if (!ctx->go.units[d].empty()) {
+        const int keep = ctx->unit_cols;
+        int best = keep;
+        float best_ms = 0;
+        const int cands[] = {0, 16384, 8192, 4096};
+        for (int k = 0; k < 4; ++k) {
+            ctx->unit_cols = cands[k];
+            int rc = cis::rebuild_gas_owner(ctx);
+            float ms = 0;
+            if (rc == 0 && !ctx->go.units[d].empty()) rc = time_apply(&ms);
+            else if (rc == 0) continue;          // no units at this width: not a candidate
+            if (rc) { ctx->unit_cols = keep; cis::rebuild_gas_owner(ctx); return done(rc); }
+            std::snprintf(line, sizeof line, "unit_cols %d%s: %.3f ms per sigma\n", cands[k],
+                          cands[k] == 0 ? " (the LDS)" : "", double(ms));
+            rep += line;
+            if (best_ms == 0 || ms < best_ms) { best = cands[k]; best_ms = ms; }
+        }
+        ctx->unit_cols = best;
+        const int rc = cis::rebuild_gas_owner(ctx);
+        if (rc) return done(rc);
+        std::snprintf(line, sizeof line, "unit_cols -> %d\n", best);
+        rep += line;
+    }
     // knob 1: launch order of the GAS owner units of this precision
     if (!ctx->go.units[d].empty()) {
         int best = ctx->unit_order[d];
@@ -1982,6 +2010,11 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             ctx->ab_mode = int(value);
             return rebuild ? cis::rebuild_gas_owner(ctx) : CISIGMA_OK;
         }
+        case CISIGMA_OPT_UNIT_LAUNCH:
+            if (value != 0 && value != 1) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit launch must be 0 or 1");
+            cis::drop_graphs(ctx);
+            ctx->unit_launch = int(value);
+            return CISIGMA_OK;
         case CISIGMA_OPT_UNIT_COLS:
             if (value < 0 || value > 65536 || value != std::floor(value) || (value > 0 && value < 64))
                 return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit columns must be 0 or 64..65536");

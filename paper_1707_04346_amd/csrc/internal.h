@@ -171,6 +171,7 @@ struct GasOwner {
     double *d_g64 = nullptr;
     // per precision ([0] FP64, [1] FP32)
     std::vector<GasUnit> units[2];
+    std::vector<std::pair<int, int>> launch[2];   // per unit in device-table order: first workgroup, rows
     uint32_t *d_act[2] = {nullptr, nullptr};   // [.][4]: {plan tile, k-step mask, row-block mask,
                                                //   beta type | first column << 8}
     int *d_units[2] = {nullptr, nullptr};      // [.][8]: ta, lo, hi, act0, nact, first alpha string, first block
@@ -257,6 +258,7 @@ struct cisigma_ctx {
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
     int ab_mode = 0;               // CISIGMA_OPT_SIGMA_PATH
     int unit_cols = 0;             // CISIGMA_OPT_UNIT_COLS (0: what the LDS holds)
+    int unit_launch = 0;           // CISIGMA_OPT_UNIT_LAUNCH (0: one launch over all units, 1: one per unit)
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)
     int spin_parity = 0;   // M_S = 0 sector: C(Ib, Ia) = p C(Ia, Ib) assumed (0: none)
     // captured apply graphs (CISIGMA_OPT_GRAPH)

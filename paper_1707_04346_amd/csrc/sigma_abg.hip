@@ -58,6 +58,7 @@ struct AbgArgs {
     const uint32_t *plan;
     uint32_t plan_bytes, zero_off;   // zero_off: element index of the zero row (C may exceed 4 GB)
     int ld0;                         // row stride of one-block spaces (the eight-wave unit kernel)
+    int block_base;                  // workgroup index of blockIdx 0 (one launch per unit: its first)
     int anexc, n, mp, ntb, nunits;   // mp: W rows (pair rows with gaps; unused rows have zero integrals)
     int nvirt;                   // the longest unit row (LDS layout)
 };
@@ -77,11 +78,12 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     T *sig = W + MP * kAbxWS;                              // [nvirt + 64]
     uint32_t *rowoff = reinterpret_cast<uint32_t *>(sig + p.nvirt + 64);   // [ntb][KP] element offsets
 
+    const int vb = int(blockIdx.x) + p.block_base;         // this workgroup in the unit table
     int ui = 0;                                            // this workgroup's unit (uniform)
-    while (ui + 1 < p.nunits && int(blockIdx.x) >= uni(p.units[8 * (ui + 1) + 6])) ++ui;
+    while (ui + 1 < p.nunits && vb >= uni(p.units[8 * (ui + 1) + 6])) ++ui;
     const int *U = p.units + 8 * uni(ui);
     const int ulo = uni(U[1]), uhi = uni(U[2]), ncol = uhi - ulo;
-    const int Ia = uni(U[5]) + (int(blockIdx.x) - uni(U[6]));
+    const int Ia = uni(U[5]) + (vb - uni(U[6]));
     const int ta = p.atype[Ia], ra = Ia - p.astart[ta];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int cb = wave & 1, grp = wave >> 1;
@@ -289,11 +291,12 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_gw(AbgArgs<T> p) {
     T *W1 = W0 + MP * kAbxWS;
     T *sig = W1 + MP * kAbxWS;                             // [nvirt + 64]
 
+    const int vb = int(blockIdx.x) + p.block_base;
     int ui = 0;
-    while (ui + 1 < p.nunits && int(blockIdx.x) >= uni(p.units[8 * (ui + 1) + 6])) ++ui;
+    while (ui + 1 < p.nunits && vb >= uni(p.units[8 * (ui + 1) + 6])) ++ui;
     const int *U = p.units + 8 * uni(ui);
     const int ulo = uni(U[1]), ncol = uni(U[2]) - ulo;
-    const int Ia = uni(U[5]) + (int(blockIdx.x) - uni(U[6]));
+    const int Ia = uni(U[5]) + (vb - uni(U[6]));
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     T *srow = p.sp + int64_t(Ia) * p.ld0 + ulo;
@@ -530,6 +533,18 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.nunits = int(G.units[d].size());
     a.nvirt = G.maxcols[d];
     int *kshape = const_cast<cisigma_ctx *>(ctx)->last_shape[sizeof(T) == 4];
+    // one launch over every unit, or (CISIGMA_OPT_UNIT_LAUNCH) one launch per unit
+    a.block_base = 0;
+    auto launch_units = [&](AbgArgs<T> x, auto run) -> hipError_t {
+        if (ctx->unit_launch == 0) return run(x, G.nblocks[d]);
+        for (const auto &lu : G.launch[d]) {
+            if (lu.second == 0) continue;
+            x.block_base = lu.first;
+            const hipError_t e = run(x, lu.second);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
     // one-block FP32: the eight-wave form when its two W buffers and the row fit
     if constexpr (sizeof(T) == 4) {
       if (ctx->cas && (size_t(2) * 16 * G.rb * kAbxWS + a.nvirt + 64) * sizeof(T) <= 160 * 1024) {
@@ -537,7 +552,7 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
         bool ran = false;
 #define CIS_RUNW(K, R, E)                                               \
     if (!ran && G.ks == K && G.rb == R && G.plan[d].ew == E) {          \
-        *err = run_abgw<T, K, R, E>(a, G.nblocks[d], s);                \
+        *err = launch_units(a, [&](const AbgArgs<T> &x, int n) { return run_abgw<T, K, R, E>(x, n, s); }); \
         kshape[0] = K; kshape[1] = R; kshape[2] = E; kshape[3] = 4;     \
         ran = true;                                                     \
     }
@@ -548,7 +563,7 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     }
 #define CIS_RUN(K, R, E)                                                \
     if (G.ks == K && G.rb == R && G.plan[d].ew == E) {                  \
-        *err = run_abg<T, K, R, E>(a, G.nblocks[d], s);                 \
+        *err = launch_units(a, [&](const AbgArgs<T> &x, int n) { return run_abg<T, K, R, E>(x, n, s); }); \
         kshape[0] = K; kshape[1] = R; kshape[2] = E; kshape[3] = 3;     \
     }
     CIS_ABG_SHAPES(CIS_RUN)

@@ -63,6 +63,7 @@ def test_autotune_reports_and_keeps_sigma(dtype):
     assert "same_spin_split ->" in report
     if ctx.last_path(prec) & cis.PATH_AB_OWNER:
         assert "gas_unit_order ->" in report
+        assert "unit_cols ->" in report
     c = si.ci_vector(ctx.ndet, 9)
     assert rel(sigma(ctx, c, dtype), ref.sigma(c)) <= TOL[dtype]
 

@@ -379,3 +379,29 @@ def test_unit_cols_option_rejects_bad_values():
             ctx.set_option(cis.OPT_UNIT_COLS, bad)
     with pytest.raises(Exception):
         ctx.set_option(cis.OPT_SIGMA_PATH, 3)
+
+
+@pytest.mark.parametrize("case,cols", [((7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])), 0), ((10, 5, 5, None), 64)],
+                         ids=["gas7", "n10_w64"])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_one_launch_per_unit_is_the_same_sigma(case, cols, dtype):
+    """CISIGMA_OPT_UNIT_LAUNCH = 1 (one launch per unit, the per-block baseline)
+    runs the same workgroups as the single launch: the same sigma bit for bit."""
+    cis = _cis()
+    norb, na, nb, gas = case
+    ctx, ref = make(norb, na, nb, gas=gas, seed=27)
+    if gas is None:
+        ctx.set_option(cis.OPT_SIGMA_PATH, 2)
+    if cols:
+        ctx.set_option(cis.OPT_UNIT_COLS, cols)
+    c = si.ci_vector(ctx.ndet, 28)
+    one = gpu_sigma(ctx, c, dtype)
+    ctx.set_option(cis.OPT_UNIT_LAUNCH, 1)
+    per = gpu_sigma(ctx, c, dtype)
+    dt = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert ctx.last_path(dt) & cis.PATH_AB_OWNER
+    assert np.array_equal(one, per)
+    assert rel(per, ref.sigma(c)) <= (TOL64 if dtype == torch.float64 else TOL32)
+    with pytest.raises(Exception):
+        ctx.set_option(cis.OPT_UNIT_LAUNCH, 2)
+
