@@ -87,8 +87,11 @@ extern "C" {
                                       at beta-type ends (GAS) or at the occupation classes of the two
                                       highest orbitals (one-block), and inside a piece only when it alone
                                       is longer.  Rebuilds the unit tables; set by cisigma_autotune */
-#define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products: at most this many columns per chunk
-                                      (a positive multiple of 64); 0 (default): as many as fit in memory */
+#define CISIGMA_OPT_SS_CHUNK 9     /* materialised same-spin products of one-block spaces: at most this many
+                                      columns per chunk (a positive multiple of 64), within the chunk the
+                                      workspace was sized for; 0 (default): the workspace's chunk, whose
+                                      slab of the gathered copy stays near 192 MiB (the Infinity Cache)
+                                      when that copy is below 2 GB, and what fits in memory */
 #define CISIGMA_OPT_OVERLAP 12     /* nonzero: cisigma_apply runs the beta-beta pass on a second
                                       stream of the context, overlapping the alpha-beta pass, and joins
                                       before the output gather (the call stays ordered on `stream`);

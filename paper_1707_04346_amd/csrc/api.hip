@@ -1141,12 +1141,22 @@ int ensure_workspace(cisigma_ctx *c, int dtype) {
     // padding columns of the C copies stay zero for good
     HIP_OR_FAIL(c, hipMemset(W.cp, 0, na), "apply: workspace");
     HIP_OR_FAIL(c, hipMemset(W.ct, 0, nb), "apply: workspace");
-    // materialised same-spin rows for one-type spins: all columns if they fit in half
-    // of what is free, else column chunks (multiples of 64)
+    // materialised same-spin rows for one-type spins: column chunks (multiples of 64)
+    // whose slab of the gathered copy stays near 192 MiB (inside the 256 MB Infinity
+    // Cache, so the ~28 reads of each row mostly hit it; measured at CAS(16,16): 4,096
+    // FP32 / 2,048 FP64 columns cut a same-spin pass 9.3 -> 8.9 ms, 19.0 -> 17.7 ms)
+    // where the gathered copy is below 2 GB, and at most what fits in half of what
+    // is free
     size_t rows = 0, cols = 0;
     if (ys_shape(c, &rows, &cols) && hipMemGetInfo(&fr, &tot) == hipSuccess) {
         size_t budget = fr / 2;
         size_t chunk = std::min(cols, budget / (rows * es) / cis::kTileCols * cis::kTileCols);
+        const size_t xrows = size_t(std::max(c->sp[0].nstr, c->sp[1].nstr)) + 1;
+        if (xrows * cols * es < (size_t(1) << 31)) {
+            const size_t slab = std::max<size_t>(cis::kTileCols, (size_t(192) << 20) / (xrows * es) / cis::kTileCols *
+                                                                   cis::kTileCols);
+            chunk = std::min(chunk, slab);
+        }
         if (chunk >= size_t(cis::kTileCols) && hipMalloc(&W.ys, rows * chunk * es) == hipSuccess)
             W.ys_chunk = int(chunk);
         else
