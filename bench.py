@@ -329,14 +329,14 @@ def time_rdm(ctx, torch, n, na, nb, ndet):
 
 def stored_same_spin_bytes():
     """HBM bytes of one same-spin pass (pair products + gather) from the committed
-    counter summary, or None when those kernels changed after the counters
-    were taken."""
+    counter summary, or None when those kernels, or the host code that sets
+    their column chunks, changed after the counters were taken."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1707_04346_amd", "csrc")
     prof = os.path.join(ROOT, "profiles", "k_sigma_ab_ws_cas16_fp32_traffic.txt")
     if not os.path.exists(prof):
         return None
-    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sigma_ss.hip", "bufio.h"))).hexdigest()
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sigma_ss.hip", "bufio.h", "api.hip"))).hexdigest()
     fields = {}
     for ln in open(prof):
         if ":" in ln:
