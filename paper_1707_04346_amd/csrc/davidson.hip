@@ -44,6 +44,91 @@ constexpr int kThick = 16;        // most vectors kept by a thick restart (curre
 template <typename T>
 __device__ __forceinline__ double ld(const T *p, int64_t i) { return double(p[i]); }
 
+// Element access of the streaming kernels.  Quad form (Q, for vectors whose
+// length and stride are multiples of 4): each thread owns four consecutive
+// elements and moves them with 16-byte loads and stores, which keeps about
+// twice the bytes in flight of four-byte accesses (measured: a Ritz-shaped pass
+// over 20 FP32 vectors streams at 4.7 TB/s this way against 2.2 TB/s).  Plain
+// form: E elements blockDim apart, bounds-checked against N.
+template <bool Q, int E>
+struct Lanes {
+    static_assert(!Q || E == 4, "the quad form moves four elements");
+    __device__ static int64_t start() {
+        return Q ? (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4
+                 : int64_t(blockIdx.x) * blockDim.x * E + threadIdx.x;
+    }
+    __device__ static int64_t stride() { return int64_t(gridDim.x) * blockDim.x * E; }
+    __device__ static int64_t at(int64_t n0, int u) { return Q ? n0 + u : n0 + int64_t(u) * blockDim.x; }
+};
+
+__device__ __forceinline__ void ld4(const float *p, double (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const double *p, double (&o)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+__device__ __forceinline__ void st4(float *p, const double (&v)[4]) {
+    *reinterpret_cast<float4 *>(p) = make_float4(float(v[0]), float(v[1]), float(v[2]), float(v[3]));
+}
+__device__ __forceinline__ void st4(double *p, const double (&v)[4]) {
+    reinterpret_cast<double2 *>(p)[0] = make_double2(v[0], v[1]);
+    reinterpret_cast<double2 *>(p)[1] = make_double2(v[2], v[3]);
+}
+
+// o[u] = p[element u of the thread's group at n0] (0 beyond N in the plain form)
+template <bool Q, int E, typename T>
+__device__ __forceinline__ void lde(const T *p, int64_t n0, int64_t N, double (&o)[E]) {
+    if constexpr (Q) {
+        ld4(p + n0, o);
+    } else {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int64_t n = Lanes<Q, E>::at(n0, u);
+            o[u] = n < N ? double(p[n]) : 0.0;
+        }
+    }
+}
+
+// the same in the storage type (converted where used, which keeps FP32 operands
+// in half the registers)
+__device__ __forceinline__ void ld4t(const float *p, float (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4t(const double *p, double (&o)[4]) {
+    const double2 a = reinterpret_cast<const double2 *>(p)[0], b = reinterpret_cast<const double2 *>(p)[1];
+    o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+
+template <bool Q, int E, typename T>
+__device__ __forceinline__ void lde_t(const T *p, int64_t n0, int64_t N, T (&o)[E]) {
+    if constexpr (Q) {
+        ld4t(p + n0, o);
+    } else {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int64_t n = Lanes<Q, E>::at(n0, u);
+            o[u] = n < N ? p[n] : T(0);
+        }
+    }
+}
+
+template <bool Q, int E, typename T>
+__device__ __forceinline__ void ste(T *p, int64_t n0, int64_t N, const double (&v)[E]) {
+    if constexpr (Q) {
+        st4(p + n0, v);
+        (void)N;
+    } else {
+#pragma unroll
+        for (int u = 0; u < E; ++u) {
+            const int64_t n = Lanes<Q, E>::at(n0, u);
+            if (n < N) p[n] = T(v[u]);
+        }
+    }
+}
+
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -83,12 +168,16 @@ __global__ __launch_bounds__(256) void k_dots(const TX *X, int64_t sx, int nx, c
 
 // partial[b][j * nx + i] = sum over block b's slice of X_i . Y_j, for j < ny <= kMultiY:
 // X is read once for all Y
-template <typename TX, typename TY>
+template <typename TX, typename TY, bool Q>
 __global__ __launch_bounds__(256) void k_dots_multi(const TX *X, int64_t sx, int nx, const TY *Y, int64_t sy, int ny,
                                                     int64_t N, double *partial) {
-    constexpr int GX = 8;                                  // X vectors per pass over Y
+    // X vectors per pass over Y (four in the FP64 quad form: its accumulators and
+    // loads of eight would leave fewer than four waves per SIMD for the 1,024
+    // workgroups; operands stay in their storage type until used)
+    constexpr int GX = Q && sizeof(TX) == 8 ? 4 : 8;
+    constexpr int E = Q ? 4 : 1;
+    using L = Lanes<Q, E>;
     __shared__ double sh[4][GX * kMultiY];
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     for (int i0 = 0; i0 < nx; i0 += GX) {
         double acc[GX][kMultiY];
@@ -96,16 +185,26 @@ __global__ __launch_bounds__(256) void k_dots_multi(const TX *X, int64_t sx, int
         for (int a = 0; a < GX; ++a)
 #pragma unroll
             for (int j = 0; j < kMultiY; ++j) acc[a][j] = 0;
-        for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-            double yv[kMultiY];
+        for (int64_t n0 = L::start(); n0 < N; n0 += L::stride()) {
+            TY yv[kMultiY][E];
 #pragma unroll
-            for (int j = 0; j < kMultiY; ++j) yv[j] = j < ny ? double(Y[j * sy + n]) : 0.0;
+            for (int j = 0; j < kMultiY; ++j) {
+                if (j < ny) {
+                    lde_t<Q, E>(Y + j * sy, n0, N, yv[j]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) yv[j][e] = TY(0);
+                }
+            }
 #pragma unroll
             for (int a = 0; a < GX; ++a) {
                 if (i0 + a >= nx) break;
-                const double xv = double(X[(i0 + a) * sx + n]);
+                TX xv[E];
+                lde_t<Q, E>(X + (i0 + a) * sx, n0, N, xv);
 #pragma unroll
-                for (int j = 0; j < kMultiY; ++j) acc[a][j] += xv * yv[j];
+                for (int j = 0; j < kMultiY; ++j)
+#pragma unroll
+                    for (int e = 0; e < E; ++e) acc[a][j] += double(xv[e]) * double(yv[j][e]);
             }
         }
 #pragma unroll
@@ -153,10 +252,12 @@ __global__ __launch_bounds__(256) void k_subtract_multi(const T *X, int64_t sx, 
 // T_j -= sum_i c[j * nx + i] X_i for j < NY (one pass over X, as k_subtract_multi), with
 // per-block partial sums of |T_j|^2 before the update and of T_j . T_k (k <= j)
 // of the stored (rounded) results: partial[b][v], v < NY + NY(NY+1)/2
-template <typename T, int NY>
+template <typename T, int NY, bool Q>
 __global__ __launch_bounds__(256) void k_subtract_gram(const T *X, int64_t sx, int nx, const double *c, T *Tv,
                                                        int64_t st, int64_t N, double *partial) {
     constexpr int NV = NY + NY * (NY + 1) / 2;
+    constexpr int E = Q ? 4 : 1;
+    using L = Lanes<Q, E>;
     __shared__ double cs[NY * 512];
     __shared__ double sh[4][NV];
     for (int i = threadIdx.x; i < NY * nx; i += blockDim.x) cs[i] = c[i];
@@ -164,32 +265,37 @@ __global__ __launch_bounds__(256) void k_subtract_gram(const T *X, int64_t sx, i
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-        double v[NY];
+    for (int64_t n0 = L::start(); n0 < N; n0 += L::stride()) {
+        double v[NY][E];
 #pragma unroll
         for (int j = 0; j < NY; ++j) {
-            v[j] = double(Tv[j * st + n]);
-            acc[j] += v[j] * v[j];
+            lde<Q, E>(Tv + j * st, n0, N, v[j]);
+#pragma unroll
+            for (int e = 0; e < E; ++e) acc[j] += v[j][e] * v[j][e];
         }
 #pragma unroll 8
         for (int i = 0; i < nx; ++i) {
-            const double xv = double(X[i * sx + n]);
+            double xv[E];
+            lde<Q, E>(X + i * sx, n0, N, xv);
 #pragma unroll
-            for (int j = 0; j < NY; ++j) v[j] -= cs[j * nx + i] * xv;
+            for (int j = 0; j < NY; ++j)
+#pragma unroll
+                for (int e = 0; e < E; ++e) v[j][e] -= cs[j * nx + i] * xv[e];
         }
-        double u[NY];
+        double u[NY][E];
 #pragma unroll
         for (int j = 0; j < NY; ++j) {
-            const T r = T(v[j]);
-            Tv[j * st + n] = r;
-            u[j] = double(r);
+#pragma unroll
+            for (int e = 0; e < E; ++e) u[j][e] = double(T(v[j][e]));
+            ste<Q, E>(Tv + j * st, n0, N, u[j]);
         }
         int q = NY;
 #pragma unroll
         for (int j = 0; j < NY; ++j)
 #pragma unroll
-            for (int k = 0; k <= j; ++k) acc[q++] += u[j] * u[k];
+            for (int k = 0; k <= j; ++k, ++q)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[q] += u[j][e] * u[k][e];
     }
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
 #pragma unroll
@@ -205,22 +311,27 @@ __global__ __launch_bounds__(256) void k_subtract_gram(const T *X, int64_t sx, i
 }
 
 // D_j = sum_{k < NY} w[j * NY + k] T_k for j < nd (FP64 combination, one rounding)
-template <typename T, int NY>
+template <typename T, int NY, bool Q>
 __global__ __launch_bounds__(256) void k_combine_new(const T *Tv, int64_t st, const double *w, int nd, T *D,
                                                      int64_t sd, int64_t N) {
+    constexpr int E = Q ? 4 : 1;
+    using L = Lanes<Q, E>;
     __shared__ double ws[NY * NY];
     for (int i = threadIdx.x; i < nd * NY; i += blockDim.x) ws[i] = w[i];
     __syncthreads();
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-        double t[NY];
+    for (int64_t n0 = L::start(); n0 < N; n0 += L::stride()) {
+        double t[NY][E];
 #pragma unroll
-        for (int k = 0; k < NY; ++k) t[k] = double(Tv[k * st + n]);
+        for (int k = 0; k < NY; ++k) lde<Q, E>(Tv + k * st, n0, N, t[k]);
         for (int j = 0; j < nd; ++j) {
-            double a = 0;
+            double a[E];
 #pragma unroll
-            for (int k = 0; k < NY; ++k) a += ws[j * NY + k] * t[k];
-            D[j * sd + n] = T(a);
+            for (int e = 0; e < E; ++e) a[e] = 0;
+#pragma unroll
+            for (int k = 0; k < NY; ++k)
+#pragma unroll
+                for (int e = 0; e < E; ++e) a[e] += ws[j * NY + k] * t[k][e];
+            ste<Q, E>(D + j * sd, n0, N, a);
         }
     }
 }
@@ -242,7 +353,7 @@ __global__ __launch_bounds__(64) void k_reduce_partials(const double *partial, i
 // the accumulators fit in 128 registers: four waves per SIMD keep the 1,024
 // workgroups of a pass resident at once; at 133 registers a quarter of them ran
 // as a second round and the pass took ~1.6x)
-template <typename T, int R, bool WX>
+template <typename T, int R, bool WX, bool Q>
 __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int64_t sv, int m, int nr,
                                                     const double *y, const double *theta, const double *hd,
                                                     double *xout, T *sout, T *tout, int64_t N, double *partial) {
@@ -255,10 +366,11 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
     double rr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) rr[r] = 0;
-    // U elements per thread, blockDim apart: 2 U loads in flight per basis vector
+    // U elements per thread (consecutive in the quad form, else blockDim apart):
+    // two basis vectors' loads in flight
     constexpr int U = 4;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x * U;
-    for (int64_t n0 = int64_t(blockIdx.x) * blockDim.x * U + threadIdx.x; n0 < N; n0 += stride) {
+    using L = Lanes<Q, U>;
+    for (int64_t n0 = L::start(); n0 < N; n0 += L::stride()) {
         double x[R][U], s[R][U];
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -267,12 +379,8 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
 #pragma unroll 2
         for (int i = 0; i < m; ++i) {
             double b[U], c[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t n = n0 + int64_t(u) * blockDim.x;
-                b[u] = n < N ? double(B[i * sv + n]) : 0.0;
-                c[u] = n < N ? double(S[i * sv + n]) : 0.0;
-            }
+            lde<Q, U>(B + i * sv, n0, N, b);
+            lde<Q, U>(S + i * sv, n0, N, c);
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -281,23 +389,25 @@ __global__ __launch_bounds__(256) void k_ritz_multi(const T *B, const T *S, int6
                     s[r][u] += ys[r][i] * c[u];
                 }
         }
+        double h[U];
+        lde<Q, U>(hd, n0, N, h);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t n = n0 + int64_t(u) * blockDim.x;
-            if (n >= N) break;
-            const double h = hd[n];
+        for (int r = 0; r < R; ++r) {
+            if (r >= nr) break;
+            double t[U];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (r >= nr) break;
+            for (int u = 0; u < U; ++u) {
+                // beyond N (plain form) x = s = 0: a zero residual and correction
                 const double res = s[r][u] - th[r] * x[r][u];
                 rr[r] += res * res;
-                if (WX) {                      // the Ritz vectors and their sigma: only when asked
-                    xout[r * N + n] = x[r][u];
-                    sout[r * N + n] = T(s[r][u]);
-                }
-                double dd = th[r] - h;
+                double dd = th[r] - h[u];
                 if (fabs(dd) < 1e-8) dd = dd < 0 ? -1e-8 : 1e-8;
-                tout[r * N + n] = T(res / dd);
+                t[u] = res / dd;
+            }
+            ste<Q, U>(tout + r * N, n0, N, t);
+            if (WX) {                          // the Ritz vectors and their sigma: only when asked
+                ste<Q, U>(xout + r * N, n0, N, x[r]);
+                ste<Q, U>(sout + r * N, n0, N, s[r]);
             }
         }
     }
@@ -339,17 +449,17 @@ __global__ __launch_bounds__(256) void k_subtract(const T *X, int64_t sx, int nx
 // V_j <- sum_i q[j * m + i] V_i for j < k <= KM, in place: every thread reads
 // element n of all m vectors before it writes element n of the first k (U
 // elements per thread, blockDim apart, for more loads in flight)
-template <typename T, int KM>
+template <typename T, int KM, bool Q>
 __global__ __launch_bounds__(256) void k_combine_inplace(T *V, int64_t sv, int m, const double *q, int k, int64_t N) {
-    constexpr int U = KM <= 8 ? 4 : 2;
+    constexpr int U = Q || KM <= 8 ? 4 : 2;
+    using L = Lanes<Q, U>;
     extern __shared__ double qs[];                       // [m][KM], zero beyond k
     for (int i = threadIdx.x; i < m * KM; i += blockDim.x) {
         const int row = i / KM, j = i % KM;
         qs[i] = j < k ? q[j * m + row] : 0.0;
     }
     __syncthreads();
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x * U;
-    for (int64_t n0 = int64_t(blockIdx.x) * blockDim.x * U + threadIdx.x; n0 < N; n0 += stride) {
+    for (int64_t n0 = L::start(); n0 < N; n0 += L::stride()) {
         double acc[KM][U];
 #pragma unroll
         for (int j = 0; j < KM; ++j)
@@ -357,11 +467,7 @@ __global__ __launch_bounds__(256) void k_combine_inplace(T *V, int64_t sv, int m
             for (int u = 0; u < U; ++u) acc[j][u] = 0;
         for (int i = 0; i < m; ++i) {
             double v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t n = n0 + int64_t(u) * blockDim.x;
-                v[u] = n < N ? double(V[i * sv + n]) : 0.0;
-            }
+            lde<Q, U>(V + i * sv, n0, N, v);
 #pragma unroll
             for (int j = 0; j < KM; ++j) {
                 const double c = qs[i * KM + j];
@@ -370,27 +476,33 @@ __global__ __launch_bounds__(256) void k_combine_inplace(T *V, int64_t sv, int m
             }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t n = n0 + int64_t(u) * blockDim.x;
-            if (n >= N) break;
-#pragma unroll
-            for (int j = 0; j < KM; ++j)
-                if (j < k) V[j * sv + n] = T(acc[j][u]);
-        }
+        for (int j = 0; j < KM; ++j)
+            if (j < k) ste<Q, U>(V + j * sv, n0, N, acc[j]);
     }
 }
 
+// (the quad form for up to 8 kept vectors: 16 of them would need 128 registers of
+// accumulators for four elements)
 template <typename T>
-void launch_combine(T *V, int64_t sv, int m, const double *q, int k, int64_t N, int g, hipStream_t s) {
-    if (k <= 4)
-        hipLaunchKernelGGL((k_combine_inplace<T, 4>), dim3(g), dim3(256), size_t(m) * 4 * sizeof(double), s, V, sv,
-                           m, q, k, N);
-    else if (k <= 8)
-        hipLaunchKernelGGL((k_combine_inplace<T, 8>), dim3(g), dim3(256), size_t(m) * 8 * sizeof(double), s, V, sv,
-                           m, q, k, N);
-    else
-        hipLaunchKernelGGL((k_combine_inplace<T, kThick>), dim3(g), dim3(256), size_t(m) * kThick * sizeof(double),
-                           s, V, sv, m, q, k, N);
+void launch_combine(T *V, int64_t sv, int m, const double *q, int k, int64_t N, int g, hipStream_t s, bool quad) {
+    if (k <= 4) {
+        if (quad)
+            hipLaunchKernelGGL((k_combine_inplace<T, 4, true>), dim3(g), dim3(256), size_t(m) * 4 * sizeof(double), s,
+                               V, sv, m, q, k, N);
+        else
+            hipLaunchKernelGGL((k_combine_inplace<T, 4, false>), dim3(g), dim3(256), size_t(m) * 4 * sizeof(double), s,
+                               V, sv, m, q, k, N);
+    } else if (k <= 8) {
+        if (quad)
+            hipLaunchKernelGGL((k_combine_inplace<T, 8, true>), dim3(g), dim3(256), size_t(m) * 8 * sizeof(double), s,
+                               V, sv, m, q, k, N);
+        else
+            hipLaunchKernelGGL((k_combine_inplace<T, 8, false>), dim3(g), dim3(256), size_t(m) * 8 * sizeof(double), s,
+                               V, sv, m, q, k, N);
+    } else {
+        hipLaunchKernelGGL((k_combine_inplace<T, kThick, false>), dim3(g), dim3(256),
+                           size_t(m) * kThick * sizeof(double), s, V, sv, m, q, k, N);
+    }
 }
 
 template <typename TI, typename TO>
@@ -423,39 +535,74 @@ __global__ void k_unit2(T *x, int64_t N, int64_t i1, int64_t i2, T v) {
         x[n] = n == i1 ? v : (n == i2 ? T(1) / T(1.4142135623730951) : T(0));
 }
 
-// lexicographic (value, index) minimum strictly above (pv, pi); with parity
-// p != 0 over the sector representatives (Ia, Ib), Ia <= Ib (Ia < Ib for p = -1)
-// of the one-block vector of side nside
-// (parity != 0: only determinants with I_alpha <= I_beta, < for p = -1; one-block
-// spaces: n = I_alpha * nside + I_beta; spaces with several blocks (nside = 0):
-// the block of n from the caller-layout block offsets, then the string indices)
+// Determinants a guess may use: all, or with parity p != 0 the sector
+// representatives (Ia, Ib), Ia <= Ib (Ia < Ib for p = -1).  One-block spaces:
+// n = I_alpha * nside + I_beta; spaces with several blocks (nside = 0): the block
+// of n from the caller-layout block offsets, then the string indices.
+struct SectorArgs {
+    int64_t nside;
+    int parity;
+    const int64_t *blkoff;
+    const BlockDev *blk;
+    int nblk;
+    const int *astart, *bstart;
+};
+
+__device__ __forceinline__ bool in_sector(const SectorArgs &a, int64_t n) {
+    if (a.parity == 0) return true;
+    int64_t ra, cb;
+    if (a.nside > 0) {
+        ra = n / a.nside;
+        cb = n % a.nside;
+    } else {
+        int lo = 0, hi = a.nblk - 1;   // last block with blkoff <= n
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) / 2;
+            if (a.blkoff[mid] <= n) lo = mid; else hi = mid - 1;
+        }
+        const BlockDev &B = a.blk[lo];
+        const int64_t r = (n - a.blkoff[lo]) / B.nb, c = (n - a.blkoff[lo]) % B.nb;
+        ra = a.astart[B.ta] + r;
+        cb = a.bstart[B.tb] + c;
+    }
+    return !(ra > cb || (a.parity < 0 && ra == cb));
+}
+
+// out[i] = hd[i * N / ns]: an evenly spaced sample of the diagonal
+__global__ void k_sample(const double *hd, int64_t N, int ns, double *out) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x)
+        out[i] = hd[int64_t(i) * N / ns];
+}
+
+// every usable n with hd[n] <= t: (hd[n], n) at the next free slot of (ov, oi)
+// (cnt counts them all; at most cap are kept; the slots' order is arbitrary and the
+// caller sorts them)
+__global__ __launch_bounds__(256) void k_collect_below(const double *hd, int64_t N, double t, SectorArgs sa,
+                                                       double *ov, int64_t *oi, unsigned long long *cnt,
+                                                       int64_t cap) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
+        const double v = hd[n];
+        if (!(v <= t) || !in_sector(sa, n)) continue;
+        const unsigned long long pos = atomicAdd(cnt, 1ull);
+        if (int64_t(pos) < cap) {
+            ov[pos] = v;
+            oi[pos] = n;
+        }
+    }
+}
+
+// lexicographic (value, index) minimum strictly above (pv, pi) over the usable
+// determinants
 __global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, double pv, int64_t pi, double *ov,
-                                                int64_t *oi, int64_t nside, int parity, const int64_t *blkoff,
-                                                const BlockDev *blk, int nblk, const int *astart, const int *bstart) {
+                                                int64_t *oi, SectorArgs sa) {
     __shared__ double sv[256];
     __shared__ int64_t si[256];
     double bv = INFINITY;
     int64_t bi = -1;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; n < N; n += stride) {
-        if (parity != 0) {
-            int64_t ra, cb;
-            if (nside > 0) {
-                ra = n / nside;
-                cb = n % nside;
-            } else {
-                int lo = 0, hi = nblk - 1;   // last block with blkoff <= n
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) / 2;
-                    if (blkoff[mid] <= n) lo = mid; else hi = mid - 1;
-                }
-                const BlockDev &B = blk[lo];
-                const int64_t r = (n - blkoff[lo]) / B.nb, c = (n - blkoff[lo]) % B.nb;
-                ra = astart[B.ta] + r;
-                cb = bstart[B.tb] + c;
-            }
-            if (ra > cb || (parity < 0 && ra == cb)) continue;
-        }
+        if (!in_sector(sa, n)) continue;
         double v = hd[n];
         bool above = (v > pv) || (v == pv && n > pi);
         if (!above) continue;
@@ -482,6 +629,8 @@ __global__ __launch_bounds__(256) void k_argmin(const double *hd, int64_t N, dou
 struct Dev {
     cisigma_ctx *ctx;
     hipStream_t s;
+    bool quad = false;   // vector length a multiple of 4: the streaming kernels' quad form
+    int ncu = 0;         // compute units of the device
     double *partial = nullptr, *dvec = nullptr, *ybuf = nullptr, *qbuf = nullptr, *pval = nullptr;
     int64_t *pidx = nullptr, *pdet = nullptr;
     int grid(int64_t N) const {
@@ -498,6 +647,13 @@ struct Dev {
                                  std::string("davidson: ") + hipGetErrorString(e_));        \
     } while (0)
 
+// the quad form applies when every vector starts on 16 bytes and steps by a
+// multiple of 4 elements
+inline bool quad_ok(const Dev &d, const void *a, int64_t sa, const void *b, int64_t sb) {
+    return d.quad && (reinterpret_cast<uintptr_t>(a) & 15) == 0 && (reinterpret_cast<uintptr_t>(b) & 15) == 0 &&
+           sa % 4 == 0 && sb % 4 == 0;
+}
+
 template <typename TX, typename TY>
 hipError_t dots(Dev &d, const TX *X, int64_t sx, int nx, const TY *y, int64_t N, double *host_out) {
     int g = d.grid(N);
@@ -513,11 +669,19 @@ template <typename TX, typename TY>
 hipError_t dots_multi(Dev &d, const TX *X, int64_t sx, int nx, const TY *Y, int64_t sy, int ny, int64_t N,
                       double *host_out) {
     if (nx == 0 || ny == 0) return hipSuccess;
-    const int g = d.grid(N);
+    const bool quad = quad_ok(d, X, sx, Y, sy);
+    // the FP32 quad form runs at three waves per SIMD: three workgroups per
+    // compute unit, so that the whole grid is resident at once
+    int g = d.grid(N);
+    if (quad && sizeof(TX) == 4 && d.ncu > 0) g = std::min(g, 3 * d.ncu);
     for (int j0 = 0; j0 < ny; j0 += kMultiY) {
         const int nyc = std::min(kMultiY, ny - j0);
-        hipLaunchKernelGGL((k_dots_multi<TX, TY>), dim3(g), dim3(256), 0, d.s, X, sx, nx, Y + int64_t(j0) * sy, sy,
-                           nyc, N, d.partial);
+        if (quad)
+            hipLaunchKernelGGL((k_dots_multi<TX, TY, true>), dim3(g), dim3(256), 0, d.s, X, sx, nx,
+                               Y + int64_t(j0) * sy, sy, nyc, N, d.partial);
+        else
+            hipLaunchKernelGGL((k_dots_multi<TX, TY, false>), dim3(g), dim3(256), 0, d.s, X, sx, nx,
+                               Y + int64_t(j0) * sy, sy, nyc, N, d.partial);
         hipLaunchKernelGGL(k_reduce_partials, dim3(nx * nyc), dim3(64), 0, d.s, d.partial, g, nx * nyc,
                            d.dvec);
         hipError_t e = hipMemcpyAsync(host_out + size_t(j0) * nx, d.dvec, size_t(nx) * nyc * sizeof(double),
@@ -555,13 +719,23 @@ hipError_t subtract_gram(Dev &d, const T *X, int64_t sx, int nx, const double *h
     hipError_t e = hipSuccess;
     if (nx > 0) e = hipMemcpyAsync(d.dvec, host_c, size_t(nx) * ny * sizeof(double), hipMemcpyHostToDevice, d.s);
     if (e != hipSuccess) return e;
-    switch (ny) {
-        case 1: hipLaunchKernelGGL((k_subtract_gram<T, 1>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
-        case 2: hipLaunchKernelGGL((k_subtract_gram<T, 2>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
-        case 3: hipLaunchKernelGGL((k_subtract_gram<T, 3>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
-        case 4: hipLaunchKernelGGL((k_subtract_gram<T, 4>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, d.partial); break;
+#define CIS_SUBG(NY, Q)                                                                                     \
+    hipLaunchKernelGGL((k_subtract_gram<T, NY, Q>), dim3(g), dim3(256), 0, d.s, X, sx, nx, d.dvec, Tv, st, N, \
+                       d.partial)
+    // (quad form up to three corrections: four need 158 registers, fewer than four
+    // waves per SIMD)
+    const bool quad = ny <= 3 && quad_ok(d, X, sx, Tv, st);
+    switch (ny * 2 + (quad ? 1 : 0)) {
+        case 2: CIS_SUBG(1, false); break;
+        case 3: CIS_SUBG(1, true); break;
+        case 4: CIS_SUBG(2, false); break;
+        case 5: CIS_SUBG(2, true); break;
+        case 6: CIS_SUBG(3, false); break;
+        case 7: CIS_SUBG(3, true); break;
+        case 8: CIS_SUBG(4, false); break;
         default: return hipErrorInvalidValue;
     }
+#undef CIS_SUBG
     hipLaunchKernelGGL(k_reduce_partials, dim3(nv), dim3(64), 0, d.s, d.partial, g, nv, d.dvec);
     std::vector<double> out(nv);
     e = hipMemcpyAsync(out.data(), d.dvec, size_t(nv) * sizeof(double), hipMemcpyDeviceToHost, d.s);
@@ -583,13 +757,21 @@ hipError_t combine_new(Dev &d, const T *Tv, int64_t st, int ny, const double *ho
     const int g = d.grid(N);
     hipError_t e = hipMemcpyAsync(d.dvec, host_w, size_t(nd) * ny * sizeof(double), hipMemcpyHostToDevice, d.s);
     if (e != hipSuccess) return e;
-    switch (ny) {
-        case 1: hipLaunchKernelGGL((k_combine_new<T, 1>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
-        case 2: hipLaunchKernelGGL((k_combine_new<T, 2>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
-        case 3: hipLaunchKernelGGL((k_combine_new<T, 3>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
-        case 4: hipLaunchKernelGGL((k_combine_new<T, 4>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N); break;
+#define CIS_COMB(NY, Q) \
+    hipLaunchKernelGGL((k_combine_new<T, NY, Q>), dim3(g), dim3(256), 0, d.s, Tv, st, d.dvec, nd, D, sd, N)
+    const bool quad = quad_ok(d, Tv, st, D, sd);
+    switch (ny * 2 + (quad ? 1 : 0)) {
+        case 2: CIS_COMB(1, false); break;
+        case 3: CIS_COMB(1, true); break;
+        case 4: CIS_COMB(2, false); break;
+        case 5: CIS_COMB(2, true); break;
+        case 6: CIS_COMB(3, false); break;
+        case 7: CIS_COMB(3, true); break;
+        case 8: CIS_COMB(4, false); break;
+        case 9: CIS_COMB(4, true); break;
         default: return hipErrorInvalidValue;
     }
+#undef CIS_COMB
     return hipGetLastError();
 }
 
@@ -653,6 +835,8 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
     double rtol = ctx->resid_tol > 0 ? ctx->resid_tol : std::sqrt(tol);
     if (mixed && ctx->resid_tol <= 0) rtol = std::max(rtol, 1e-5);
     Dev d{ctx, ctx->stream};
+    d.quad = N % 4 == 0;   // every vector below is its own allocation with stride N
+    if (hipDeviceGetAttribute(&d.ncu, hipDeviceAttributeMultiprocessorCount, ctx->dev) != hipSuccess) d.ncu = 0;
     T *B = nullptr, *S = nullptr, *SX = nullptr, *TB = nullptr;
     double *X64 = nullptr, *hd = nullptr, *sig64 = nullptr;
     // free-memory check before the big allocations
@@ -701,22 +885,76 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
         double pv = -INFINITY;
         int64_t pi = -1;
         std::vector<uint32_t> sa, sb;   // strings, for the mirror determinants of sector guesses
-        std::vector<double> hv(g);
-        std::vector<int64_t> hi(g);
         const int nlow = std::max(nroots, np);
-        for (int r = 0; r < nlow; ++r) {
-            hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx, nside, par,
-                               ctx->d_blkoff, ctx->bt.blk, ctx->lay.nblk, ctx->d_tstart[0], ctx->d_tstart[1]);
-            DV_TRY(hipMemcpyAsync(hv.data(), d.dvec, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
-            DV_TRY(hipMemcpyAsync(hi.data(), d.pidx, g * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
+        const SectorArgs sec{nside, par, ctx->d_blkoff, ctx->bt.blk, ctx->lay.nblk, ctx->d_tstart[0],
+                             ctx->d_tstart[1]};
+        // the nlow usable determinants of lowest (H_II, index), in that order: every
+        // one with H_II <= t is collected for a threshold t from an evenly spaced
+        // sample of H_II, raised until at least nlow are, and sorted here (then the
+        // first nlow are exactly the lowest); one argmin pass per determinant when
+        // more than the collection buffer tie at the threshold
+        std::vector<std::pair<double, int64_t>> low;
+        {
+            const int ns = int(std::min<int64_t>(N, 16384));
+            std::vector<double> samp(ns);
+            hipLaunchKernelGGL(k_sample, dim3((ns + 255) / 256), dim3(256), 0, d.s, hd, N, ns, d.partial);
+            DV_TRY(hipMemcpyAsync(samp.data(), d.partial, ns * sizeof(double), hipMemcpyDeviceToHost, d.s));
             DV_TRY(hipStreamSynchronize(d.s));
-            double bv = INFINITY;
-            int64_t bi = -1;
-            for (int b = 0; b < g; ++b)
-                if (hi[b] >= 0 && (bi < 0 || hv[b] < bv || (hv[b] == bv && hi[b] < bi))) { bv = hv[b]; bi = hi[b]; }
-            if (bi < 0) return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: fewer determinants than roots");
-            pv = bv;
-            pi = bi;
+            std::sort(samp.begin(), samp.end());
+            // collection buffer: the first cap doubles of d.partial and the cap after them
+            const int64_t cap = int64_t(1) << 18;
+            static_assert((int64_t(1) << 19) <= int64_t(kRedBlocks) * 512 * kMultiY, "collection buffer");
+            double *cv = d.partial;
+            int64_t *ci = reinterpret_cast<int64_t *>(d.partial + cap);
+            auto *cnt = reinterpret_cast<unsigned long long *>(d.pidx);
+            int64_t k = std::max<int64_t>(1, (int64_t(nlow) * ns + N - 1) / N) + 1;   // sample rank of t
+            while (true) {
+                const double t = k > ns ? INFINITY : samp[size_t(k - 1)];
+                const unsigned long long zero = 0;
+                unsigned long long c = 0;
+                DV_TRY(hipMemcpyAsync(cnt, &zero, sizeof(zero), hipMemcpyHostToDevice, d.s));
+                hipLaunchKernelGGL(k_collect_below, dim3(g), dim3(256), 0, d.s, hd, N, t, sec, cv, ci, cnt, cap);
+                DV_TRY(hipMemcpyAsync(&c, cnt, sizeof(c), hipMemcpyDeviceToHost, d.s));
+                DV_TRY(hipStreamSynchronize(d.s));
+                if (int64_t(c) > cap) break;   // ties beyond the buffer: the argmin passes below
+                if (int64_t(c) >= nlow || k > ns) {
+                    std::vector<double> v(c);
+                    std::vector<int64_t> ix(c);
+                    if (c > 0) {
+                        DV_TRY(hipMemcpyAsync(v.data(), cv, c * sizeof(double), hipMemcpyDeviceToHost, d.s));
+                        DV_TRY(hipMemcpyAsync(ix.data(), ci, c * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
+                        DV_TRY(hipStreamSynchronize(d.s));
+                    }
+                    for (size_t i = 0; i < size_t(c); ++i) low.emplace_back(v[i], ix[i]);
+                    std::sort(low.begin(), low.end());
+                    if (low.size() > size_t(nlow)) low.resize(nlow);
+                    break;
+                }
+                k *= 4;
+            }
+        }
+        if (low.empty()) {
+            std::vector<double> hv(g);
+            std::vector<int64_t> hi(g);
+            for (int r = 0; r < nlow; ++r) {
+                hipLaunchKernelGGL(k_argmin, dim3(g), dim3(256), 0, d.s, hd, N, pv, pi, d.dvec, d.pidx, sec);
+                DV_TRY(hipMemcpyAsync(hv.data(), d.dvec, g * sizeof(double), hipMemcpyDeviceToHost, d.s));
+                DV_TRY(hipMemcpyAsync(hi.data(), d.pidx, g * sizeof(int64_t), hipMemcpyDeviceToHost, d.s));
+                DV_TRY(hipStreamSynchronize(d.s));
+                double bv = INFINITY;
+                int64_t bi = -1;
+                for (int b = 0; b < g; ++b)
+                    if (hi[b] >= 0 && (bi < 0 || hv[b] < bv || (hv[b] == bv && hi[b] < bi))) { bv = hv[b]; bi = hi[b]; }
+                if (bi < 0) break;
+                pv = bv;
+                pi = bi;
+                low.emplace_back(bv, bi);
+            }
+        }
+        if (low.size() < size_t(nlow)) return cis_set_error(ctx, CISIGMA_EINVAL, "davidson: fewer determinants than roots");
+        for (int r = 0; r < nlow; ++r) {
+            const double bv = low[size_t(r)].first;
+            const int64_t bi = low[size_t(r)].second;
             if (np > 0) {
                 pdet.push_back(bi);
                 pdiag.push_back(bv);
@@ -859,10 +1097,17 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             for (int r = 0; r < nr; ++r) yy[size_t(nr) * mm + r] = theta[r0 + r];
             hipError_t e = hipMemcpyAsync(d.ybuf, yy.data(), yy.size() * sizeof(double), hipMemcpyHostToDevice, d.s);
             if (e != hipSuccess) return e;
-#define CIS_RITZ(RR, WXX)                                                                                       \
-    hipLaunchKernelGGL((k_ritz_multi<T, RR, WXX>), dim3(g), dim3(256), 0, d.s, B, S, N, mm, nr, d.ybuf,             \
+#define CIS_RITZ1(RR, WXX, QQ)                                                                                  \
+    hipLaunchKernelGGL((k_ritz_multi<T, RR, WXX, QQ>), dim3(g), dim3(256), 0, d.s, B, S, N, mm, nr, d.ybuf,         \
                        d.ybuf + size_t(nr) * mm, hd, X64 + int64_t(r0) * N, SX + int64_t(r0) * N,                 \
                        TB + int64_t(r0) * N, N, d.partial)
+#define CIS_RITZ(RR, WXX)              \
+    do {                               \
+        if (d.quad)                    \
+            CIS_RITZ1(RR, WXX, true);  \
+        else                           \
+            CIS_RITZ1(RR, WXX, false); \
+    } while (0)
             static_assert(kRitzRoots == 4, "one instantiation per root count");
             switch (nr * 2 + (want_x ? 1 : 0)) {
                 case 2: CIS_RITZ(1, false); break;
@@ -875,6 +1120,7 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
                 default: CIS_RITZ(4, true); break;
             }
 #undef CIS_RITZ
+#undef CIS_RITZ1
             if (norms) {
                 std::vector<double> part(size_t(nr) * g);
                 e = hipMemcpyAsync(part.data(), d.partial, part.size() * sizeof(double), hipMemcpyDeviceToHost, d.s);
@@ -1038,8 +1284,8 @@ int run(cisigma_ctx *ctx, int nroots, double tol, double *energies, void *vecs, 
             }
             if (k > nroots) {
                 DV_TRY(hipMemcpyAsync(d.qbuf, Q.data(), size_t(k) * m * sizeof(double), hipMemcpyHostToDevice, d.s));
-                launch_combine<T>(B, N, m, d.qbuf, k, N, g, d.s);
-                launch_combine<T>(S, N, m, d.qbuf, k, N, g, d.s);
+                launch_combine<T>(B, N, m, d.qbuf, k, N, g, d.s, d.quad);
+                launch_combine<T>(S, N, m, d.qbuf, k, N, g, d.s, d.quad);
                 DV_TRY(hipGetLastError());
                 std::vector<double> GQ(size_t(m) * k, 0.0);
                 for (int i = 0; i < m; ++i)

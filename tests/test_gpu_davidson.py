@@ -71,7 +71,7 @@ def test_hmat_block_matches_oracle(case):
 @pytest.mark.parametrize("pspace", [64, 0], ids=["pspace64", "nopspace"])
 @pytest.mark.parametrize("thick", [1, 0], ids=["thick", "plain"])
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-def test_davidson_restarts_vs_dense(thick, prec, pspace):
+def test_davidson_thick_and_plain_restarts_vs_dense(thick, prec, pspace):
     """A subspace of 3 nroots vectors forces a collapse every iteration or two:
     thick restarts (current + previous Ritz vectors) and plain ones (current
     only) both reach the dense eigenvalues."""
@@ -166,14 +166,17 @@ def test_davidson_max_iter_gives_enoconv():
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("nroots,max_space", [(5, 15), (3, 9), (4, 12)], ids=["r5s15", "r3s9", "r4s12"])
-def test_davidson_restarts_vs_dense(prec, nroots, max_space):
-    """CAS(8,8) with a small subspace, so the thick restart runs many times:
-    5 roots keep up to 10 vectors per restart (the 16-coefficient in-place
-    combination) and take two passes of the four-root Ritz kernel; 3 and 4
-    roots keep up to 6 and 8 (the 8-coefficient combination).  Energies against
-    dense eigh of the oracle's H."""
+@pytest.mark.parametrize("space", [(8, 4, 4), (7, 4, 3)], ids=["cas8_quad", "n7a4b3_plain"])
+def test_davidson_restarts_vs_dense(prec, nroots, max_space, space):
+    """A small subspace, so the thick restart runs many times: 5 roots keep up
+    to 10 vectors per restart (the 16-coefficient in-place combination) and take
+    two passes of the four-root Ritz kernel; 3 and 4 roots keep up to 6 and 8
+    (the 8-coefficient combination).  CAS(8,8) has 4,900 determinants (the
+    vector kernels' four-element form), n7a4b3 1,225 (their plain form).
+    Energies against dense eigh of the oracle's H."""
     cis = _cis()
-    ctx, ref = make(8, 4, 4)
+    ctx, ref = make(*space)
+    assert (ctx.ndet % 4 == 0) == (space == (8, 4, 4))
     w = np.linalg.eigvalsh(ref.hmat())
     ctx.set_option(cis.OPT_MAX_SPACE, max_space)
     ctx.set_option(cis.OPT_THICK_RESTART, 1)
@@ -184,3 +187,29 @@ def test_davidson_restarts_vs_dense(prec, nroots, max_space):
     assert status == 0
     assert st["iterations"] > max_space // nroots   # at least one restart happened
     assert np.allclose(e, w[:nroots], atol=1e-8 if prec == "fp64" else 1e-6), (e - w[:nroots])
+
+
+@pytest.mark.parametrize("case", [((8, 4, 4), 16), ((7, 4, 3), 40), ((10, 5, 5), 256)],
+                         ids=["cas8_np16", "n7a4b3_np40", "cas10_np256"])
+def test_pspace_is_the_lowest_diagonal(case):
+    """The P-space is the np determinants of lowest (H_II, index), H_II as the
+    library computes it (cisigma_hdiag; n_alpha = n_beta puts pairs of equal or
+    nearly equal H_II at the boundary): after one FP64 iteration the Ritz values
+    are the lowest eigenvalues of H over exactly that set, built from the
+    oracle's matrix elements."""
+    (norb, na, nb), npp = case
+    cis = _cis()
+    ctx, ref = make(norb, na, nb, seed=2)
+    hd = torch.empty(ctx.ndet, dtype=torch.float64, device="cuda")
+    ctx.hdiag(hd)
+    torch.cuda.synchronize()
+    h = hd.cpu().numpy()
+    P = np.lexsort((np.arange(h.size), h))[:npp]
+    Hpp = np.array([[ref.h_elem(int(i), int(j)) for j in P] for i in P])
+    lam = np.linalg.eigvalsh(Hpp)
+    ctx.set_option(cis.OPT_PSPACE, npp)
+    ctx.set_option(cis.OPT_MAX_ITER, 1)
+    nroots = 3
+    e, st, status = ctx.davidson(nroots, 1e-12, allow_noconv=True)
+    assert status == cis.ENOCONV and st["iterations"] == 1
+    assert np.allclose(e, lam[:nroots], atol=1e-9, rtol=0), (e - lam[:nroots])
