@@ -427,7 +427,8 @@ int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags);
  *             kernel with the own row in a k step; 2: one-block kernel with the
  *             own row as the rank-1 start of the accumulators; 3: units of
  *             the GAS form (four waves); 4: units of a one-block space with
- *             its sigma row split, eight-wave form (FP32)
+ *             its sigma row split, eight-wave form (FP32); 5: units of the GAS
+ *             form, eight waves (FP32 with C below 4 GB)
  * shape is a host int[4], written.  EINVAL for NULL arguments or a bad dtype.
  */
 int cisigma_last_shape(const cisigma_ctx *ctx, int dtype, int *shape);

@@ -57,17 +57,23 @@ struct AbgArgs {
     const int *units;            // [nunits][8]: ta, lo, hi, act0, nact, first alpha string, first workgroup
     const uint32_t *plan;
     uint32_t plan_bytes, zero_off;   // zero_off: element index of the zero row (C may exceed 4 GB)
+    uint32_t cp_bytes;               // bytes of C with its zero row when below 4 GB, else 0
     int ld0;                         // row stride of one-block spaces (the eight-wave unit kernel)
     int block_base;                  // workgroup index of blockIdx 0 (one launch per unit: its first)
     int anexc, n, mp, ntb, nunits;   // mp: W rows (pair rows with gaps; unused rows have zero integrals)
     int nvirt;                   // the longest unit row (LDS layout)
 };
 
-template <typename T, int KS, int RB, int EW>
-__global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
+template <typename T, int KS, int RB, int EW, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
-    constexpr int RBW = (RB + 1) / 2;
+    constexpr int NT = 64 * NW;                             // threads
+    constexpr int NG = NW / 2;                              // row-block groups (x two column halves)
+    // eight waves: gathers as 32-bit byte offsets through a buffer resource (C
+    // below 4 GB), one address register per load instead of two
+    constexpr bool BUF = NW == 8;
+    constexpr int RBW = (RB + NG - 1) / NG;
     constexpr int MP = 16 * RB;
     constexpr int KP = 4 * KS;
     constexpr int PW = (EW + 1) * 64;
@@ -85,9 +91,11 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     const int ulo = uni(U[1]), uhi = uni(U[2]), ncol = uhi - ulo;
     const int Ia = uni(U[5]) + (vb - uni(U[6]));
     const int ta = p.atype[Ia], ra = Ia - p.astart[ta];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the scatter role branches per wave
     const int cb = wave & 1, grp = wave >> 1;
-    const int rb0 = grp == 0 ? 0 : RBW, nrb = grp == 0 ? RBW : RB - RBW;
+    const int rb0 = grp * RBW, nrb = RB - rb0 < RBW ? RB - rb0 : RBW;   // nrb may be <= 0
+    const bool scat = wave < 4;                            // the tile plan's four wave ranges
     const int64_t *segrow = p.seg + int64_t(ta) * p.ntb;
     const int *coff = p.coff + int64_t(ta) * p.ntb;
     // the unit's compact columns [lo, hi): the parts of the allowed blocks of ta inside them
@@ -97,10 +105,10 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         const int cnt = p.bstart[u + 1] - p.bstart[u];
         const int x0 = o > ulo ? o : ulo, x1 = o + cnt < uhi ? o + cnt : uhi;
         const T *src = p.sp + segrow[u] + int64_t(ra) * p.ld[u] - o;
-        for (int x = x0 + tid; x < x1; x += 256) sig[x - ulo] = src[x];
+        for (int x = x0 + tid; x < x1; x += NT) sig[x - ulo] = src[x];
     }
     const int *sl = p.slot + int64_t(ta) * KP;
-    for (int idx = tid; idx < KP * p.ntb; idx += 256) {
+    for (int idx = tid; idx < KP * p.ntb; idx += NT) {
         const int u = idx / KP, q = idx % KP;
         const int e = sl[q];
         int Ja = -1;
@@ -157,25 +165,37 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     if (nact > 0) {
         const __amdgpu_buffer_rsrc_t pr = buffer_of(p.plan, p.plan_bytes);
         const T *cl = p.cp + (cb * 16 + (lane & 15));   // this lane's column of the item's first column
+        const __amdgpu_buffer_rsrc_t crs = buffer_of(p.cp, BUF ? p.cp_bytes : 0u);
+        const uint32_t colo = uint32_t(cb * 16 + (lane & 15));
         const uint32_t pl = uint32_t(wave * PW + lane) * 4u;
         const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
         const uint4 *act = p.act + uni(U[3]);
-        T bc[KS], bn[KS];
-        acc_t acc[RBW], acc2[RBW];
+        T bc[KS];
+        acc_t acc[RBW];
         // gathered rows of an item for every k step: one LDS offset read each
         // (only the k steps the item multiplies: the others read the zero row anyway);
-        // 32-bit element offsets on a 64-bit base, so C may exceed 4 GB
+        // four waves: 32-bit element offsets on a 64-bit base, so C may exceed 4 GB
         auto load = [&](const uint4 &e, T (&b)[KS]) {
             const uint32_t *ro = rowoff + (e.w & 255u) * KP + (lane >> 4);
-            const T *src = cl + (e.w >> 8);
+            if constexpr (BUF) {
+                const uint32_t c0 = (e.w >> 8) + colo;
 #pragma unroll
-            for (int t = 0; t < KS; ++t) {
-                if ((e.y >> t) & 1u) b[t] = src[ro[4 * t]];
-                else b[t] = T(0);
+                for (int t = 0; t < KS; ++t) {
+                    if ((e.y >> t) & 1u) buffer_ld(b[t], crs, (ro[4 * t] + c0) * uint32_t(sizeof(T)), 0u);
+                    else b[t] = T(0);
+                }
+            } else {
+                const T *src = cl + (e.w >> 8);
+#pragma unroll
+                for (int t = 0; t < KS; ++t) {
+                    if ((e.y >> t) & 1u) b[t] = src[ro[4 * t]];
+                    else b[t] = T(0);
+                }
             }
         };
-        // two accumulators per row block (even and odd k steps): independent MFMA
-        // chains.  FP64: only the item's active k steps (a uniform branch each);
+        // one accumulator chain per row block (a second one on the odd k steps cost
+        // the registers of the eight-wave form: GAS(20,20) FP32 67.1 -> 66.1 ms
+        // without it).  FP64: only the item's active k steps (a uniform branch each);
         // FP32: the k steps in four chunks, a chunk multiplied when one of its k
         // steps is active (measured at GAS(20,20): FP64 148 ms per-step vs 159 ms
         // chunked, FP32 79 ms chunked vs 88 ms per-step)
@@ -188,14 +208,12 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
 #pragma unroll
             for (int r = 0; r < RBW; ++r) {
                 acc[r] = acc_t{0, 0, 0, 0};
-                acc2[r] = acc_t{0, 0, 0, 0};
                 if (r >= nrb || !((rm >> (rb0 + r)) & 1u)) continue;
                 if (PER_STEP) {
 #pragma unroll
                     for (int t = 0; t < KS; ++t) {
                         if (!((km >> t) & 1u)) continue;
-                        if (t & 1) acc2[r] = M::op(A[r][t], bc[t], acc2[r]);
-                        else acc[r] = M::op(A[r][t], bc[t], acc[r]);
+                        acc[r] = M::op(A[r][t], bc[t], acc[r]);
                     }
                 } else {
 #pragma unroll
@@ -205,12 +223,10 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
 #pragma unroll
                         for (int t = 0; t < KS; ++t) {
                             if (!((cm >> t) & 1u)) continue;
-                            if (t & 1) acc2[r] = M::op(A[r][t], bc[t], acc2[r]);
-                            else acc[r] = M::op(A[r][t], bc[t], acc[r]);
+                            acc[r] = M::op(A[r][t], bc[t], acc[r]);
                         }
                     }
                 }
-                acc[r] += acc2[r];
             }
         };
         auto store_w = [&](uint32_t rm) {
@@ -221,38 +237,46 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
                     for (int i = 0; i < 4; ++i)
                         W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
         };
-        // items i + 1 and i + 2 are read one iteration ahead of their use
+        // items i + 1 and i + 2 are read one iteration ahead of their use; the
+        // gathered rows of an item in one buffer, loaded in the iteration that
+        // multiplies them (a second buffer, one item ahead, cost the registers of the
+        // eight-wave form: 64.0 -> 57.5 ms without it)
         uint4 e1 = uni_ld(act + (nact > 1 ? 1 : 0)), e2 = uni_ld(act + (nact > 2 ? 2 : nact - 1));
         {
             const uint4 e0 = uni_ld(act);
             load(e0, bc);
-            load(e1, bn);
             products(e0.y, e0.z);
             store_w(e0.z);
         }
-        // act .x: plan tile | its entries per lane << 24
-        uint32_t pw_[EW], ph, nw_[EW], nh;
-        const uint32_t x0 = uni(act[0].x);
-        int pn = int(x0 >> 24), nn = 0;
-        abx_plan_load_n<EW>(pr, pl, (x0 & 0xffffffu) * (PT * 4u), pw_, ph, pn);
+        // act .x: plan tile | its entries per lane << 24.  A tile's plan words are
+        // read at the start of its own item, in flight while the next item's
+        // products run (read one item earlier they held 17 more registers:
+        // 66.1 -> 64.0 ms without them)
+        uint32_t pw_[EW], ph;
+        uint32_t xc = uni(act[0].x);
+        int pn = 0;
         __syncthreads();
         for (int i = 0; i < nact; ++i) {
             const bool more = i + 1 < nact;
             const uint4 e3 = uni_ld(act + (i + 3 < nact ? i + 3 : nact - 1));
-#pragma unroll
-            for (int t = 0; t < KS; ++t) bc[t] = bn[t];          // rows of item i + 1
-            load(e2, bn);                                        // item i + 2, in flight for a whole item
-            nn = int(e1.x >> 24);
-            abx_plan_load_n<EW>(pr, pl, (e1.x & 0xffffffu) * (PT * 4u), nw_, nh, nn);
-            products(more ? e1.y : 0u, e1.z);                    // next item's W (after the last: nothing)
-            abx_scatter_n<T, EW, TS>(W, sig, pw_, ph, spare, pn);
+            if (more) load(e1, bc);                              // rows of item i + 1
+            pn = int(xc >> 24);
+            if (scat) abx_plan_load_n<EW>(pr, pl, (xc & 0xffffffu) * (PT * 4u), pw_, ph, pn);
+            // next item's W (after the last: nothing).  Eight waves: the scatter of
+            // this item first, while the rows load (GAS(20,20) FP32 57.5 ms against
+            // 61.7 the other way round); four waves: the products first (FP64 115 ms
+            // against 121)
+            if constexpr (NW == 8) {
+                if (scat) abx_scatter_n<T, EW, TS>(W, sig, pw_, ph, spare, pn);
+                products(more ? e1.y : 0u, e1.z);
+            } else {
+                products(more ? e1.y : 0u, e1.z);
+                if (scat) abx_scatter_n<T, EW, TS>(W, sig, pw_, ph, spare, pn);
+            }
             __syncthreads();                                     // W of this item consumed
             if (more) store_w(e1.z);
             __syncthreads();
-#pragma unroll
-            for (int q = 0; q < EW; ++q) pw_[q] = nw_[q];
-            ph = nh;
-            pn = nn;
+            xc = e1.x;
             e1 = e2;
             e2 = e3;
         }
@@ -263,7 +287,7 @@ __global__ __launch_bounds__(256, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         const int cnt = p.bstart[u + 1] - p.bstart[u];
         const int x0 = o > ulo ? o : ulo, x1 = o + cnt < uhi ? o + cnt : uhi;
         T *dst = p.sp + segrow[u] + int64_t(ra) * p.ld[u] - o;
-        for (int x = x0 + tid; x < x1; x += 256) dst[x] = sig[x - ulo];
+        for (int x = x0 + tid; x < x1; x += NT) dst[x] = sig[x - ulo];
     }
 }
 
@@ -447,15 +471,26 @@ size_t abg_lds(int nvirt, int rb, int ks, int ntb) {
     return (size_t(16) * rb * kAbxWS + nvirt + 64) * sizeof(T) + size_t(4) * ks * ntb * sizeof(uint32_t);
 }
 
-template <typename T, int KS, int RB, int EW>
-hipError_t run_abg(const AbgArgs<T> &a, int na, hipStream_t s) {
+// Waves per workgroup of the GAS kernel: FP32 with C below 4 GB eight (two per
+// SIMD, each with a quarter of the W row blocks; waves 0-3 also scatter: at
+// GAS(20,20) sigma_3 72.3 -> 64.0 ms), else four (FP64: its A fragments would
+// not fit two waves per SIMD)
+template <typename T, int KS, int RB, int EW, int NW>
+hipError_t run_abg_nw(const AbgArgs<T> &a, int na, hipStream_t s) {
     const size_t lds = abg_lds<T>(a.nvirt, RB, KS, a.ntb);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_g<T, KS, RB, EW>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_g<T, KS, RB, EW, NW>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sigma_ab_g<T, KS, RB, EW>), dim3(na), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_sigma_ab_g<T, KS, RB, EW, NW>), dim3(na), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
+}
+
+template <typename T, int KS, int RB, int EW>
+hipError_t run_abg(const AbgArgs<T> &a, int na, hipStream_t s) {
+    if constexpr (sizeof(T) == 4)
+        if (a.cp_bytes != 0) return run_abg_nw<T, KS, RB, EW, 8>(a, na, s);
+    return run_abg_nw<T, KS, RB, EW, 4>(a, na, s);
 }
 
 template <typename T, int KS, int RB, int EW>
@@ -524,6 +559,7 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.plan = plan;
     a.plan_bytes = uint32_t(plb);
     a.zero_off = uint32_t(L.size);
+    a.cp_bytes = cpe * sizeof(T) < (uint64_t(1) << 32) ? uint32_t(cpe * sizeof(T)) : 0u;
     a.anexc = A.nexc;
     a.n = ctx->n;
     a.mp = 16 * G.rb;
@@ -564,7 +600,8 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
 #define CIS_RUN(K, R, E)                                                \
     if (G.ks == K && G.rb == R && G.plan[d].ew == E) {                  \
         *err = launch_units(a, [&](const AbgArgs<T> &x, int n) { return run_abg<T, K, R, E>(x, n, s); }); \
-        kshape[0] = K; kshape[1] = R; kshape[2] = E; kshape[3] = 3;     \
+        kshape[0] = K; kshape[1] = R; kshape[2] = E;                    \
+        kshape[3] = sizeof(T) == 4 && a.cp_bytes != 0 ? 5 : 3;          \
     }
     CIS_ABG_SHAPES(CIS_RUN)
 #undef CIS_RUN

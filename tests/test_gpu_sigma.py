@@ -362,8 +362,9 @@ def test_owner_units_match_oracle(case, cols, shape, dtype):
     dt = cis.FP32 if dtype == torch.float32 else cis.FP64
     assert ctx.last_path(dt) & cis.PATH_AB_OWNER
     got = ctx.last_shape(dt)
-    # FP32 one-block rows: the eight-wave unit kernel; otherwise the four-wave GAS form
-    assert got[3] == (4 if gas is None and dtype == torch.float32 else 3), got
+    # FP32 one-block rows: the eight-wave unit kernel; FP32 GAS: the eight-wave GAS
+    # form; FP64: the four-wave GAS form
+    assert got[3] == (3 if dtype == torch.float64 else 4 if gas is None else 5), got
     if shape is not None:
         assert got[:2] == shape, got
     tol = TOL64 if dtype == torch.float64 else TOL32

@@ -197,7 +197,7 @@ def test_symmetric_spaces_take_the_owner_paths(case, dtype):
     torch.cuda.synchronize()
     prec = cis.FP32 if dtype == torch.float32 else cis.FP64
     assert ctx.last_path(prec) == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
-    assert ctx.last_shape(prec)[3] == 3
+    assert ctx.last_shape(prec)[3] == (5 if dtype == torch.float32 else 3)   # GAS form: eight waves in FP32
     got = S1.double().cpu().numpy()
     assert rel(got, ref.sigma(c)) <= TOL[dtype]
     assert torch.equal(S1, S2)
