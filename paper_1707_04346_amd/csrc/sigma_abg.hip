@@ -64,6 +64,49 @@ struct AbgArgs {
     int nvirt;                   // the longest unit row (LDS layout)
 };
 
+// abx_scatter_n over the entries in chunks of CH: the W values and old sigma
+// values of one chunk in registers at a time (a lane writes each real target
+// once, at the end of its group, so a later chunk never reads a slot an earlier
+// one wrote except the lane's discard slot).  With all 16 entries' operands
+// loaded first the eight-wave FP32 form spilled 132 bytes per lane; in chunks of
+// 4, none: GAS(20,20) sigma_3 FP32 57.6 -> 52.6 ms, FP64 115.6 -> 93.8 ms (its
+// spill 552 -> 244 bytes)
+template <typename T, int EW, int TS, int CH>
+__device__ __forceinline__ void abg_scatter_ch(const T *W, T *sig, const uint32_t (&w)[EW], uint32_t hdr,
+                                               uint32_t spare, int n) {
+    const char *wb = reinterpret_cast<const char *>(W);
+    char *sb = reinterpret_cast<char *>(sig);
+    T run = 0;
+    bool any_start = (hdr & 1u) != 0;
+    uint32_t last = spare;
+#pragma unroll
+    for (int c0 = 0; c0 < EW; c0 += CH) {
+        if (c0 >= n) break;
+        T val[CH], old[CH];
+        uint32_t t[CH];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (c0 + q >= n) break;
+            t[q] = (w[c0 + q] >> 16) << TS;
+            val[q] = flip_if(*reinterpret_cast<const T *>(wb + (w[c0 + q] & 0xfffeu)), w[c0 + q]);
+            old[q] = *reinterpret_cast<const T *>(sb + t[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < CH; ++q) {
+            if (c0 + q >= n) break;
+            const bool st = c0 + q == 0 ? (hdr & 1u) != 0 : last != spare;
+            any_start = any_start || st;
+            run = st ? val[q] : run + val[q];
+            *reinterpret_cast<T *>(sb + t[q]) = old[q] + run;
+            last = t[q];
+        }
+    }
+    const T tail = last != spare ? T(0) : run;
+    const T carry = carry3<T>(tail, any_start ? 1 : 0);
+    T *d = reinterpret_cast<T *>(sb + (hdr & ~3u));
+    *d = *d + carry;
+}
+
 template <typename T, int KS, int RB, int EW, int NW>
 __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     using M = Mfma<T>;
@@ -267,11 +310,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
             // 61.7 the other way round); four waves: the products first (FP64 115 ms
             // against 121)
             if constexpr (NW == 8) {
-                if (scat) abx_scatter_n<T, EW, TS>(W, sig, pw_, ph, spare, pn);
+                if (scat) abg_scatter_ch<T, EW, TS, 4>(W, sig, pw_, ph, spare, pn);
                 products(more ? e1.y : 0u, e1.z);
             } else {
                 products(more ? e1.y : 0u, e1.z);
-                if (scat) abx_scatter_n<T, EW, TS>(W, sig, pw_, ph, spare, pn);
+                if (scat) abg_scatter_ch<T, EW, TS, 4>(W, sig, pw_, ph, spare, pn);
             }
             __syncthreads();                                     // W of this item consumed
             if (more) store_w(e1.z);
