@@ -279,7 +279,8 @@ def stored_traffic(kernel_tag):
     taken (the summary records the source's SHA-256)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1707_04346_amd", "csrc")
-    srcs = [os.path.join(csrc, f) for f in (("sigma_abx.hip", "abx.h") if kernel_tag == "k_sigma_ab_ws" else ("sigma_ab.hip",))]
+    one_block = kernel_tag in ("k_sigma_ab_ws", "k_sigma_ab_x")
+    srcs = [os.path.join(csrc, f) for f in (("sigma_abx.hip", "abx.h") if one_block else ("sigma_ab.hip",))]
     prof = os.path.join(ROOT, "profiles", f"{kernel_tag}_cas16_fp32_traffic.txt")
     if not (all(os.path.exists(f) for f in srcs) and os.path.exists(prof)):
         return None
@@ -333,7 +334,7 @@ def stored_same_spin_bytes():
     their column chunks, changed after the counters were taken."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1707_04346_amd", "csrc")
-    prof = os.path.join(ROOT, "profiles", "k_sigma_ab_ws_cas16_fp32_traffic.txt")
+    prof = os.path.join(ROOT, "profiles", "k_sigma_ab_x_cas16_fp32_traffic.txt")
     if not os.path.exists(prof):
         return None
     sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in ("sigma_ss.hip", "bufio.h", "api.hip"))).hexdigest()
@@ -558,12 +559,18 @@ def main():
     ab_s = pp32["sigma_ab"] / 1e3
     achieved = flops / ab_s / 1e12
     owner = bool(path32 & cis.PATH_AB_OWNER)
+    shared = bool(path32 & cis.PATH_AB_SHARED_CU)
+    tag = ("k_sigma_ab_x" if shared else "k_sigma_ab_ws") if owner else "k_sigma_ab"
+    kdesc = {"k_sigma_ab_x": "k_sigma_ab_x (owner-computes sigma_3, one-W-tile form, two workgroups per CU: "
+                             "gathered C rows -> FP32 MFMA on six waves over three SIMDs, LDS scatter on two "
+                             "waves on the fourth)",
+             "k_sigma_ab_ws": "k_sigma_ab_ws (owner-computes sigma_3: gathered C rows -> FP32 MFMA on six waves "
+                              "over three SIMDs, LDS scatter on two waves on the fourth)",
+             "k_sigma_ab": "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"}
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK["fp32"], "unit": "TFLOP/s",
                 "frac": achieved / PEAK["fp32"],
-                "traffic": stored_traffic("k_sigma_ab_ws" if owner else "k_sigma_ab") if args.workload == "cas16" else None,
-                "kernel": ("k_sigma_ab_ws (owner-computes sigma_3: gathered C rows -> FP32 MFMA on six waves over "
-                           "three SIMDs, LDS scatter on two waves on the fourth)" if owner
-                           else "k_sigma_ab (sigma_3 gather -> FP32 MFMA -> atomic scatter)"),
+                "traffic": stored_traffic(tag) if args.workload == "cas16" else None,
+                "kernel": kdesc[tag],
                 "flops_per_launch": flops,
                 "flops_definition": "sparse minimum: 2 x sum over determinants of (alpha single excitations incl. "
                                     "E_kk) x (beta single excitations incl. E_kk) with the source determinant in "

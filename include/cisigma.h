@@ -414,6 +414,8 @@ int cisigma_pass_times(cisigma_ctx *ctx, double *ms, int *ncalls);
  */
 #define CISIGMA_PATH_AB_OWNER 1          /* sigma_3 by the owner-computes kernel (no global atomics) */
 #define CISIGMA_PATH_SS_MATERIALISED 2   /* same-spin parts by materialised pair products + gather */
+#define CISIGMA_PATH_AB_SHARED_CU 4      /* sigma_3 by the one-block owner kernel in its one-W-tile form, two
+                                            workgroups per compute unit (FP32, where two fit) */
 int cisigma_last_path(const cisigma_ctx *ctx, int dtype, int *flags);
 
 /*

@@ -106,7 +106,7 @@ EXPORTS = ["cisigma_init", "cisigma_free", "cisigma_ndet", "cisigma_layout", "ci
            "cisigma_pass_times", "cisigma_last_path", "cisigma_last_error", "cisigma_strerror", "cisigma_rdm",
            "cisigma_hmat_block", "cisigma_autotune", "cisigma_last_shape",
            "cisigma_apply_noalloc", "cisigma_set_log", "cisigma_init_sym"]
-PATH_AB_OWNER, PATH_SS_MATERIALISED = 1, 2
+PATH_AB_OWNER, PATH_SS_MATERIALISED, PATH_AB_SHARED_CU = 1, 2, 4
 
 
 class CisigmaError(RuntimeError):

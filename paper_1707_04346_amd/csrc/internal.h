@@ -255,6 +255,7 @@ struct cisigma_ctx {
     int log_calls = 0;             // Davidson calls logged so far
     int last_path[2] = {0, 0};     // CISIGMA_PATH_* flags of the last apply, [FP64, FP32]
     int last_shape[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};   // owner-computes sigma_3 shape of the last apply
+    int abx_shared[2] = {0, 0};    // the one-block owner kernel last ran two workgroups per CU, [FP64, FP32]
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
     int ab_mode = 0;               // CISIGMA_OPT_SIGMA_PATH
     int unit_cols = 0;             // CISIGMA_OPT_UNIT_COLS (0: what the LDS holds)

@@ -340,9 +340,13 @@ hipError_t sigma_ab_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStrea
         // one-block spaces: the one-block owner kernel when its sigma row fits (unless
         // path 2 asks for the units), else the GAS owner kernel (which splits long rows
         // over units), else the general kernel
-        if ((ctx->cas && ctx->ab_mode != 2 && launch_sigma_ab_owner(ctx, cp, sp, dt, s, &e)) ||
-            launch_sigma_ab_gas(ctx, cp, sp, dt, s, &e)) {
-            if (e == hipSuccess) const_cast<cisigma_ctx *>(ctx)->last_path[sizeof(T) == 4] |= CISIGMA_PATH_AB_OWNER;
+        const bool one = ctx->cas && ctx->ab_mode != 2 && launch_sigma_ab_owner(ctx, cp, sp, dt, s, &e);
+        if (one || launch_sigma_ab_gas(ctx, cp, sp, dt, s, &e)) {
+            if (e == hipSuccess) {
+                int &f = const_cast<cisigma_ctx *>(ctx)->last_path[sizeof(T) == 4];
+                f |= CISIGMA_PATH_AB_OWNER;
+                if (one && ctx->abx_shared[sizeof(T) == 4]) f |= CISIGMA_PATH_AB_SHARED_CU;
+            }
             return e;
         }
     }

@@ -171,12 +171,15 @@ __device__ __forceinline__ void abx_store_w(T *W, const typename Mfma<T>::acc_t 
                 W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
 }
 
-// ---- eight-wave form with one W buffer (FP64) ------------------------------------
+// ---- eight-wave form with one W buffer (FP64; FP32 where two fit per CU) ---------
 //
-// The roles are split by SIMD as in the FP32 form below (waves 3 and 7 scatter,
-// the other six multiply), but the FP64 sigma row leaves room for one W tile
-// only: the producing waves compute the next tile's W in registers while the
-// scatter waves consume this tile's, and store it between two barriers.
+// The roles are split by SIMD as in the two-buffer form below (waves 3 and 7
+// scatter, the other six multiply), but with one W tile: the producing waves
+// compute the next tile's W in registers while the scatter waves consume this
+// tile's, and store it between two barriers.  The FP64 sigma row leaves room for
+// no second tile; in FP32 the smaller LDS lets two workgroups share a compute
+// unit (CAS(16,16): 71 KB each, 118 registers), so one workgroup's matrix waves
+// issue while the other's wait at a barrier.
 template <typename T, int KS, int RB, int EW, bool SELF>
 __global__ __launch_bounds__(512, 1) void k_sigma_ab_x(AbxArgs<T> p) {
     using acc_t = typename Mfma<T>::acc_t;
@@ -352,29 +355,41 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_ws(AbxArgs<T> p) {
         *reinterpret_cast<vec_t *>(p.sp + rowoff + cc) = *reinterpret_cast<const vec_t *>(sig + cc);
 }
 
-// LDS bytes: the W tile (two for the eight-wave FP32 form) and the sigma row
-// with its 64 discard slots
+// LDS bytes: nw W tiles and the sigma row with its 64 discard slots
 template <typename T>
-size_t abx_lds(int ld, int rb) {
-    const size_t nw = sizeof(T) == 4 ? 2 : 1;
-    return (nw * 16 * rb * kAbxWS + ld + 64) * sizeof(T);
+size_t abx_lds(int ld, int rb, int nw) {
+    return (size_t(nw) * 16 * rb * kAbxWS + ld + 64) * sizeof(T);
 }
 
+// FP32: the one-W-tile form when two of its workgroups fit on a compute unit
+// (registers and LDS, as the runtime's occupancy query reports them): while
+// one workgroup waits at a barrier the other's matrix waves issue (CAS(16,16)
+// sigma_3 34.6 -> 32.1 ms against the two-W-tile form, which fits one per CU);
+// otherwise the two-W-tile form.  FP64: one W tile (its row leaves room for no
+// more).  *shared: the one-W-tile form ran two workgroups per CU.
 template <typename T, int KS, int RB, int EW, bool SELF>
-hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s) {
-    const size_t lds = abx_lds<T>(a.ld, RB);
-    if (lds > 160 * 1024 || 16 * RB < a.npair || 4 * KS < a.anexc + (SELF ? 1 : 0)) return hipErrorInvalidValue;
+hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s, int *shared) {
+    *shared = 0;
+    const size_t lds1 = abx_lds<T>(a.ld, RB, 1);
+    if (lds1 > 160 * 1024 || 16 * RB < a.npair || 4 * KS < a.anexc + (SELF ? 1 : 0)) return hipErrorInvalidValue;
+    const void *kx = reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RB, EW, SELF>);
+    hipError_t e = hipFuncSetAttribute(kx, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds1));
+    if (e != hipSuccess) return e;
     if constexpr (sizeof(T) == 4) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_ws<T, KS, RB, EW, SELF>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        int per_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kx, 512, lds1);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_sigma_ab_ws<T, KS, RB, EW, SELF>), dim3(a.Na), dim3(512), lds, s, a);
-    } else {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_x<T, KS, RB, EW, SELF>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW, SELF>), dim3(a.Na), dim3(512), lds, s, a);
+        const size_t lds2 = abx_lds<T>(a.ld, RB, 2);
+        if (per_cu < 2 && lds2 <= 160 * 1024) {
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_ws<T, KS, RB, EW, SELF>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds2));
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_sigma_ab_ws<T, KS, RB, EW, SELF>), dim3(a.Na), dim3(512), lds2, s, a);
+            return hipGetLastError();
+        }
+        *shared = per_cu >= 2 ? 1 : 0;
     }
+    hipLaunchKernelGGL((k_sigma_ab_x<T, KS, RB, EW, SELF>), dim3(a.Na), dim3(512), lds1, s, a);
     return hipGetLastError();
 }
 
@@ -407,15 +422,15 @@ int width_for(int ks, int rb, int need) {
     return best;
 }
 
-// shape[4] receives {KS, RB, EW, 1: row in a k step, 2: rank-1 start}
+// shape[4] receives {KS, RB, EW, 1: row in a k step, 2: rank-1 start}; *shared as run_abx
 template <typename T>
-bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, int *shape) {
+bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, int *shape, int *shared) {
     const int rb = rb_of(a.npair);
     if (a.anexc > 0 && a.anexc % 4 == 0) {
         const int ks1 = a.anexc / 4;
 #define CIS_RUN1(K, R, E)                                           \
     if (ks1 == K && rb == R && ew == E) {                           \
-        *err = run_abx<T, K, R, E, false>(a, s);                    \
+        *err = run_abx<T, K, R, E, false>(a, s, shared);            \
         shape[0] = K; shape[1] = R; shape[2] = E; shape[3] = 2;     \
         return true;                                                \
     }
@@ -425,7 +440,7 @@ bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, i
     const int ks = ks_of(a.anexc);
 #define CIS_RUN(K, R, E)                                            \
     if (ks == K && rb == R && ew == E) {                            \
-        *err = run_abx<T, K, R, E, true>(a, s);                     \
+        *err = run_abx<T, K, R, E, true>(a, s, shared);             \
         shape[0] = K; shape[1] = R; shape[2] = E; shape[3] = 1;     \
         return true;                                                \
     }
@@ -454,14 +469,15 @@ bool owner_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hi
     x.npair = ctx->npair;
     x.Na = A.nstr;
     x.ld = ctx->pl[0].ld[0];
-    if (abx_lds<T>(x.ld, rb_of(x.npair)) > 160 * 1024) return false;
+    if (abx_lds<T>(x.ld, rb_of(x.npair), 1) > 160 * 1024) return false;
     // 32-bit byte offsets of the gathered rows (the zero row Na included) and of the plan
     const uint64_t cpb = (uint64_t(x.Na) + 1) * uint64_t(x.ld) * sizeof(T);
     const uint64_t plb = uint64_t(P.ntile) * 4 * (P.ew + 1) * 64 * sizeof(uint32_t);
     if (cpb >= (uint64_t(1) << 31) || plb >= (uint64_t(1) << 31)) return false;
     x.cp_bytes = uint32_t(cpb);
     x.plan_bytes = uint32_t(plb);
-    return dispatch_abx<T>(x, P.ew, s, err, const_cast<cisigma_ctx *>(ctx)->last_shape[sizeof(T) == 4]);
+    auto *c = const_cast<cisigma_ctx *>(ctx);
+    return dispatch_abx<T>(x, P.ew, s, err, c->last_shape[sizeof(T) == 4], &c->abx_shared[sizeof(T) == 4]);
 }
 
 }  // namespace
