@@ -77,7 +77,10 @@ extern "C" {
 #define CISIGMA_OPT_PROFILE 7      /* nonzero: time every pass of cisigma_apply with HIP events (resets the totals) */
 #define CISIGMA_OPT_SIGMA_PATH 8   /* 0: automatic kernel choice; 1: only the general (scatter-atomic) kernels;
                                       2: for one-block spaces, the owner-computes units of the GAS form
-                                      in place of the one-block owner kernel (rebuilds the unit tables) */
+                                      in place of the one-block owner kernel (rebuilds the unit tables);
+                                      3: as 0, but the one-block owner kernel in FP32 in its two-W-tile
+                                      form (one workgroup per compute unit) even where two workgroups of
+                                      the one-W-tile form would fit */
 #define CISIGMA_OPT_UNIT_LAUNCH 19 /* owner-computes units: 0 (default) one launch over every unit, longest
                                       rows of work first; 1: one launch per unit, in the same order (the
                                       per-block launch baseline) */

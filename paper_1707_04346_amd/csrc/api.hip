@@ -2014,8 +2014,8 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             return CISIGMA_OK;
         case CISIGMA_OPT_SIGMA_PATH: {
             cis::drop_graphs(ctx);
-            if (value != 0 && value != 1 && value != 2)
-                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0, 1 or 2");
+            if (value < 0 || value > 3)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: sigma path must be 0, 1, 2 or 3");
             const bool rebuild = ctx->cas && (value == 2) != (ctx->ab_mode == 2);
             ctx->ab_mode = int(value);
             return rebuild ? cis::rebuild_gas_owner(ctx) : CISIGMA_OK;

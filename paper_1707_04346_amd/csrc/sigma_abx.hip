@@ -366,9 +366,10 @@ size_t abx_lds(int ld, int rb, int nw) {
 // one workgroup waits at a barrier the other's matrix waves issue (CAS(16,16)
 // sigma_3 34.6 -> 32.1 ms against the two-W-tile form, which fits one per CU);
 // otherwise the two-W-tile form.  FP64: one W tile (its row leaves room for no
-// more).  *shared: the one-W-tile form ran two workgroups per CU.
+// more).  *shared: the one-W-tile form ran two workgroups per CU.  two_w: the
+// two-W-tile form in FP32 wherever it fits (CISIGMA_OPT_SIGMA_PATH = 3).
 template <typename T, int KS, int RB, int EW, bool SELF>
-hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s, int *shared) {
+hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s, int *shared, bool two_w) {
     *shared = 0;
     const size_t lds1 = abx_lds<T>(a.ld, RB, 1);
     if (lds1 > 160 * 1024 || 16 * RB < a.npair || 4 * KS < a.anexc + (SELF ? 1 : 0)) return hipErrorInvalidValue;
@@ -380,7 +381,7 @@ hipError_t run_abx(const AbxArgs<T> &a, hipStream_t s, int *shared) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kx, 512, lds1);
         if (e != hipSuccess) return e;
         const size_t lds2 = abx_lds<T>(a.ld, RB, 2);
-        if (per_cu < 2 && lds2 <= 160 * 1024) {
+        if ((per_cu < 2 || two_w) && lds2 <= 160 * 1024) {
             e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_ws<T, KS, RB, EW, SELF>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds2));
             if (e != hipSuccess) return e;
@@ -422,15 +423,16 @@ int width_for(int ks, int rb, int need) {
     return best;
 }
 
-// shape[4] receives {KS, RB, EW, 1: row in a k step, 2: rank-1 start}; *shared as run_abx
+// shape[4] receives {KS, RB, EW, 1: row in a k step, 2: rank-1 start}; *shared, two_w as run_abx
 template <typename T>
-bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, int *shape, int *shared) {
+bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, int *shape, int *shared,
+                  bool two_w) {
     const int rb = rb_of(a.npair);
     if (a.anexc > 0 && a.anexc % 4 == 0) {
         const int ks1 = a.anexc / 4;
 #define CIS_RUN1(K, R, E)                                           \
     if (ks1 == K && rb == R && ew == E) {                           \
-        *err = run_abx<T, K, R, E, false>(a, s, shared);            \
+        *err = run_abx<T, K, R, E, false>(a, s, shared, two_w);     \
         shape[0] = K; shape[1] = R; shape[2] = E; shape[3] = 2;     \
         return true;                                                \
     }
@@ -440,7 +442,7 @@ bool dispatch_abx(const AbxArgs<T> &a, int ew, hipStream_t s, hipError_t *err, i
     const int ks = ks_of(a.anexc);
 #define CIS_RUN(K, R, E)                                            \
     if (ks == K && rb == R && ew == E) {                            \
-        *err = run_abx<T, K, R, E, true>(a, s, shared);             \
+        *err = run_abx<T, K, R, E, true>(a, s, shared, two_w);      \
         shape[0] = K; shape[1] = R; shape[2] = E; shape[3] = 1;     \
         return true;                                                \
     }
@@ -477,7 +479,8 @@ bool owner_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hi
     x.cp_bytes = uint32_t(cpb);
     x.plan_bytes = uint32_t(plb);
     auto *c = const_cast<cisigma_ctx *>(ctx);
-    return dispatch_abx<T>(x, P.ew, s, err, c->last_shape[sizeof(T) == 4], &c->abx_shared[sizeof(T) == 4]);
+    return dispatch_abx<T>(x, P.ew, s, err, c->last_shape[sizeof(T) == 4], &c->abx_shared[sizeof(T) == 4],
+                           ctx->ab_mode == 3);
 }
 
 }  // namespace

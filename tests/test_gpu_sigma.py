@@ -380,8 +380,34 @@ def test_unit_cols_option_rejects_bad_values():
     for bad in (-1, 1, 63, 70000, 100.5):
         with pytest.raises(Exception):
             ctx.set_option(cis.OPT_UNIT_COLS, bad)
-    with pytest.raises(Exception):
-        ctx.set_option(cis.OPT_SIGMA_PATH, 3)
+    for bad in (-1, 4):
+        with pytest.raises(Exception):
+            ctx.set_option(cis.OPT_SIGMA_PATH, bad)
+
+
+@pytest.mark.parametrize("case", [(10, 5, 5), (12, 6, 6), (9, 5, 4)], ids=["cas10", "cas12", "n9a5b4"])
+def test_one_block_two_w_form_matches_oracle(case):
+    """FP32 one-block sigma_3 in both forms: by default the one-W-tile kernel with
+    two workgroups per compute unit (PATH_AB_SHARED_CU); with CISIGMA_OPT_SIGMA_PATH
+    = 3 the double-buffered two-W-tile kernel, one workgroup per CU (the form the
+    shapes whose registers leave room for one workgroup take).  Both against the
+    oracle's sigma, each repeating bit for bit."""
+    cis = _cis()
+    norb, na, nb = case
+    ctx, ref = make(norb, na, nb, seed=29)
+    c = si.ci_vector(ctx.ndet, 30)
+    want = ref.sigma(c)
+    s1 = gpu_sigma(ctx, c, torch.float32)
+    assert ctx.last_path(cis.FP32) == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED | cis.PATH_AB_SHARED_CU
+    ctx.set_option(cis.OPT_SIGMA_PATH, 3)
+    s2 = gpu_sigma(ctx, c, torch.float32)
+    assert ctx.last_path(cis.FP32) == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
+    assert ctx.last_shape(cis.FP32)[3] in (1, 2)
+    assert rel(s1, want) <= TOL32 and rel(s2, want) <= TOL32
+    assert np.array_equal(gpu_sigma(ctx, c, torch.float32), s2)
+    s64 = gpu_sigma(ctx, c, torch.float64)   # FP64 has one form: path 3 changes nothing there
+    assert ctx.last_path(cis.FP64) == cis.PATH_AB_OWNER | cis.PATH_SS_MATERIALISED
+    assert rel(s64, want) <= TOL64
 
 
 @pytest.mark.parametrize("case,cols", [((7, 3, 3, ([2, 3, 2], [3, 5, 6], [4, 6, 6])), 0), ((10, 5, 5, None), 64)],
