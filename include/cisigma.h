@@ -105,8 +105,11 @@ extern "C" {
                                       alpha-beta pass */
 #define CISIGMA_OPT_GAS_UNIT_ORDER 16 /* launch order of the GAS owner-computes units (both precisions):
                                       0 (default) most source tiles per row first, 1 alpha-type order,
-                                      2 most total work first, 3 heavy and light alternating; set by
-                                      cisigma_autotune per precision */
+                                      2 most total work first, 3 heavy and light alternating, 4 heaviest
+                                      first by the batch weight sum_j c_j l_j of Sec. 3.1 Eq. 10, 5 by
+                                      (sum_j c_j) N_blocks of Eq. 11 (a unit as the batch, its blocks'
+                                      connections c_j and determinants l_j); set by cisigma_autotune per
+                                      precision */
 #define CISIGMA_OPT_SS_SPLIT 17     /* column split of the grid of the same-spin pair-product kernel of
                                       spaces with several types (GAS or point-group symmetry; row-store
                                       or atomic form), 1..64; 0 (default): a heuristic; set by

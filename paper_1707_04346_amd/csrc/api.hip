@@ -1314,6 +1314,51 @@ int gas_set_unit_order(cisigma_ctx *c, int d, int order) {
     std::vector<size_t> ord(nu);
     for (size_t k = 0; k < nu; ++k) ord[k] = k;
     auto work = [&](size_t k) { return double(U[k].nact) * A.tcount[U[k].ta]; };
+    // The paper's batch weights (Sec. 3.1) with a unit as the batch and its allowed
+    // (alpha type, beta type) blocks, restricted to the unit's columns, as the
+    // batch's blocks: l_j the determinants of block j in the unit, c_j its
+    // connections -- the allowed blocks (ta', tb') with ta' and tb' one excitation
+    // away from its types (GAS occupations that differ by at most one electron
+    // moved between spaces) -- a = sum_j c_j l_j (Eq. 10), b = (sum_j c_j) N_blocks
+    // (Eq. 11).
+    std::vector<double> wa(nu, 0.0), wb(nu, 0.0);
+    if (order == 4 || order == 5) {
+        const auto &B = c->sp[1];
+        const int nta = A.ntype, ntb = B.ntype, ng = c->gas.ngas;
+        auto near = [&](const std::vector<int> &occ, int t, int u) {
+            int dist = 0;
+            for (int g = 0; g < ng; ++g) dist += std::abs(occ[size_t(t) * ng + g] - occ[size_t(u) * ng + g]);
+            return dist <= 2;
+        };
+        auto allowed = [&](int ta, int tb) { return c->lay.boff[size_t(ta) * ntb + tb] >= 0; };
+        std::vector<double> conn(size_t(nta) * ntb, 0.0);
+        for (int ta = 0; ta < nta; ++ta)
+            for (int tb = 0; tb < ntb; ++tb) {
+                if (!allowed(ta, tb)) continue;
+                int cnt = 0;
+                for (int ua = 0; ua < nta; ++ua)
+                    for (int ub = 0; ub < ntb; ++ub)
+                        if (allowed(ua, ub) && near(A.tocc, ta, ua) && near(B.tocc, tb, ub)) ++cnt;
+                conn[size_t(ta) * ntb + tb] = cnt;
+            }
+        for (size_t k = 0; k < nu; ++k) {
+            const int ta = U[k].ta;
+            int col = 0, nblocks = 0;   // compact columns of ta: its allowed blocks in beta-type order
+            double sum_cl = 0, sum_c = 0;
+            for (int tb = 0; tb < ntb; ++tb) {
+                if (!allowed(ta, tb)) continue;
+                const int x0 = std::max(col, U[k].lo), x1 = std::min(col + B.tcount[tb], U[k].hi);
+                col += B.tcount[tb];
+                if (x1 <= x0) continue;
+                const double cj = conn[size_t(ta) * ntb + tb];
+                sum_cl += cj * double(A.tcount[ta]) * double(x1 - x0);
+                sum_c += cj;
+                ++nblocks;
+            }
+            wa[k] = sum_cl;
+            wb[k] = sum_c * nblocks;
+        }
+    }
     if (order == 1) {
         std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
             return U[x].ta != U[y].ta ? U[x].ta < U[y].ta : U[x].lo < U[y].lo;
@@ -1328,6 +1373,9 @@ int gas_set_unit_order(cisigma_ctx *c, int d, int order) {
             }
             ord.swap(alt);
         }
+    } else if (order == 4 || order == 5) {
+        const auto &w = order == 4 ? wa : wb;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t x, size_t y) { return w[x] > w[y]; });
     }
     std::vector<int> utab;
     int nblk = 0;
@@ -1918,7 +1966,7 @@ CIS_API int cisigma_autotune(cisigma_ctx *ctx, int dtype, int reps, char *report
     if (!ctx->go.units[d].empty()) {
         int best = ctx->unit_order[d];
         float best_ms = 0;
-        for (int order = 0; order < 4; ++order) {
+        for (int order = 0; order < 6; ++order) {
             int rc = cis::gas_set_unit_order(ctx, d, order);
             float ms = 0;
             if (rc == 0) rc = time_apply(&ms);
@@ -2037,7 +2085,7 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             ctx->ss_chunk = int(value);
             return CISIGMA_OK;
         case CISIGMA_OPT_GAS_UNIT_ORDER: {
-            if (value < 0 || value > 3) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit order out of range");
+            if (value < 0 || value > 5) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit order out of range");
             int rc = cis::gas_set_unit_order(ctx, 0, int(value));
             if (rc == CISIGMA_OK) rc = cis::gas_set_unit_order(ctx, 1, int(value));
             return rc;

@@ -41,14 +41,21 @@ def test_knobs_keep_sigma(case, dtype):
     ref = oracle.Space(norb, na, nb, h, g, gas=gas)
     c = si.ci_vector(ctx.ndet, 5)
     want = ref.sigma(c)
-    for order in range(4):
+    # unit launch orders 0-5 (4, 5: the batch weights of Sec. 3.1 Eqs. 10 and 11):
+    # only the order of independent workgroups changes, so sigma is the same bit for bit
+    first = None
+    for order in range(6):
         ctx.set_option(cis.OPT_GAS_UNIT_ORDER, order)
-        assert rel(sigma(ctx, c, dtype), want) <= TOL[dtype], order
+        got = sigma(ctx, c, dtype)
+        assert rel(got, want) <= TOL[dtype], order
+        if first is None:
+            first = got
+        assert np.array_equal(got, first), order
     for split in (1, 3, 16, 0):
         ctx.set_option(cis.OPT_SS_SPLIT, split)
         assert rel(sigma(ctx, c, dtype), want) <= TOL[dtype], split
     with pytest.raises(cis.CisigmaError):
-        ctx.set_option(cis.OPT_GAS_UNIT_ORDER, 4)
+        ctx.set_option(cis.OPT_GAS_UNIT_ORDER, 6)
 
 
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
