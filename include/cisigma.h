@@ -84,6 +84,13 @@ extern "C" {
 #define CISIGMA_OPT_UNIT_LAUNCH 19 /* owner-computes units: 0 (default) one launch over every unit, longest
                                       rows of work first; 1: one launch per unit, in the same order (the
                                       per-block launch baseline) */
+#define CISIGMA_OPT_DETERMINISTIC 20 /* 1: cisigma_apply (and the Davidson's sigma builds) use only kernels
+                                      without floating-point atomics, whose results repeat bit for bit;
+                                      an apply that would need a float-atomic kernel (shapes outside the
+                                      owner-computes and stored-row kernels, stored rows that do not fit
+                                      in memory, CISIGMA_OPT_SIGMA_PATH = 1) fails with
+                                      CISIGMA_EUNSUPPORTED instead; the sigma output is then not written.
+                                      0 (default): such applies run the atomic kernels */
 #define CISIGMA_OPT_UNIT_COLS 18   /* owner-computes units (GAS spaces, one-block spaces whose sigma row is
                                       longer than the LDS, or path 2): at most this many sigma columns per
                                       unit, 64..65536; 0 (default): as many as the LDS holds.  Rows are cut

@@ -28,6 +28,7 @@ OPT_LOW_MEMORY = 15
 OPT_GAS_UNIT_ORDER = 16
 OPT_SS_SPLIT = 17
 OPT_UNIT_COLS = 18
+OPT_DETERMINISTIC = 20
 OPT_UNIT_LAUNCH = 19
 
 if not os.path.exists(LIB_PATH):

@@ -1192,6 +1192,10 @@ int apply_sigma_ws(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStr
                    bool own) {
     // one-type spins with room for the materialised same-spin rows avoid global atomics there
     const bool mat = c->ab_mode != 1 && W.ys != nullptr;   // W.ys only where the form applies
+    if (c->deterministic && !mat)
+        return cis_set_error(c, CISIGMA_EUNSUPPORTED,
+                             "apply: deterministic mode: the same-spin parts of this space would need the "
+                             "float-atomic kernel (no stored pair-product rows for it)");
     hipEvent_t ev[CISIGMA_NPASS + 1];
     const bool prof = own && c->profile;
     if (prof) {
@@ -1236,7 +1240,14 @@ int apply_sigma_ws(cisigma_ctx *c, const void *C, void *sigma, int dtype, hipStr
                     "apply: sigma_1 (beta-beta)");
         HIP_OR_FAIL(c, hipEventRecord(c->ev_join, c->side), "apply: join");
     }
-    HIP_OR_FAIL(c, launch_sigma_ab(c, W.cp, W.sp, dtype, s), "apply: sigma_3 (alpha-beta)");
+    {
+        const hipError_t e = launch_sigma_ab(c, W.cp, W.sp, dtype, s);
+        if (e == hipErrorNotSupported && c->deterministic)
+            return cis_set_error(c, CISIGMA_EUNSUPPORTED,
+                                 "apply: deterministic mode: sigma_3 of this space would need the float-atomic "
+                                 "general kernel (no owner-computes kernel covers it)");
+        HIP_OR_FAIL(c, e, "apply: sigma_3 (alpha-beta)");
+    }
     HIP_OR_FAIL(c, mark(CISIGMA_PASS_SIGMA_AB), "apply: profiling events");
     if (fork)
         HIP_OR_FAIL(c, hipStreamWaitEvent(s, c->ev_join, 0), "apply: join");
@@ -2068,6 +2079,11 @@ CIS_API int cisigma_set_option(cisigma_ctx *ctx, int key, double value) {
             ctx->ab_mode = int(value);
             return rebuild ? cis::rebuild_gas_owner(ctx) : CISIGMA_OK;
         }
+        case CISIGMA_OPT_DETERMINISTIC:
+            if (value != 0 && value != 1)
+                return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: deterministic must be 0 or 1");
+            ctx->deterministic = int(value);
+            return CISIGMA_OK;
         case CISIGMA_OPT_UNIT_LAUNCH:
             if (value != 0 && value != 1) return cis_set_error(ctx, CISIGMA_EINVAL, "set_option: unit launch must be 0 or 1");
             cis::drop_graphs(ctx);

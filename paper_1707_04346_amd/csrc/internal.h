@@ -258,6 +258,7 @@ struct cisigma_ctx {
     int abx_shared[2] = {0, 0};    // the one-block owner kernel last ran two workgroups per CU, [FP64, FP32]
     // kernel choice: 0 automatic, 1 the general scatter-atomic kernels only (CISIGMA_OPT_SIGMA_PATH)
     int ab_mode = 0;               // CISIGMA_OPT_SIGMA_PATH
+    int deterministic = 0;         // CISIGMA_OPT_DETERMINISTIC
     int unit_cols = 0;             // CISIGMA_OPT_UNIT_COLS (0: what the LDS holds)
     int unit_launch = 0;           // CISIGMA_OPT_UNIT_LAUNCH (0: one launch over all units, 1: one per unit)
     int ss_chunk = 0;      // cap on the materialised same-spin column chunk (0: none)

@@ -350,6 +350,8 @@ hipError_t sigma_ab_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStrea
             return e;
         }
     }
+    // the general kernel accumulates with float atomics: refused in deterministic mode
+    if (ctx->deterministic) return hipErrorNotSupported;
     const int mb = (A.nexc + 15) / 16;   // 16-row blocks of alpha excitations
     if (ks > 0 && ks * 4 == ctx->kp && mb <= 8) {
         if (mb <= 4) return dispatch_ks<T, 1>(a, s, ks);

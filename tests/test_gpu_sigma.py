@@ -434,3 +434,52 @@ def test_one_launch_per_unit_is_the_same_sigma(case, cols, dtype):
     with pytest.raises(Exception):
         ctx.set_option(cis.OPT_UNIT_LAUNCH, 2)
 
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["fp64", "fp32"])
+def test_deterministic_mode(dtype):
+    """CISIGMA_OPT_DETERMINISTIC = 1: spaces the atomic-free kernels cover give the
+    same sigma as before, bit for bit, and a converged Davidson; an apply that
+    would need a float-atomic kernel is refused (EUNSUPPORTED) and leaves the
+    output untouched -- sigma_3 forced onto the general kernel (SIGMA_PATH = 1),
+    and a space without stored same-spin rows (one-block, 15 orbitals, 2 beta
+    electrons: its same-spin passes take the atomic kernel)."""
+    cis = _cis()
+    ctx, ref = make(8, 4, 4, seed=31)
+    c = si.ci_vector(ctx.ndet, 32)
+    plain = gpu_sigma(ctx, c, dtype)
+    ctx.set_option(cis.OPT_DETERMINISTIC, 1)
+    det = gpu_sigma(ctx, c, dtype)
+    assert np.array_equal(det, plain)
+    assert rel(det, ref.sigma(c)) <= (TOL64 if dtype == torch.float64 else TOL32)
+    if dtype == torch.float64:
+        w = np.linalg.eigvalsh(ref.hmat())
+        e, st, status = ctx.davidson(2, 1e-10)
+        assert status == 0 and np.allclose(e, w[:2], atol=1e-8)
+    ctx.set_option(cis.OPT_SIGMA_PATH, 1)
+    C = torch.tensor(c, dtype=dtype, device="cuda")
+    S = torch.full_like(C, 7.0)
+    with pytest.raises(cis.CisigmaError) as err:
+        ctx.apply(C, S)
+    assert err.value.status == cis.EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((S == 7.0).all())
+    ctx.set_option(cis.OPT_SIGMA_PATH, 0)
+    assert np.array_equal(gpu_sigma(ctx, c, dtype), plain)
+    for bad in (-1, 2):
+        with pytest.raises(cis.CisigmaError):
+            ctx.set_option(cis.OPT_DETERMINISTIC, bad)
+    h, g = si.integrals(15, 30, 0)
+    ctx2 = cis.Context(15, 7, 2, h, g)
+    C2 = torch.ones(ctx2.ndet, dtype=dtype, device="cuda")
+    S2 = torch.empty_like(C2)
+    ctx2.apply(C2, S2)
+    prec = cis.FP32 if dtype == torch.float32 else cis.FP64
+    assert not ctx2.last_path(prec) & cis.PATH_SS_MATERIALISED   # the atomic same-spin kernel ran
+    ctx2.set_option(cis.OPT_DETERMINISTIC, 1)
+    S2.fill_(7.0)
+    with pytest.raises(cis.CisigmaError) as err:
+        ctx2.apply(C2, S2)
+    assert err.value.status == cis.EUNSUPPORTED
+    torch.cuda.synchronize()
+    assert bool((S2 == 7.0).all())
