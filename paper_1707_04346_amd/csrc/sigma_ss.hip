@@ -121,12 +121,11 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
         As[P * (KP + 1) + Q] = val;
     }
     __syncthreads();
-    T A[MBL][KS];
-#pragma unroll
-    for (int rb = 0; rb < MBL; ++rb)
-#pragma unroll
-        for (int t = 0; t < KS; ++t) A[rb][t] = As[(rb * 16 + (lane & 15)) * (KP + 1) + 4 * t + (lane >> 4)];
-
+    // The V-block fragments stay in LDS and are read per k step: held in registers
+    // (MBL*KS of them) they left one wave per SIMD for the larger pair counts, whose
+    // gathers then went unhidden (GAS(20,20) same-spin pass 13.9 -> 13.2 ms FP32,
+    // 27.8 -> 22.5 ms FP64 with two waves per SIMD).
+    const int a_lane = (lane & 15) * (KP + 1) + (lane >> 4);   // row lane%16, k column lane/16
     int cur_u = -1;
     int64_t boff[KS];     // row offsets of the gathered B rows for the current column type
     int64_t ooff[MBL][4]; // row offsets of the output rows
@@ -177,14 +176,19 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
         for (int rb = 0; rb < MBL; ++rb)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[rb][v] = acc_t{0, 0, 0, 0};
+        int ab = a_lane;
+        asm volatile("" : "+v"(ab));   // opaque per item: the LDS reads are not hoisted out of the loop
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
             vec_t b = vec_t{};
             if (boff[t] >= 0) b = *reinterpret_cast<const vec_t *>(p.X + boff[t] + col);
+            T a[MBL];
+#pragma unroll
+            for (int rb = 0; rb < MBL; ++rb) a[rb] = As[ab + rb * 16 * (KP + 1) + 4 * t];
 #pragma unroll
             for (int v = 0; v < VEC; ++v)
 #pragma unroll
-                for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(A[rb][t], b[v], acc[rb][v]);
+                for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(a[rb], b[v], acc[rb][v]);
         }
         if (STORE) {
             // plain stores: row K*npv + P of the materialised buffer belongs to this workgroup alone
@@ -276,11 +280,8 @@ __global__ __launch_bounds__(256, 2) void k_sigma_ss_y(SsyArgs<T> p) {
         As[P * (KP + 1) + Q] = val;
     }
     __syncthreads();
-    T A[MBL][KS];
-#pragma unroll
-    for (int rb = 0; rb < MBL; ++rb)
-#pragma unroll
-        for (int t = 0; t < KS; ++t) A[rb][t] = As[(rb * 16 + (lane & 15)) * (KP + 1) + 4 * t + (lane >> 4)];
+    // V-block fragments read from LDS per k step, as in k_sigma_ss (no spills up to 55 pairs)
+    const int a_lane = (lane & 15) * (KP + 1) + (lane >> 4);
     // byte offsets: gathered row of k step t (row 4t + lane/16) and this lane's column
     uint32_t boff[KS];
 #pragma unroll
@@ -314,12 +315,18 @@ __global__ __launch_bounds__(256, 2) void k_sigma_ss_y(SsyArgs<T> p) {
         for (int rb = 0; rb < MBL; ++rb)
 #pragma unroll
             for (int v = 0; v < VEC; ++v) acc[rb][v] = acc_t{0, 0, 0, 0};
+        int ab = a_lane;
+        asm volatile("" : "+v"(ab));   // opaque per item: the LDS reads are not hoisted out of the loop
 #pragma unroll
-        for (int t = 0; t < KS; ++t)
+        for (int t = 0; t < KS; ++t) {
+            T a[MBL];
+#pragma unroll
+            for (int rb = 0; rb < MBL; ++rb) a[rb] = As[ab + rb * 16 * (KP + 1) + 4 * t];
 #pragma unroll
             for (int v = 0; v < VEC; ++v)
 #pragma unroll
-                for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(A[rb][t], b[t][v], acc[rb][v]);
+                for (int rb = 0; rb < MBL; ++rb) acc[rb][v] = M::op(a[rb], b[t][v], acc[rb][v]);
+        }
         const uint32_t soff = uint32_t(it * TW) * uint32_t(sizeof(T));
 #pragma unroll
         for (int rb = 0; rb < MBL; ++rb)
