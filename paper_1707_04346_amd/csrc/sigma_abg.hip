@@ -112,7 +112,16 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
     constexpr int NT = 64 * NW;                             // threads
-    constexpr int NG = NW / 2;                              // row-block groups (x two column halves)
+    // FP64 shapes whose half of the A fragments alone would take more than 320
+    // registers per lane: every wave multiplies both 16-column halves for a quarter
+    // of the row blocks (strided over the waves), so it holds a quarter of the
+    // fragments (GAS(20,20), 26 k steps x 14 row blocks: 234 registers spilled
+    // before; sigma_3 93.7 -> 82.9 ms).  Smaller shapes keep two row groups x two
+    // column halves: the strided split leaves their row blocks uneven (CAS(16,16)
+    // D2h, 9 row blocks: 84.1 -> 92.6 ms with it).
+    constexpr bool FC = sizeof(T) == 8 && (RB + 1) / 2 * KS * 2 > 320;
+    constexpr int NH = FC ? 2 : 1;                          // column halves per wave
+    constexpr int NG = FC ? NW : NW / 2;                    // row-block groups (x 2 / NH column halves)
     // eight waves: gathers as 32-bit byte offsets through a buffer resource (C
     // below 4 GB), one address register per load instead of two
     constexpr bool BUF = NW == 8;
@@ -136,8 +145,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     const int ta = p.atype[Ia], ra = Ia - p.astart[ta];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform: the scatter role branches per wave
-    const int cb = wave & 1, grp = wave >> 1;
-    const int rb0 = grp * RBW, nrb = RB - rb0 < RBW ? RB - rb0 : RBW;   // nrb may be <= 0
+    const int cb = FC ? 0 : wave & 1, grp = FC ? wave : wave >> 1;
+    const int rb0 = FC ? grp : grp * RBW;
+    const int nrb = FC ? (RB - grp + NG - 1) / NG : RB - rb0 < RBW ? RB - rb0 : RBW;   // nrb may be <= 0
+    // row block of the wave's r-th fragment row: a contiguous run, or every NG-th (FC)
+    auto rbi = [&](int r) { return FC ? rb0 + NG * r : rb0 + r; };
     const bool scat = wave < 4;                            // the tile plan's four wave ranges
     const int64_t *segrow = p.seg + int64_t(ta) * p.ntb;
     const int *coff = p.coff + int64_t(ta) * p.ntb;
@@ -169,7 +181,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         }
         rowoff[idx] = off;
     }
-    // A fragments: row m (grouped pair order) = 16*(rb0 + r) + lane%16, gathered row 4t + lane/16
+    // A fragments: row m (grouped pair order) = 16*rbi(r) + lane%16, gathered row 4t + lane/16
     T A[RBW][KS];
     const uint32_t xa = p.astr[Ia];
 #pragma unroll
@@ -187,7 +199,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         }
 #pragma unroll
         for (int r = 0; r < RBW; ++r) {
-            const int m = (rb0 + r) * 16 + (lane & 15);
+            const int m = rbi(r) * 16 + (lane & 15);
             T val = 0;
             if (r < nrb && m < p.mp) {
                 if (g) {
@@ -213,26 +225,27 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         const uint32_t pl = uint32_t(wave * PW + lane) * 4u;
         const uint32_t spare = uint32_t(ncol + lane) * uint32_t(sizeof(T));
         const uint4 *act = p.act + uni(U[3]);
-        T bc[KS];
-        acc_t acc[RBW];
+        T bc[NH][KS];
+        acc_t acc[NH][RBW];
         // gathered rows of an item for every k step: one LDS offset read each
         // (only the k steps the item multiplies: the others read the zero row anyway);
         // four waves: 32-bit element offsets on a 64-bit base, so C may exceed 4 GB
-        auto load = [&](const uint4 &e, T (&b)[KS]) {
+        auto load = [&](const uint4 &e, T (&b)[NH][KS]) {
             const uint32_t *ro = rowoff + (e.w & 255u) * KP + (lane >> 4);
             if constexpr (BUF) {
                 const uint32_t c0 = (e.w >> 8) + colo;
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
-                    if ((e.y >> t) & 1u) buffer_ld(b[t], crs, (ro[4 * t] + c0) * uint32_t(sizeof(T)), 0u);
-                    else b[t] = T(0);
+                    if ((e.y >> t) & 1u) buffer_ld(b[0][t], crs, (ro[4 * t] + c0) * uint32_t(sizeof(T)), 0u);
+                    else b[0][t] = T(0);
                 }
             } else {
                 const T *src = cl + (e.w >> 8);
 #pragma unroll
                 for (int t = 0; t < KS; ++t) {
-                    if ((e.y >> t) & 1u) b[t] = src[ro[4 * t]];
-                    else b[t] = T(0);
+                    const bool on = (e.y >> t) & 1u;
+#pragma unroll
+                    for (int h = 0; h < NH; ++h) b[h][t] = on ? src[ro[4 * t] + 16 * h] : T(0);
                 }
             }
         };
@@ -250,13 +263,15 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         auto products = [&](uint32_t km, uint32_t rm) {
 #pragma unroll
             for (int r = 0; r < RBW; ++r) {
-                acc[r] = acc_t{0, 0, 0, 0};
-                if (r >= nrb || !((rm >> (rb0 + r)) & 1u)) continue;
+#pragma unroll
+                for (int h = 0; h < NH; ++h) acc[h][r] = acc_t{0, 0, 0, 0};
+                if (r >= nrb || !((rm >> rbi(r)) & 1u)) continue;
                 if (PER_STEP) {
 #pragma unroll
                     for (int t = 0; t < KS; ++t) {
                         if (!((km >> t) & 1u)) continue;
-                        acc[r] = M::op(A[r][t], bc[t], acc[r]);
+#pragma unroll
+                        for (int h = 0; h < NH; ++h) acc[h][r] = M::op(A[r][t], bc[h][t], acc[h][r]);
                     }
                 } else {
 #pragma unroll
@@ -266,7 +281,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
 #pragma unroll
                         for (int t = 0; t < KS; ++t) {
                             if (!((cm >> t) & 1u)) continue;
-                            acc[r] = M::op(A[r][t], bc[t], acc[r]);
+#pragma unroll
+                            for (int h = 0; h < NH; ++h) acc[h][r] = M::op(A[r][t], bc[h][t], acc[h][r]);
                         }
                     }
                 }
@@ -275,10 +291,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         auto store_w = [&](uint32_t rm) {
 #pragma unroll
             for (int r = 0; r < RBW; ++r)
-                if (r < nrb && ((rm >> (rb0 + r)) & 1u))
+                if (r < nrb && ((rm >> rbi(r)) & 1u))
 #pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        W[((rb0 + r) * 16 + M::out_row(lane, i)) * kAbxWS + cb * 16 + (lane & 15)] = acc[r][i];
+                    for (int h = 0; h < NH; ++h)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            W[(rbi(r) * 16 + M::out_row(lane, i)) * kAbxWS + (cb + h) * 16 + (lane & 15)] =
+                                acc[h][r][i];
         };
         // items i + 1 and i + 2 are read one iteration ahead of their use; the
         // gathered rows of an item in one buffer, loaded in the iteration that
