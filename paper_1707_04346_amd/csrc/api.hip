@@ -704,8 +704,9 @@ int build_gas_owner(cisigma_ctx *c, bool one_block) {
     for (int o = 0; o < n; ++o) ++gsize[space[o]];
     // gathered-row slots of each alpha type.  With spatial symmetry the source type
     // of an excitation depends on its orbitals' irreps, not on the type alone: the
-    // slots then follow the excitation list (source "any", -3), every k step is
-    // multiplied, and the tiles and row blocks come from the plans alone.
+    // slots then follow the excitation list (source "any", -3), the k-step masks
+    // here take every step (the kernel narrows them per beta type from the row
+    // offsets of its string), and the tiles and row blocks come from the plans.
     std::vector<int> slot(size_t(A.ntype) * kp, -1), slot_src(size_t(A.ntype) * kp, -1);
     for (int ta = 0; ta < A.ntype && c->sym; ++ta) {
         for (int q = 0; q < A.nexc; ++q) {
@@ -827,7 +828,8 @@ int build_gas_owner(cisigma_ctx *c, bool one_block) {
         const size_t es = d == 0 ? 8 : 4;
         // the kernel addresses C with 32-bit element offsets (its zero row included)
         if (uint64_t(c->pl[0].size) + uint64_t(ldmax) >= (uint64_t(1) << 32)) continue;
-        const size_t fixed = (size_t(16) * rb * WS + 64) * es + size_t(4) * kp * ntb;
+        // (point-group spaces: one more word per beta type, the kernel's per-type k-step masks)
+        const size_t fixed = (size_t(16) * rb * WS + 64) * es + size_t(4) * (kp + (c->sym ? 1 : 0)) * ntb;
         if (fixed >= 160 * 1024) continue;
         int cmax = int(std::min<size_t>((160 * 1024 - fixed) / es, 65536 - 64 - 1));
         if (c->unit_cols > 0) cmax = std::min(cmax, c->unit_cols);

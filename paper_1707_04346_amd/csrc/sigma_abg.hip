@@ -62,6 +62,7 @@ struct AbgArgs {
     int block_base;                  // workgroup index of blockIdx 0 (one launch per unit: its first)
     int anexc, n, mp, ntb, nunits;   // mp: W rows (pair rows with gaps; unused rows have zero integrals)
     int nvirt;                   // the longest unit row (LDS layout)
+    int rtk;                     // 1 (point-group spaces): LDS for the per-beta-type k-step masks
 };
 
 // abx_scatter_n over the entries in chunks of CH: the W values and old sigma
@@ -107,7 +108,7 @@ __device__ __forceinline__ void abg_scatter_ch(const T *W, T *sig, const uint32_
     *d = *d + carry;
 }
 
-template <typename T, int KS, int RB, int EW, int NW>
+template <typename T, int KS, int RB, int EW, int NW, bool RTK>
 __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
@@ -180,6 +181,21 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
             if (s >= 0) off = uint32_t(s + int64_t(Ja - p.astart[t2]) * p.ld[u]);
         }
         rowoff[idx] = off;
+    }
+    // RTK (point-group spaces): the host's k-step masks are per alpha type and
+    // take every step, but a tile of beta type u only meets the slots whose
+    // source row lies in a block allowed with u (the others gather the zero
+    // row); the steps holding one, per u, narrow each item's mask (CAS(16,16)
+    // D2h sigma_3: FP64 83.9 -> 64.5 ms, FP32 40.0 -> 37.7 ms, the same sigma)
+    uint32_t *ukm = rowoff + p.ntb * KP;                  // [ntb]
+    if constexpr (RTK) {
+        __syncthreads();                                  // rowoff complete
+        for (int u = tid; u < p.ntb; u += NT) {
+            uint32_t m = 0;
+            for (int q = 0; q < KP; ++q)
+                if (rowoff[u * KP + q] != p.zero_off) m |= 1u << (q >> 2);
+            ukm[u] = m;
+        }
     }
     // A fragments: row m (grouped pair order) = 16*rbi(r) + lane%16, gathered row 4t + lane/16
     T A[RBW][KS];
@@ -254,8 +270,10 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         // without it).  FP64: only the item's active k steps (a uniform branch each);
         // FP32: the k steps in four chunks, a chunk multiplied when one of its k
         // steps is active (measured at GAS(20,20): FP64 148 ms per-step vs 159 ms
-        // chunked, FP32 79 ms chunked vs 88 ms per-step)
-        constexpr bool PER_STEP = sizeof(T) == 8;
+        // chunked, FP32 79 ms chunked vs 88 ms per-step); with the per-beta-type
+        // masks (RTK) FP32 goes per step too: most chunks then hold an active step
+        // among idle ones (CAS(16,16) D2h sigma_3 37.1 -> 25.6 ms)
+        constexpr bool PER_STEP = sizeof(T) == 8 || RTK;
         constexpr uint32_t CM0 = PER_STEP ? 1u : (1u << (KS / 4)) - 1u;
         constexpr uint32_t CM1 = ((1u << (KS / 2)) - 1u) & ~CM0;
         constexpr uint32_t CM2 = ((1u << (3 * KS / 4)) - 1u) & ~(CM0 | CM1);
@@ -303,9 +321,14 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         // gathered rows of an item in one buffer, loaded in the iteration that
         // multiplies them (a second buffer, one item ahead, cost the registers of the
         // eight-wave form: 64.0 -> 57.5 ms without it)
-        uint4 e1 = uni_ld(act + (nact > 1 ? 1 : 0)), e2 = uni_ld(act + (nact > 2 ? 2 : nact - 1));
+        auto item = [&](int i) {                          // tile entry i, its k-step mask narrowed
+            uint4 e = uni_ld(act + i);
+            if constexpr (RTK) e.y &= uint32_t(__builtin_amdgcn_readfirstlane(int(ukm[e.w & 255u])));
+            return e;
+        };
+        uint4 e1 = item(nact > 1 ? 1 : 0), e2 = item(nact > 2 ? 2 : nact - 1);
         {
-            const uint4 e0 = uni_ld(act);
+            const uint4 e0 = item(0);
             load(e0, bc);
             products(e0.y, e0.z);
             store_w(e0.z);
@@ -320,7 +343,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_sigma_ab_g(AbgArgs<T> p) {
         __syncthreads();
         for (int i = 0; i < nact; ++i) {
             const bool more = i + 1 < nact;
-            const uint4 e3 = uni_ld(act + (i + 3 < nact ? i + 3 : nact - 1));
+            const uint4 e3 = item(i + 3 < nact ? i + 3 : nact - 1);
             if (more) load(e1, bc);                              // rows of item i + 1
             pn = int(xc >> 24);
             if (scat) abx_plan_load_n<EW>(pr, pl, (xc & 0xffffffu) * (PT * 4u), pw_, ph, pn);
@@ -529,30 +552,39 @@ __global__ __launch_bounds__(512, 1) void k_sigma_ab_gw(AbgArgs<T> p) {
 }
 
 template <typename T>
-size_t abg_lds(int nvirt, int rb, int ks, int ntb) {
-    return (size_t(16) * rb * kAbxWS + nvirt + 64) * sizeof(T) + size_t(4) * ks * ntb * sizeof(uint32_t);
+size_t abg_lds(int nvirt, int rb, int ks, int ntb, int rtk) {
+    return (size_t(16) * rb * kAbxWS + nvirt + 64) * sizeof(T) + (size_t(4) * ks + rtk) * ntb * sizeof(uint32_t);
 }
 
 // Waves per workgroup of the GAS kernel: FP32 with C below 4 GB eight (two per
 // SIMD, each with a quarter of the W row blocks; waves 0-3 also scatter: at
 // GAS(20,20) sigma_3 72.3 -> 64.0 ms), else four (FP64: its A fragments would
 // not fit two waves per SIMD)
-template <typename T, int KS, int RB, int EW, int NW>
+template <typename T, int KS, int RB, int EW, int NW, bool RTK>
 hipError_t run_abg_nw(const AbgArgs<T> &a, int na, hipStream_t s) {
-    const size_t lds = abg_lds<T>(a.nvirt, RB, KS, a.ntb);
+    const size_t lds = abg_lds<T>(a.nvirt, RB, KS, a.ntb, a.rtk);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_g<T, KS, RB, EW, NW>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_sigma_ab_g<T, KS, RB, EW, NW, RTK>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_sigma_ab_g<T, KS, RB, EW, NW>), dim3(na), dim3(64 * NW), lds, s, a);
+    hipLaunchKernelGGL((k_sigma_ab_g<T, KS, RB, EW, NW, RTK>), dim3(na), dim3(64 * NW), lds, s, a);
     return hipGetLastError();
 }
 
+template <typename T, int KS, int RB, int EW, bool RTK>
+hipError_t run_abg_rtk(const AbgArgs<T> &a, int na, hipStream_t s) {
+    if constexpr (sizeof(T) == 4)
+        if (a.cp_bytes != 0) return run_abg_nw<T, KS, RB, EW, 8, RTK>(a, na, s);
+    return run_abg_nw<T, KS, RB, EW, 4, RTK>(a, na, s);
+}
+
+// the per-beta-type k-step masks are compiled for the shapes of point-group
+// spaces up to CAS(16,16) (17 k steps x 9 row blocks); larger shapes run without
 template <typename T, int KS, int RB, int EW>
 hipError_t run_abg(const AbgArgs<T> &a, int na, hipStream_t s) {
-    if constexpr (sizeof(T) == 4)
-        if (a.cp_bytes != 0) return run_abg_nw<T, KS, RB, EW, 8>(a, na, s);
-    return run_abg_nw<T, KS, RB, EW, 4>(a, na, s);
+    if constexpr (KS * RB <= 17 * 9)
+        if (a.rtk) return run_abg_rtk<T, KS, RB, EW, true>(a, na, s);
+    return run_abg_rtk<T, KS, RB, EW, false>(a, na, s);
 }
 
 template <typename T, int KS, int RB, int EW>
@@ -630,6 +662,7 @@ bool gas_t(const cisigma_ctx *ctx, const void *cp, void *sp, hipStream_t s, hipE
     a.units = G.d_units[d];
     a.nunits = int(G.units[d].size());
     a.nvirt = G.maxcols[d];
+    a.rtk = ctx->sym ? 1 : 0;
     int *kshape = const_cast<cisigma_ctx *>(ctx)->last_shape[sizeof(T) == 4];
     // one launch over every unit, or (CISIGMA_OPT_UNIT_LAUNCH) one launch per unit
     a.block_base = 0;
