@@ -63,10 +63,13 @@ __device__ __forceinline__ int xcd_contig(int b, int n) {
 }
 
 // MODE 0: accumulate into Y with atomics; 1: store column chunks of rows
-// K*npv+P; 2: store each product row into the row of its pair entry; 3: as 2,
+// K*npv+P; 2: store each product row into the row of its pair entry,
 // multiplying per item only the k steps and row blocks that hold a gathered
-// row or a stored row of the item's column type (point-group spaces: V is
-// block-diagonal by pair irrep, so one column type meets about one pair irrep)
+// row or a stored row of the item's column type (GAS: many pairs of a K lead to
+// strings not allowed with a given column type; point-group spaces: V is
+// block-diagonal by pair irrep, so one column type meets about one pair irrep.
+// GAS(20,20) same-spin pass 13.2 -> 7.4 ms FP32, 22.3 -> 12.2 ms FP64; CAS(16,16)
+// D2h 5.4 -> 3.5 ms FP32; the same sigma bit for bit)
 template <typename T, int KS, int MBL, int MODE>
 __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     constexpr bool STORE = MODE == 1;
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
     int cur_u = -1;
     int64_t boff[KS];     // row offsets of the gathered B rows for the current column type
     int64_t ooff[MBL][4]; // row offsets of the output rows
-    uint64_t km = ~0ull;  // MODE 3: k steps and row blocks the current column type uses
+    uint64_t km = ~0ull;  // MODE 2: k steps and row blocks the current column type uses
     uint32_t rbm = ~0u;
     const int item_end = STORE ? p.tile_end * HALVES : p.ntiles * HALVES;
     for (int item = (STORE ? p.tile_begin * HALVES : 0) + wave + 4 * blockIdx.y; item < item_end;
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
                     int64_t o = -1;
                     if (J >= 0) {
                         int tj = p.stype[J];
-                        if (MODE >= 2) {
+                        if (MODE == 2) {
                             const int yc = p.ycol[int64_t(tj) * p.nto + u];
                             const int64_t yo = p.yoff[int64_t(K) * p.npv + P];
                             if (yc >= 0 && yo >= 0) o = yo + yc;
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
                     }
                     ooff[rb][i] = o;
                 }
-            if constexpr (MODE == 3) {
+            if constexpr (MODE == 2) {
                 km = 0;
 #pragma unroll
                 for (int t = 0; t < KS; ++t)
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
         asm volatile("" : "+v"(ab));   // opaque per item: the LDS reads are not hoisted out of the loop
 #pragma unroll
         for (int t = 0; t < KS; ++t) {
-            if (MODE == 3 && !((km >> t) & 1ull)) continue;
+            if (MODE == 2 && !((km >> t) & 1ull)) continue;
             vec_t b = vec_t{};
             if (boff[t] >= 0) b = *reinterpret_cast<const vec_t *>(p.X + boff[t] + col);
             T a[MBL];
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
             for (int v = 0; v < VEC; ++v)
 #pragma unroll
                 for (int rb = 0; rb < MBL; ++rb)
-                    if (MODE != 3 || ((rbm >> rb) & 1u)) acc[rb][v] = M::op(a[rb], b[v], acc[rb][v]);
+                    if (MODE != 2 || ((rbm >> rb) & 1u)) acc[rb][v] = M::op(a[rb], b[v], acc[rb][v]);
         }
         if (STORE) {
             // plain stores: row K*npv + P of the materialised buffer belongs to this workgroup alone
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(256) void k_sigma_ss(SsArgs<T> p) {
                     for (int v = 0; v < VEC; ++v) o[v] = acc[rb][v][i];
                     *reinterpret_cast<vec_t *>(p.Ys + (int64_t(K) * p.npv + P) * p.ldy + (col - p.col_begin)) = o;
                 }
-        } else if (MODE >= 2) {
+        } else if (MODE == 2) {
             // plain stores: each (pair entry, column) element has one producer
 #pragma unroll
             for (int rb = 0; rb < MBL; ++rb)
@@ -647,9 +650,7 @@ hipError_t same_spin_t(const cisigma_ctx *ctx, int spin, const void *X, void *Y,
         a.Ys = static_cast<T *>(Ys);
         a.yoff = S.d_yoff;
         a.ycol = S.d_ycol;
-        // point-group spaces: the masked form (MODE 3)
-        hipError_t e = ctx->sym ? (bucketed ? buckets(std::integral_constant<int, 3>{}) : dispatch_ss<T, 3>(a, s))
-                                : (bucketed ? buckets(std::integral_constant<int, 2>{}) : dispatch_ss<T, 2>(a, s));
+        hipError_t e = bucketed ? buckets(std::integral_constant<int, 2>{}) : dispatch_ss<T, 2>(a, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_pair_gather_rows<T>), dim3(S.nstr), dim3(256), 0, s, static_cast<const T *>(Ys),
                            S.d_yoff, S.d_ycol, S.d_pair_inv, per, S.d_stype, ctx->d_tstart[spin], L.d_seg, L.d_ld,
